@@ -1,0 +1,171 @@
+/*
+ * bfscut.h -- C ABI of the MI355X (gfx950) top-k closeness engine.
+ *
+ * The engine returns the k nodes of largest generalised closeness
+ *     c(v) = (r(v) - 1)^2 / ((n - 1) f(v))          (Section 1)
+ * where r(v) = |R(v)| counts the nodes reachable from v (v included) and
+ * f(v) = sum of d(v, w) over w in R(v) (Table 1), computed with the pruned
+ * BFS of Borassi, Crescenzi and Marino (Algorithm 1 and the BFSCut function
+ * of Section 2.5, bounds of Lemma 1 / Corollary 1 / Lemma 2, reach bounds of
+ * Section 2.3-2.4).  All ranking decisions are exact integer arithmetic:
+ *
+ *   A(v) = (r(v)-1)^2, F(v) = f(v)     ((A, F) = (0, 1) when r(v) = 1, c = 0)
+ *   key(v) > key(w)  iff  A(v) F(w) > A(w) F(v) (unsigned 128-bit), or the
+ *                         products are equal and v < w.
+ *
+ * Results are sorted by decreasing key.  Closeness itself is not returned; a
+ * caller computes it for display as (r-1)^2 / ((n-1) f), and 0 when r = 1.
+ *
+ * Conventions:
+ *  - every function returns bc_status and never throws; on failure
+ *    bc_last_error() returns a message (thread-local, valid until the next
+ *    call on the same thread);
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory of the current device;
+ *  - all calls are blocking unless stated otherwise and take an optional
+ *    hipStream_t (passed as void*; NULL = the legacy default stream).
+ */
+#ifndef BFSCUT_H
+#define BFSCUT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BC_OK = 0,
+    BC_EINVAL = -1,     /* bad argument (NULL pointer, k <= 0, bad option)      */
+    BC_EGRAPH = -2,     /* malformed CSR (see bc_graph_create)                  */
+    BC_ENOMEM = -3,     /* device or host allocation failed / over budget       */
+    BC_EDEVICE = -4,    /* HIP runtime error                                    */
+    BC_EAGAIN = -5,     /* asynchronous query not finished yet                  */
+    BC_ECANCELED = -6   /* asynchronous query was cancelled                     */
+} bc_status;
+
+typedef struct bc_graph bc_graph;
+
+/* bc_graph_create flags */
+#define BC_DIRECTED    0x1u  /* arcs are directed (else every edge must appear in both rows) */
+#define BC_VALIDATE    0x2u  /* undirected only: reject a CSR that is not symmetric           */
+#define BC_DEVICE_PTRS 0x4u  /* row_ptr / col are device pointers (read, never kept)          */
+
+/* Source processing order (Algorithm 1 processes nodes in decreasing degree). */
+#define BC_ORDER_DEGREE 0    /* decreasing out-degree, ties by increasing id (the paper's order) */
+#define BC_ORDER_GIVEN  1    /* opts.perm: a permutation of [0, n) (host pointer)                */
+#define BC_ORDER_SCORES 2    /* opts.scores: decreasing score, ties by out-degree then id        */
+
+/* Execution mode.  Neither changes the result, only the speed. */
+#define BC_MODE_PLAIN   0    /* one batch of W sources at a time, level-synchronous
+                                kernels launched by a host loop                       */
+#define BC_MODE_BATCHED 1    /* seed batches level-synchronously, then one persistent
+                                launch in which every workgroup runs whole batches    */
+
+typedef struct bc_opts {
+    uint32_t size;          /* sizeof(bc_opts): versioning                               */
+    int32_t mode;           /* BC_MODE_*                                                 */
+    int32_t order;          /* BC_ORDER_*                                                */
+    int32_t width;          /* W: sources per bit-parallel batch, 64, 128 or 256         */
+    const int32_t* perm;    /* BC_ORDER_GIVEN: host, n entries                           */
+    const float* scores;    /* BC_ORDER_SCORES: host, n entries                          */
+    float pull_alpha;       /* push -> pull when frontier arcs > m / pull_alpha (0 = never pull) */
+    float pull_beta;        /* pull -> push when frontier nodes < n / pull_beta          */
+    int32_t slots;          /* BC_MODE_BATCHED: concurrent workgroup batches (0 = auto)  */
+    int32_t seed_batches;   /* BC_MODE_BATCHED: level-synchronous batches first (-1 = auto) */
+    int32_t block;          /* threads per workgroup in the level kernels (0 = auto)     */
+    int32_t reserved;
+} bc_opts;
+
+typedef struct bc_stats {
+    uint32_t size;          /* sizeof(bc_stats)                                          */
+    uint32_t batches;       /* source batches processed                                  */
+    uint64_t m_vis;         /* arcs a sequential BFSCut of each source would scan,
+                               summed over sources (the paper's visited arcs)            */
+    uint64_t node_arcs;     /* arcs the level kernels scanned (each frontier node once
+                               per level, shared by all its live sources)                */
+    uint64_t levels;        /* level steps executed                                      */
+    uint64_t pull_levels;   /* of which bottom-up                                        */
+    uint64_t n_cut, n_done, n_trivial;  /* per-source outcomes                            */
+    double preprocess_ms;   /* bc_graph_create time (canonical CSR and reach data)       */
+    double query_ms;        /* bc_topk time, call to return                              */
+} bc_stats;
+
+/* Fill *opts with the defaults (plain mode, degree order, W = 64). */
+void bc_opts_default(bc_opts* opts);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* bc_last_error(void);
+
+/* Library version string. */
+const char* bc_version(void);
+
+/*
+ * bc_graph_create -- upload a CSR graph and run the pre-processing step.
+ *
+ *   n        node count, 0 <= n < 2^31
+ *   row_ptr  n + 1 int32 offsets, row_ptr[0] = 0, non-decreasing, row_ptr[n] = m
+ *   col      m int32 targets in [0, n)
+ *   flags    BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS
+ *   stream   hipStream_t used by this graph's work (NULL = default stream)
+ *   out      receives the handle; release it with bc_graph_destroy
+ *
+ * The arrays are copied: the caller may free or reuse them on return (host
+ * or device).  Rows may be unsorted and may hold self-loops and repeated
+ * arcs; these are removed on the device (they change no distance).  The
+ * pre-processing follows Section 2.3 (undirected: r(v) = size of the
+ * connected component) and Section 2.4 (directed: alpha(v) <= r(v) <=
+ * omega(v) from the weighted DAG of strongly connected components).
+ *
+ * Errors: BC_EINVAL (n < 0, NULL pointer), BC_EGRAPH (row_ptr[0] != 0,
+ * decreasing row_ptr, row_ptr[n] != m, col outside [0, n), or with
+ * BC_VALIDATE an undirected CSR that is not symmetric), BC_ENOMEM, BC_EDEVICE.
+ */
+bc_status bc_graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
+                          uint32_t flags, void* stream, bc_graph** out);
+
+/* Release a graph and all its device memory.  NULL is accepted. */
+bc_status bc_graph_destroy(bc_graph* g);
+
+/*
+ * bc_graph_info -- sizes after canonicalisation (host pointers, any may be NULL).
+ */
+bc_status bc_graph_info(const bc_graph* g, int32_t* n, int64_t* m, int32_t* directed,
+                        double* preprocess_ms);
+
+/*
+ * bc_graph_reach -- copy the per-node reach data (host pointers, n entries each):
+ * undirected: lo = hi = r(v); directed: lo = alpha(v), hi = omega(v).
+ */
+bc_status bc_graph_reach(const bc_graph* g, uint32_t* lo, uint32_t* hi);
+
+/*
+ * bc_graph_csr -- copy the canonical CSR (host pointers: row_ptr n + 1 entries,
+ * col m entries as reported by bc_graph_info).
+ */
+bc_status bc_graph_csr(const bc_graph* g, int32_t* row_ptr, int32_t* col);
+
+/*
+ * bc_topk -- the k nodes of largest closeness (Algorithm 1).
+ *
+ *   k        number of nodes wanted, k >= 1; count = min(k, n) results
+ *   opts     NULL for the defaults (bc_opts_default)
+ *   ids      host, capacity k: node ids, decreasing key
+ *   farness  host, capacity k: exact f(v)
+ *   reach    host, capacity k: exact r(v)
+ *   count    host: number of results written
+ *   stats    host, optional (NULL): counters and timings of this call
+ *
+ * The caller owns every output array.  Blocking.  Several calls may run on
+ * one graph at the same time from different threads (each call allocates its
+ * own working memory).  Errors: BC_EINVAL (k <= 0, NULL outputs, bad opts),
+ * BC_ENOMEM, BC_EDEVICE.
+ */
+bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uint64_t* farness,
+                  uint32_t* reach, int32_t* count, bc_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFSCUT_H */

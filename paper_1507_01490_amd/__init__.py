@@ -1,0 +1,232 @@
+"""Exact top-k closeness centrality on AMD MI355X (gfx950).
+
+Thin ctypes binding over ``libbfscut.so`` (C ABI in ``include/bfscut.h``):
+argument marshalling only, every step runs in the library's HIP kernels.
+PyTorch is used, when given, only for device memory and streams.
+
+Example::
+
+    import paper_1507_01490_amd as bc
+    from paper_1507_01490_amd import synth
+    g = synth.barabasi_albert(100000, 5, seed=1)
+    with bc.Graph(g.row_ptr, g.col, directed=False) as G:
+        res = G.topk(10)
+    res.ids, res.farness, res.reach      # decreasing closeness, ties by id
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = ["Graph", "TopK", "Opts", "Stats", "BcError", "load_library", "closeness",
+           "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES",
+           "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.so")
+
+BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS = 0x1, 0x2, 0x4
+ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES = 0, 1, 2
+MODE_PLAIN, MODE_BATCHED = 0, 1
+_STATUS = {0: "BC_OK", -1: "BC_EINVAL", -2: "BC_EGRAPH", -3: "BC_ENOMEM", -4: "BC_EDEVICE",
+           -5: "BC_EAGAIN", -6: "BC_ECANCELED"}
+
+
+class BcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("perm", ctypes.c_void_p), ("scores", ctypes.c_void_p),
+                ("pull_alpha", ctypes.c_float), ("pull_beta", ctypes.c_float),
+                ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("batches", ctypes.c_uint32), ("m_vis", ctypes.c_uint64),
+                ("node_arcs", ctypes.c_uint64), ("levels", ctypes.c_uint64),
+                ("pull_levels", ctypes.c_uint64), ("n_cut", ctypes.c_uint64),
+                ("n_done", ctypes.c_uint64), ("n_trivial", ctypes.c_uint64),
+                ("preprocess_ms", ctypes.c_double), ("query_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbfscut.so.  Raises if it has not been built (there is no
+    fallback: the library is the only implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1507_01490_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.bc_last_error.restype = ctypes.c_char_p
+    lib.bc_version.restype = ctypes.c_char_p
+    lib.bc_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    lib.bc_graph_create.argtypes = [i32, i64, P, P, u32, P, ctypes.POINTER(P)]
+    lib.bc_graph_destroy.argtypes = [P]
+    lib.bc_graph_info.argtypes = [P, P, P, P, P]
+    lib.bc_graph_reach.argtypes = [P, P, P]
+    lib.bc_graph_csr.argtypes = [P, P, P]
+    lib.bc_topk.argtypes = [P, i32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(Stats)]
+    for name in ("bc_graph_create", "bc_graph_destroy", "bc_graph_info", "bc_graph_reach",
+                 "bc_graph_csr", "bc_topk"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise BcError(status, load_library().bc_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def closeness(r, f, n: int) -> np.ndarray:
+    """(r-1)^2 / ((n-1) f) for display (0 when r = 1); ranking never uses it."""
+    r = np.asarray(r, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        c = (r - 1.0) ** 2 / (max(n - 1, 1) * f)
+    return np.where(r <= 1, 0.0, c)
+
+
+@dataclass
+class TopK:
+    ids: np.ndarray
+    farness: np.ndarray
+    reach: np.ndarray
+    stats: dict = field(default_factory=dict)
+
+
+class Graph:
+    """A CSR graph resident on the GPU with its pre-processed reach data.
+
+    ``row_ptr``/``col`` are int32 numpy arrays (host) or int32 torch CUDA
+    tensors (device); either way the library copies them."""
+
+    def __init__(self, row_ptr, col, directed: bool = False, validate: bool = False, stream=None):
+        lib = load_library()
+        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0)
+        if _is_torch(row_ptr):
+            if not row_ptr.is_cuda:
+                row_ptr, col = row_ptr.numpy(), col.numpy()
+            else:
+                flags |= BC_DEVICE_PTRS
+        if flags & BC_DEVICE_PTRS:
+            n = int(row_ptr.numel()) - 1
+            m = int(col.numel())
+            rp_p = ctypes.c_void_p(row_ptr.data_ptr())
+            col_p = ctypes.c_void_p(col.data_ptr()) if m else None
+            keep = (row_ptr, col)
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            n = int(rp.shape[0]) - 1
+            m = int(cl.shape[0])
+            rp_p, col_p = _ptr(rp), (_ptr(cl) if m else None)
+            keep = (rp, cl)
+        s = None
+        if stream is not None:
+            s = ctypes.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+        h = ctypes.c_void_p()
+        _check(lib.bc_graph_create(n, m, rp_p, col_p, flags, s, ctypes.byref(h)))
+        del keep
+        self._h = h
+        self.directed = bool(directed)
+        nn, mm, dd, pp = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib.bc_graph_info(h, ctypes.byref(nn), ctypes.byref(mm), ctypes.byref(dd), ctypes.byref(pp)))
+        self.n, self.m, self.preprocess_ms = nn.value, mm.value, pp.value
+
+    # context manager / lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().bc_graph_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reach(self):
+        """(lo, hi) per node: undirected r(v) twice; directed alpha(v), omega(v)."""
+        lo = np.zeros(max(self.n, 1), np.uint32)
+        hi = np.zeros(max(self.n, 1), np.uint32)
+        _check(load_library().bc_graph_reach(self._h, _ptr(lo), _ptr(hi)))
+        return lo[:self.n], hi[:self.n]
+
+    def csr(self):
+        rp = np.zeros(self.n + 1, np.int32)
+        col = np.zeros(max(self.m, 1), np.int32)
+        _check(load_library().bc_graph_csr(self._h, _ptr(rp), _ptr(col)))
+        return rp, col[:self.m]
+
+    def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
+             pull_alpha: float = 0.0, pull_beta: float = 24.0, slots: int = 0,
+             seed_batches: int = -1) -> TopK:
+        """The k nodes of largest closeness: ids, exact farness, exact reach."""
+        lib = load_library()
+        o = Opts()
+        lib.bc_opts_default(ctypes.byref(o))
+        o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}.get(mode, mode) if isinstance(mode, str) else int(mode)
+        if isinstance(mode, str) and mode not in ("plain", "batched"):
+            raise ValueError(f"unknown mode {mode!r}")
+        o.width = int(width)
+        o.pull_alpha = float(pull_alpha)
+        o.pull_beta = float(pull_beta)
+        o.slots = int(slots)
+        o.seed_batches = int(seed_batches)
+        keep = []
+        if order is not None:
+            perm = np.ascontiguousarray(order, dtype=np.int32)
+            if perm.shape[0] != self.n:
+                raise ValueError("order must hold n entries")
+            o.order = ORDER_GIVEN
+            o.perm = perm.ctypes.data
+            keep.append(perm)
+        elif scores is not None:
+            sc = np.ascontiguousarray(scores, dtype=np.float32)
+            if sc.shape[0] != self.n:
+                raise ValueError("scores must hold n entries")
+            o.order = ORDER_SCORES
+            o.scores = sc.ctypes.data
+            keep.append(sc)
+        kk = max(1, int(k))
+        ids = np.zeros(kk, np.int32)
+        far = np.zeros(kk, np.uint64)
+        rea = np.zeros(kk, np.uint32)
+        cnt = ctypes.c_int32()
+        st = Stats()
+        st.size = ctypes.sizeof(Stats)
+        _check(lib.bc_topk(self._h, int(k), ctypes.byref(o), _ptr(ids), _ptr(far), _ptr(rea),
+                           ctypes.byref(cnt), ctypes.byref(st)))
+        c = cnt.value
+        return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())

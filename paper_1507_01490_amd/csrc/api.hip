@@ -1,0 +1,142 @@
+// C ABI of the library (declared in include/bfscut.h).  Every entry point
+// returns a bc_status and never lets a C++ exception cross the boundary.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "bc_internal.h"
+
+namespace bc {
+
+static thread_local char g_err[512];
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+}  // namespace bc
+
+using bc::set_error;
+
+#define BC_GUARD_BEGIN try {
+#define BC_GUARD_END                                   \
+    }                                                  \
+    catch (const std::bad_alloc&) {                    \
+        set_error("host allocation failed");           \
+        return BC_ENOMEM;                              \
+    }                                                  \
+    catch (...) {                                      \
+        set_error("internal error");                   \
+        return BC_EDEVICE;                             \
+    }
+
+extern "C" {
+
+const char* bc_last_error(void) { return bc::g_err; }
+
+const char* bc_version(void) { return "bfscut-gfx950 0.1"; }
+
+void bc_opts_default(bc_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->size = sizeof(bc_opts);
+    o->mode = BC_MODE_PLAIN;
+    o->order = BC_ORDER_DEGREE;
+    o->width = 64;
+    o->perm = nullptr;
+    o->scores = nullptr;
+    o->pull_alpha = 0.f;
+    o->pull_beta = 24.f;
+    o->slots = 0;
+    o->seed_batches = -1;
+    o->block = 0;
+}
+
+bc_status bc_graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
+                          void* stream, bc_graph** out) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!out) { set_error("out is NULL"); return BC_EINVAL; }
+    *out = nullptr;
+    if (n < 0 || m < 0) { set_error("negative size"); return BC_EINVAL; }
+    if (!row_ptr || (m > 0 && !col)) { set_error("row_ptr/col is NULL"); return BC_EINVAL; }
+    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS)) { set_error("unknown flag bits"); return BC_EINVAL; }
+    bc_graph* g = new bc_graph();
+    g->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&g->device);
+    bc_status s = bc::graph_build(g, n, m, row_ptr, col, flags);
+    if (s != BC_OK) {
+        (void)hipStreamSynchronize(g->stream);
+        delete g;
+        return s;
+    }
+    *out = g;
+    return BC_OK;
+    BC_GUARD_END
+}
+
+bc_status bc_graph_destroy(bc_graph* g) {
+    BC_GUARD_BEGIN
+    if (!g) return BC_OK;
+    (void)hipStreamSynchronize(g->stream);
+    delete g;
+    return BC_OK;
+    BC_GUARD_END
+}
+
+bc_status bc_graph_info(const bc_graph* g, int32_t* n, int64_t* m, int32_t* directed, double* preprocess_ms) {
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (n) *n = g->dg.n;
+    if (m) *m = g->dg.m;
+    if (directed) *directed = g->dg.directed;
+    if (preprocess_ms) *preprocess_ms = g->preprocess_ms;
+    return BC_OK;
+}
+
+bc_status bc_graph_reach(const bc_graph* g, uint32_t* lo, uint32_t* hi) {
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    size_t bytes = sizeof(uint32_t) * (size_t)g->dg.n;
+    if (bytes == 0) return BC_OK;
+    if (lo) BC_HIP(hipMemcpyAsync(lo, g->dg.x0, bytes, hipMemcpyDeviceToHost, g->stream));
+    if (hi) BC_HIP(hipMemcpyAsync(hi, g->dg.x1, bytes, hipMemcpyDeviceToHost, g->stream));
+    BC_HIP(hipStreamSynchronize(g->stream));
+    return BC_OK;
+}
+
+bc_status bc_graph_csr(const bc_graph* g, int32_t* row_ptr, int32_t* col) {
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (row_ptr)
+        BC_HIP(hipMemcpyAsync(row_ptr, g->dg.rp, sizeof(int32_t) * ((size_t)g->dg.n + 1), hipMemcpyDeviceToHost,
+                              g->stream));
+    if (col && g->dg.m > 0)
+        BC_HIP(hipMemcpyAsync(col, g->dg.col, sizeof(int32_t) * (size_t)g->dg.m, hipMemcpyDeviceToHost, g->stream));
+    BC_HIP(hipStreamSynchronize(g->stream));
+    return BC_OK;
+}
+
+bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uint64_t* farness, uint32_t* reach,
+                  int32_t* count, bc_stats* stats) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (k <= 0) { set_error("k must be positive (got %d)", k); return BC_EINVAL; }
+    if (!ids || !farness || !reach || !count) { set_error("NULL output array"); return BC_EINVAL; }
+    bc_opts o;
+    bc_opts_default(&o);
+    if (opts) {
+        if (opts->size < sizeof(uint32_t) || opts->size > sizeof(bc_opts)) {
+            set_error("opts.size %u not supported", opts->size);
+            return BC_EINVAL;
+        }
+        std::memcpy(&o, opts, opts->size);
+        o.size = sizeof(bc_opts);
+    }
+    return bc::run_topk(g, k, o, ids, farness, reach, count, stats);
+    BC_GUARD_END
+}
+
+}  // extern "C"

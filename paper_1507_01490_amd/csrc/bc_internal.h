@@ -1,0 +1,110 @@
+// Internal declarations of the gfx950 top-k closeness library.
+//
+// Device-side layout of one graph (all int32 unless noted):
+//   rp[n+1], col[m]        canonical out-CSR (rows sorted, no self-loops or repeats)
+//   irp[n+1], icol[m]      in-CSR (directed graphs; aliases the out-CSR otherwise)
+//   deg[n]   (u32)         out-degree
+//   x0[n], x1[n] (u32)     reach data: undirected x0 = x1 = r(v) (component size);
+//                          directed x0 = alpha(v), x1 = omega(v)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "bfscut.h"
+
+namespace bc {
+
+void set_error(const char* fmt, ...);
+
+#define BC_HIP(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::bc::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                            __FILE__, __LINE__);                                        \
+            return BC_EDEVICE;                                                          \
+        }                                                                               \
+    } while (0)
+
+#define BC_TRY(expr)                      \
+    do {                                  \
+        bc_status s_ = (expr);            \
+        if (s_ != BC_OK) return s_;       \
+    } while (0)
+
+struct DevGraph {
+    int32_t n;
+    int64_t m;
+    int32_t directed;
+    const int32_t* rp;
+    const int32_t* col;
+    const int32_t* irp;
+    const int32_t* icol;
+    const uint32_t* deg;
+    const uint32_t* x0;
+    const uint32_t* x1;
+};
+
+// Device allocation owned by a graph or a query; freed in the destructor.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    bc_status alloc(size_t nbytes) {
+        release();
+        if (nbytes == 0) nbytes = 8;
+        if (hipMalloc(&p, nbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            set_error("hipMalloc of %zu bytes failed", nbytes);
+            return BC_ENOMEM;
+        }
+        bytes = nbytes;
+        return BC_OK;
+    }
+    template <class T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+}  // namespace bc
+
+struct bc_graph {
+    bc::DevGraph dg{};
+    bc::DevBuf rp, col, irp, icol, deg, x0, x1;
+    bc::DevBuf order_deg;  // cached degree order (int32 n), built on first use
+    bool have_order_deg = false;
+    hipStream_t stream = nullptr;
+    double preprocess_ms = 0.0;
+    int device = 0;
+};
+
+namespace bc {
+
+// Pre-processing (preprocess.hip): validation, canonical CSR, degrees,
+// transpose and reach data.  rp/col are host or device pointers per flags.
+bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp, const int32_t* col,
+                      uint32_t flags);
+
+// Source orders (preprocess.hip): decreasing out-degree (ties by id), or a
+// given permutation, or decreasing score (ties by degree, then id).
+bc_status order_by_degree(bc_graph* g, int32_t* d_order);
+bc_status order_by_scores(bc_graph* g, const float* h_scores, int32_t* d_order);
+bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order);
+
+// Top-k drivers (topk.hip).
+bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness,
+                   uint32_t* reach, int32_t* count, bc_stats* st);
+
+}  // namespace bc

@@ -1,0 +1,390 @@
+// Pre-processing step of the method (linear time, done once per graph):
+//   * CSR validation and canonical form (rows sorted, self-loops and repeated
+//     arcs removed; neither changes a distance),
+//   * out-degrees, and the in-CSR of a directed graph,
+//   * reach data: for an undirected graph r(v) is the size of v's connected
+//     component (Section 2.3); for a directed graph alpha(v) <= r(v) <=
+//     omega(v) come from the weighted DAG of strongly connected components
+//     (Section 2.4), see scc.hip.
+//   * source orders for Algorithm 1 (decreasing degree, given, or scored).
+#include <hipcub/hipcub.hpp>
+
+#include <chrono>
+
+#include "bc_internal.h"
+
+namespace bc {
+
+bc_status directed_reach(bc_graph* g);  // scc.hip
+
+namespace {
+
+constexpr int kBlk = 256;
+
+inline unsigned grid_for(int64_t work, int64_t cap = 8192) {
+    int64_t b = (work + kBlk - 1) / kBlk;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+__device__ inline int32_t ld_relaxed(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_relaxed(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// err bits: 1 bad row_ptr, 2 col out of range, 4 not canonical, 8 not symmetric
+__global__ void k_validate(int32_t n, int64_t m, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, uint32_t* err) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n; u += stride) {
+        int32_t b = rp[u];
+        if (u == 0 && b != 0) atomicOr(err, 1u);
+        if (u == n) {
+            if ((int64_t)b != m) atomicOr(err, 1u);
+            continue;
+        }
+        int32_t e = rp[u + 1];
+        if (e < b || b < 0 || (int64_t)e > m) {
+            atomicOr(err, 1u);
+            continue;
+        }
+        uint32_t bits = 0;
+        int32_t prev = -1;
+        for (int32_t i = b; i < e; ++i) {
+            int32_t w = col[i];
+            if (w < 0 || w >= n) { bits |= 2u; break; }
+            if (w == (int32_t)u || w <= prev) bits |= 4u;
+            prev = w;
+        }
+        if (bits) atomicOr(err, bits);
+    }
+}
+
+// keep[i] = 1 for the first copy of each non-loop arc of a sorted row
+__global__ void k_mark_keep(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            int32_t* __restrict__ cnt) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int32_t c = 0, prev = -1;
+        for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+            int32_t w = col[i];
+            if (w != (int32_t)u && w != prev) ++c;
+            prev = w;
+        }
+        cnt[u] = c;
+    }
+}
+
+__global__ void k_compact_rows(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const int32_t* __restrict__ nrp, int32_t* __restrict__ ncol) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int32_t o = nrp[u], prev = -1;
+        for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+            int32_t w = col[i];
+            if (w != (int32_t)u && w != prev) ncol[o++] = w;
+            prev = w;
+        }
+    }
+}
+
+__global__ void k_set_last(int32_t* nrp, int32_t n, const int32_t* cnt) {
+    // nrp holds the exclusive sum of cnt in [0, n); close it with the total
+    if (blockIdx.x == 0 && threadIdx.x == 0) nrp[n] = (n > 0 ? nrp[n - 1] + cnt[n - 1] : 0);
+}
+
+__global__ void k_degree(int32_t n, const int32_t* __restrict__ rp, uint32_t* __restrict__ deg) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        deg[u] = (uint32_t)(rp[u + 1] - rp[u]);
+}
+
+// undirected symmetry: every arc u->w has its reverse w->u (rows are sorted)
+__global__ void k_symmetric(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            uint32_t* err) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+            int32_t w = col[i];
+            int32_t lo = rp[w], hi = rp[w + 1];
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (col[mid] < (int32_t)u) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= rp[w + 1] || col[lo] != (int32_t)u) { atomicOr(err, 8u); break; }
+        }
+    }
+}
+
+// ---- connected components: lock-free union-find (hook larger root under smaller)
+
+__device__ int32_t uf_find(int32_t* P, int32_t v) {
+    for (;;) {
+        int32_t p = ld_relaxed(&P[v]);
+        if (p == v) return v;
+        int32_t gp = ld_relaxed(&P[p]);
+        if (gp != p) st_relaxed(&P[v], gp);  // path halving: gp is an ancestor of v
+        v = gp;
+    }
+}
+
+__global__ void k_uf_init(int32_t n, int32_t* P) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) P[u] = (int32_t)u;
+}
+
+__global__ void k_uf_union(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           int32_t* P) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+            int32_t w = col[i];
+            if (w < (int32_t)u) continue;  // each undirected edge once
+            int32_t a = (int32_t)u, b = w;
+            for (;;) {
+                a = uf_find(P, a);
+                b = uf_find(P, b);
+                if (a == b) break;
+                if (a < b) { int32_t t = a; a = b; b = t; }
+                if (atomicCAS(&P[a], a, b) == a) break;
+            }
+        }
+    }
+}
+
+__global__ void k_uf_count(int32_t n, int32_t* P, uint32_t* __restrict__ size, int32_t* __restrict__ label) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int32_t r = uf_find(P, (int32_t)u);
+        label[u] = r;
+        atomicAdd(&size[r], 1u);
+    }
+}
+
+__global__ void k_uf_reach(int32_t n, const int32_t* __restrict__ label, const uint32_t* __restrict__ size,
+                           uint32_t* __restrict__ x0, uint32_t* __restrict__ x1) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        uint32_t s = size[label[u]];
+        x0[u] = s;
+        x1[u] = s;
+    }
+}
+
+// ---- orders
+
+__global__ void k_degree_keys(int32_t n, const uint32_t* __restrict__ deg, uint64_t* __restrict__ key) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        key[u] = ((uint64_t)(0xFFFFFFFFu - deg[u]) << 32) | (uint32_t)u;
+}
+
+__global__ void k_low32(int32_t n, const uint64_t* __restrict__ key, int32_t* __restrict__ out) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        out[u] = (int32_t)(key[u] & 0xFFFFFFFFu);
+}
+
+// score -> unsigned key whose ascending order is decreasing score
+__global__ void k_score_keys(int32_t n, const float* __restrict__ s, const int32_t* __restrict__ order,
+                             uint32_t* __restrict__ key) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t b = __float_as_uint(s[order[i]]);
+        uint32_t asc = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // monotone in the float
+        key[i] = ~asc;
+    }
+}
+
+__global__ void k_perm_check(int32_t n, const int32_t* __restrict__ perm, uint32_t* __restrict__ seen,
+                             uint32_t* err) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t v = perm[i];
+        if (v < 0 || v >= n) { atomicOr(err, 1u); continue; }
+        if (atomicAdd(&seen[v], 1u) != 0) atomicOr(err, 1u);
+    }
+}
+
+template <class F>
+bc_status cub_call(F&& f, hipStream_t s, DevBuf& tmp) {
+    size_t bytes = 0;
+    BC_HIP(f((void*)nullptr, bytes));
+    if (tmp.bytes < bytes) BC_TRY(tmp.alloc(bytes));
+    BC_HIP(f(tmp.p, bytes));
+    (void)s;
+    return BC_OK;
+}
+
+}  // namespace
+
+bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, const int32_t* col_in,
+                      uint32_t flags) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = g->stream;
+    const bool dev = (flags & BC_DEVICE_PTRS) != 0;
+    const bool directed = (flags & BC_DIRECTED) != 0;
+    if (m >= (int64_t)INT32_MAX) {
+        set_error("m = %lld arcs does not fit int32 offsets", (long long)m);
+        return BC_EGRAPH;
+    }
+    DevBuf rp0, col0, errb, tmp;
+    BC_TRY(rp0.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+    BC_TRY(col0.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+    BC_TRY(errb.alloc(sizeof(uint32_t)));
+    hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    BC_HIP(hipMemcpyAsync(rp0.p, rp_in, sizeof(int32_t) * ((size_t)n + 1), kind, s));
+    if (m > 0) BC_HIP(hipMemcpyAsync(col0.p, col_in, sizeof(int32_t) * (size_t)m, kind, s));
+    BC_HIP(hipMemsetAsync(errb.p, 0, sizeof(uint32_t), s));
+    k_validate<<<grid_for((int64_t)n + 1), kBlk, 0, s>>>(n, m, rp0.as<int32_t>(), col0.as<int32_t>(),
+                                                        errb.as<uint32_t>());
+    uint32_t err = 0;
+    BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (err & 1u) { set_error("malformed row_ptr (row_ptr[0] != 0, decreasing, or row_ptr[n] != m)"); return BC_EGRAPH; }
+    if (err & 2u) { set_error("col entry outside [0, n)"); return BC_EGRAPH; }
+
+    int64_t mc = m;
+    if (err & 4u) {
+        // canonical form: sort every row, then drop self-loops and repeats
+        DevBuf sorted, cnt, nrp;
+        BC_TRY(sorted.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+        BC_TRY(cnt.alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+        BC_TRY(nrp.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+        const int32_t* rpp = rp0.as<int32_t>();
+        BC_TRY(cub_call([&](void* t, size_t& b) {
+            return hipcub::DeviceSegmentedRadixSort::SortKeys(t, b, col0.as<int32_t>(), sorted.as<int32_t>(),
+                                                              (int)m, n, rpp, rpp + 1, 0, 32, s);
+        }, s, tmp));
+        k_mark_keep<<<grid_for(n), kBlk, 0, s>>>(n, rpp, sorted.as<int32_t>(), cnt.as<int32_t>());
+        BC_TRY(cub_call([&](void* t, size_t& b) {
+            return hipcub::DeviceScan::ExclusiveSum(t, b, cnt.as<int32_t>(), nrp.as<int32_t>(), n, s);
+        }, s, tmp));
+        k_set_last<<<1, 1, 0, s>>>(nrp.as<int32_t>(), n, cnt.as<int32_t>());
+        int32_t newm = 0;
+        BC_HIP(hipMemcpyAsync(&newm, nrp.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        mc = newm;
+        BC_TRY(g->rp.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+        BC_TRY(g->col.alloc(sizeof(int32_t) * (size_t)(mc > 0 ? mc : 1)));
+        BC_HIP(hipMemcpyAsync(g->rp.p, nrp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+        k_compact_rows<<<grid_for(n), kBlk, 0, s>>>(n, rpp, sorted.as<int32_t>(), g->rp.as<int32_t>(),
+                                                    g->col.as<int32_t>());
+        BC_HIP(hipStreamSynchronize(s));
+    } else {
+        std::swap(g->rp.p, rp0.p);
+        std::swap(g->rp.bytes, rp0.bytes);
+        std::swap(g->col.p, col0.p);
+        std::swap(g->col.bytes, col0.bytes);
+    }
+
+    g->dg.n = n;
+    g->dg.m = mc;
+    g->dg.directed = directed ? 1 : 0;
+    g->dg.rp = g->rp.as<int32_t>();
+    g->dg.col = g->col.as<int32_t>();
+    BC_TRY(g->deg.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+    k_degree<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->deg.as<uint32_t>());
+    g->dg.deg = g->deg.as<uint32_t>();
+    BC_TRY(g->x0.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+    BC_TRY(g->x1.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+    g->dg.x0 = g->x0.as<uint32_t>();
+    g->dg.x1 = g->x1.as<uint32_t>();
+
+    if (!directed) {
+        if (flags & BC_VALIDATE) {
+            BC_HIP(hipMemsetAsync(errb.p, 0, sizeof(uint32_t), s));
+            k_symmetric<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, errb.as<uint32_t>());
+            BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
+            BC_HIP(hipStreamSynchronize(s));
+            if (err & 8u) { set_error("undirected CSR is not symmetric"); return BC_EGRAPH; }
+        }
+        g->dg.irp = g->dg.rp;
+        g->dg.icol = g->dg.col;
+        DevBuf P, size, label;
+        BC_TRY(P.alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+        BC_TRY(size.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+        BC_TRY(label.alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+        BC_HIP(hipMemsetAsync(size.p, 0, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
+        if (n > 0) {
+            k_uf_init<<<grid_for(n), kBlk, 0, s>>>(n, P.as<int32_t>());
+            k_uf_union<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, P.as<int32_t>());
+            k_uf_count<<<grid_for(n), kBlk, 0, s>>>(n, P.as<int32_t>(), size.as<uint32_t>(), label.as<int32_t>());
+            k_uf_reach<<<grid_for(n), kBlk, 0, s>>>(n, label.as<int32_t>(), size.as<uint32_t>(),
+                                                    g->x0.as<uint32_t>(), g->x1.as<uint32_t>());
+        }
+        BC_HIP(hipStreamSynchronize(s));
+    } else {
+        BC_TRY(directed_reach(g));
+    }
+    BC_HIP(hipGetLastError());
+    auto t1 = std::chrono::steady_clock::now();
+    g->preprocess_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return BC_OK;
+}
+
+bc_status order_by_degree(bc_graph* g, int32_t* d_order) {
+    int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    hipStream_t s = g->stream;
+    if (!g->have_order_deg) {
+        DevBuf k0, k1, tmp;
+        BC_TRY(k0.alloc(sizeof(uint64_t) * (size_t)n));
+        BC_TRY(k1.alloc(sizeof(uint64_t) * (size_t)n));
+        BC_TRY(g->order_deg.alloc(sizeof(int32_t) * (size_t)n));
+        k_degree_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.deg, k0.as<uint64_t>());
+        BC_TRY(cub_call([&](void* t, size_t& b) {
+            return hipcub::DeviceRadixSort::SortKeys(t, b, k0.as<uint64_t>(), k1.as<uint64_t>(), n, 0, 64, s);
+        }, s, tmp));
+        k_low32<<<grid_for(n), kBlk, 0, s>>>(n, k1.as<uint64_t>(), g->order_deg.as<int32_t>());
+        BC_HIP(hipStreamSynchronize(s));
+        g->have_order_deg = true;
+    }
+    BC_HIP(hipMemcpyAsync(d_order, g->order_deg.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    return BC_OK;
+}
+
+bc_status order_by_scores(bc_graph* g, const float* h_scores, int32_t* d_order) {
+    int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    hipStream_t s = g->stream;
+    BC_TRY(order_by_degree(g, d_order));
+    DevBuf sc, key0, key1, val1, tmp;
+    BC_TRY(sc.alloc(sizeof(float) * (size_t)n));
+    BC_TRY(key0.alloc(sizeof(uint32_t) * (size_t)n));
+    BC_TRY(key1.alloc(sizeof(uint32_t) * (size_t)n));
+    BC_TRY(val1.alloc(sizeof(int32_t) * (size_t)n));
+    BC_HIP(hipMemcpyAsync(sc.p, h_scores, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+    k_score_keys<<<grid_for(n), kBlk, 0, s>>>(n, sc.as<float>(), d_order, key0.as<uint32_t>());
+    // radix sort is stable: equal scores keep the degree order
+    BC_TRY(cub_call([&](void* t, size_t& b) {
+        return hipcub::DeviceRadixSort::SortPairs(t, b, key0.as<uint32_t>(), key1.as<uint32_t>(), d_order,
+                                                  val1.as<int32_t>(), n, 0, 32, s);
+    }, s, tmp));
+    BC_HIP(hipMemcpyAsync(d_order, val1.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    BC_HIP(hipStreamSynchronize(s));
+    return BC_OK;
+}
+
+bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order) {
+    int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    hipStream_t s = g->stream;
+    DevBuf seen, errb;
+    BC_TRY(seen.alloc(sizeof(uint32_t) * (size_t)n));
+    BC_TRY(errb.alloc(sizeof(uint32_t)));
+    BC_HIP(hipMemcpyAsync(d_order, h_perm, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemsetAsync(seen.p, 0, sizeof(uint32_t) * (size_t)n, s));
+    BC_HIP(hipMemsetAsync(errb.p, 0, sizeof(uint32_t), s));
+    k_perm_check<<<grid_for(n), kBlk, 0, s>>>(n, d_order, seen.as<uint32_t>(), errb.as<uint32_t>());
+    uint32_t err = 0;
+    BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (err) { set_error("opts.perm is not a permutation of [0, n)"); return BC_EINVAL; }
+    return BC_OK;
+}
+
+}  // namespace bc

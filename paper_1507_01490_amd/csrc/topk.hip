@@ -1,0 +1,1059 @@
+// Top-k closeness on gfx950: Algorithm 1 with the BFSCut function
+// (Section 2.5), run as bit-parallel multi-source BFS.
+//
+// A batch holds W = 64 * WW sources, one bit each.  Per node the level
+// kernels keep three dense W-bit masks (WW uint64 words, node-major):
+//   seen[v]   sources that have reached v          (the "visited" marks)
+//   cur[v]    sources for which v is in the current frontier Gamma_d
+//   nxt[v]    sources reaching v in the level being built
+// and three node lists of capacity n: the current frontier and the next one
+// (double-buffered; a node appears once per level), and the reset list
+// (each node once, when its seen mask first becomes non-zero) that clears
+// the marks when the batch ends.
+//
+// Per source (SrcState) the counters of Table 1 are kept exactly:
+//   nd = n_d (nodes within distance d), fd = f_d (distance sum over them),
+//   tg = ~gamma_{d+1} (sum of out-degrees over Gamma_d), mvis (arcs a
+//   sequential search of this source scans).
+// After a level is built, gamma_{d+1}(b) and ~gamma_{d+2}(b) are column sums
+// over the new frontier masks; a source whose gamma is 0 is complete
+// (r = nd, f = fd).  Every live source is then tested against the current
+// k-th best record with the bound of Lemma 1 (undirected, x = r(v)) or
+// Lemma 2 (directed, x in {alpha(v), omega(v)}), and retired from the batch
+// (its bit cleared from `active`) when it cannot enter the top-k.
+//
+// The k-th best record: a device top-k list guarded by a lock, plus an
+// append-only ring of immutable threshold records and a monotone sequence
+// number.  A reader takes the record at seq-1 (acquire); any record it can
+// see is <= the true k-th best, and a stale one only weakens the cut (the
+// shared value of the parallel loop, Section 2.1), so results never change.
+#include <chrono>
+#include <cstring>
+
+#include "bc_internal.h"
+
+namespace bc {
+
+namespace {
+
+constexpr int kBlk = 256;  // threads per workgroup in every level kernel
+
+enum : int32_t { S_EMPTY = 0, S_LIVE = 1, S_CUT = 2, S_DONE = 3, S_TRIVIAL = 4 };
+
+struct SrcState {
+    int32_t id, status;
+    uint32_t x0, x1;
+    uint64_t nd, fd, tg, mvis;
+};
+
+struct Rec {           // one completed source; fields read/written atomically
+    uint64_t A, F;     // (r-1)^2 and f, or (0, 1) when r = 1
+    uint64_t f;        // exact farness
+    uint64_t idr;      // id (low 32 bits) | r (high 32 bits)
+};
+
+struct ThRec {         // immutable threshold record
+    uint64_t A, F;
+    int64_t id;
+};
+
+struct QStats {
+    unsigned long long m_vis, node_arcs, levels, pull_levels, n_cut, n_done, n_trivial, batches;
+};
+
+struct TopKDev {
+    int32_t k;
+    int32_t* cnt;
+    uint32_t* lock;
+    uint32_t* seq;
+    Rec* list;
+    ThRec* ring;
+};
+
+// Level-synchronous control block (device memory), one per plain slot.
+struct Ctl {
+    uint32_t d, flen, nlen, clen;  // level, frontier length, next-list and reset-list counters
+    uint32_t live, pull, chunk, done_blocks;
+    uint32_t stamp, parity;        // first-touch stamp; frontier list = parity ? qb : qa
+    unsigned long long front_arcs, acc_arcs;
+    unsigned long long active[4];
+    uint32_t cnt_g[256];
+    unsigned long long cnt_t[256];
+};
+
+struct SlotPtrs {
+    uint64_t* seen;     // n * WW
+    uint64_t* nxt;      // n * WW
+    uint64_t* cur;      // n * WW
+    uint32_t* touched;  // n, first-touch stamps (WW > 1 only)
+    int32_t* qa;        // n, frontier lists (double-buffered)
+    int32_t* qb;        // n
+    int32_t* clr;       // n, reset list
+};
+
+struct LevelParams {
+    float pull_alpha, pull_beta;
+    int32_t can_pull;
+};
+
+// ------------------------------------------------------------ helpers
+
+__device__ inline uint64_t ld64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int32_t ld32(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// key(x) > key(y): A_x F_y > A_y F_x in 128 bits, ties by the smaller id
+__device__ inline bool key_gt(uint64_t Ax, uint64_t Fx, int32_t ix, uint64_t Ay, uint64_t Fy, int32_t iy) {
+    unsigned __int128 a = (unsigned __int128)Ax * Fy;
+    unsigned __int128 b = (unsigned __int128)Ay * Fx;
+    if (a != b) return a > b;
+    return ix < iy;
+}
+
+// Insert one completed source into the top-k list (caller serialises).  When
+// the list is full afterwards, publish its k-th record.
+__device__ void topk_insert(const TopKDev& T, uint64_t A, uint64_t F, uint64_t f, int32_t id, uint32_t r) {
+    const int32_t k = T.k;
+    int32_t c = ld32(T.cnt);
+    if (c == k) {
+        Rec* last = &T.list[k - 1];
+        if (!key_gt(A, F, id, ld64(&last->A), ld64(&last->F), (int32_t)(uint32_t)ld64(&last->idr))) return;
+    }
+    int32_t i;
+    if (c < k) {
+        i = c;
+        c += 1;
+        __hip_atomic_store(T.cnt, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        i = k - 1;
+    }
+    while (i > 0) {
+        Rec* y = &T.list[i - 1];
+        uint64_t yA = ld64(&y->A), yF = ld64(&y->F), yidr = ld64(&y->idr);
+        if (!key_gt(A, F, id, yA, yF, (int32_t)(uint32_t)yidr)) break;
+        Rec* z = &T.list[i];
+        st64(&z->A, yA);
+        st64(&z->F, yF);
+        st64(&z->f, ld64(&y->f));
+        st64(&z->idr, yidr);
+        --i;
+    }
+    Rec* z = &T.list[i];
+    st64(&z->A, A);
+    st64(&z->F, F);
+    st64(&z->f, f);
+    st64(&z->idr, ((uint64_t)r << 32) | (uint32_t)id);
+    if (c == k) {
+        uint32_t s = __hip_atomic_load(T.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Rec* kth = &T.list[k - 1];
+        ThRec* o = &T.ring[s];
+        st64(&o->A, ld64(&kth->A));
+        st64(&o->F, ld64(&kth->F));
+        st64((uint64_t*)&o->id, (uint64_t)(int64_t)(int32_t)(uint32_t)ld64(&kth->idr));
+        __hip_atomic_store(T.seq, s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ inline bool load_threshold(const TopKDev& T, ThRec* th) {
+    uint32_t s = __hip_atomic_load(T.seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (s == 0) return false;
+    ThRec* r = &T.ring[s - 1];
+    th->A = ld64(&r->A);
+    th->F = ld64(&r->F);
+    th->id = (int64_t)ld64((const uint64_t*)&r->id);
+    return true;
+}
+
+__device__ inline void lock_acquire(uint32_t* l) {
+    while (atomicCAS(l, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(2);
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+}
+__device__ inline void lock_release(uint32_t* l) {
+    __hip_atomic_store(l, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The cut rule at level d for a live source (Lemma 1 / Lemma 2 with the
+// current k-th best record th).  For each candidate reach x,
+//   L_x = f_d - ~gamma_{d+1} + (d+2)(x - n_d)   (farness lower bound),
+// and the source cannot enter the top-k when L_x / (x-1)^2 > F/A for every
+// x, or >= for every x with the source id larger than th.id.
+__device__ inline bool cut_rule(const SrcState& s, uint32_t d, const ThRec& th) {
+    const uint32_t xs[2] = {s.x0, s.x1};
+    const int nx = s.x1 != s.x0 ? 2 : 1;
+    bool all_gt = true, all_ge = true;
+    for (int i = 0; i < nx; ++i) {
+        const int64_t x = (int64_t)xs[i];
+        const int64_t L = (int64_t)s.fd - (int64_t)s.tg + (int64_t)(d + 2) * (x - (int64_t)s.nd);
+        if (L <= 0) return false;
+        const unsigned __int128 lhs = (unsigned __int128)(uint64_t)L * th.A;
+        const unsigned __int128 rhs = (unsigned __int128)th.F * (uint64_t)((x - 1) * (x - 1));
+        all_gt = all_gt && (lhs > rhs);
+        all_ge = all_ge && (lhs >= rhs);
+    }
+    return all_gt || (all_ge && (int64_t)s.id > th.id);
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// Wave-aggregated append of w to list[] when `app` holds.
+__device__ inline void append_if(bool app, int32_t w, int32_t* list, uint32_t* ctr) {
+    unsigned long long bal = __ballot(app);
+    if (bal == 0) return;
+    const int lane = (int)lane_id();
+    const int leader = __ffsll((long long)bal) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(bal));
+    base = __shfl(base, leader);
+    if (app) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = w;
+}
+
+// Visit arc (u -> w) for the live source bits m of u.
+template <int WW>
+__device__ inline bool visit(const SlotPtrs& P, int32_t w, const uint64_t* m, uint32_t stamp) {
+    if constexpr (WW == 1) {
+        const uint64_t nb = m[0] & ~P.seen[w];
+        if (!nb) return false;
+        return atomicOr((unsigned long long*)&P.nxt[w], (unsigned long long)nb) == 0ull;
+    } else {
+        uint64_t nb[WW];
+        uint64_t any = 0;
+#pragma unroll
+        for (int j = 0; j < WW; ++j) {
+            nb[j] = m[j] & ~P.seen[(size_t)w * WW + j];
+            any |= nb[j];
+        }
+        if (!any) return false;
+#pragma unroll
+        for (int j = 0; j < WW; ++j)
+            if (nb[j]) atomicOr((unsigned long long*)&P.nxt[(size_t)w * WW + j], (unsigned long long)nb[j]);
+        return atomicMax(&P.touched[w], stamp) < stamp;
+    }
+}
+
+// Block-wide exclusive scan of one uint32 per thread (kBlk threads).
+__device__ inline uint32_t block_exscan(uint32_t v, uint32_t* tmp /* kBlk/64 + 1 */, uint32_t* total) {
+    const int lane = (int)lane_id();
+    const int wave = threadIdx.x / 64;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) tmp[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int i = 0; i < kBlk / 64; ++i) {
+            uint32_t t = tmp[i];
+            tmp[i] = acc;
+            acc += t;
+        }
+        tmp[kBlk / 64] = acc;
+    }
+    __syncthreads();
+    uint32_t r = tmp[wave] + x - v;
+    *total = tmp[kBlk / 64];
+    __syncthreads();
+    return r;
+}
+
+template <int WW>
+struct LdsExpand {
+    int32_t beg[kBlk];
+    uint32_t off[kBlk + 1];
+    uint64_t m[kBlk * WW];
+    uint32_t scan[kBlk / 64 + 1];
+    uint32_t chunk;
+};
+
+template <int WW>
+struct LdsFinish {
+    uint64_t nb[kBlk * WW];
+    uint32_t deg[kBlk];
+};
+
+// Expand entries [e0, e1) (at most kBlk) of the frontier list F: every arc of
+// every entry with a live bit, balanced over the workgroup by a scan of the
+// degrees.  Newly reached nodes are appended once to the next list N.
+template <int WW>
+__device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
+                               const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW>& L,
+                               unsigned long long* arcs) {
+    const int tid = threadIdx.x;
+    const uint32_t e = e0 + tid;
+    uint32_t deg = 0;
+    int32_t beg = 0;
+    uint64_t m[WW];
+#pragma unroll
+    for (int j = 0; j < WW; ++j) m[j] = 0;
+    if (e < e1) {
+        const int32_t u = F[e];
+        uint64_t any = 0;
+#pragma unroll
+        for (int j = 0; j < WW; ++j) {
+            m[j] = P.cur[(size_t)u * WW + j] & act[j];
+            any |= m[j];
+        }
+        if (any) {
+            beg = G.rp[u];
+            deg = (uint32_t)(G.rp[u + 1] - beg);
+        }
+    }
+    L.beg[tid] = beg;
+#pragma unroll
+    for (int j = 0; j < WW; ++j) L.m[tid * WW + j] = m[j];
+    uint32_t total;
+    const uint32_t off = block_exscan(deg, L.scan, &total);
+    L.off[tid] = off;
+    __syncthreads();
+    for (uint32_t a = tid; a < total; a += kBlk) {
+        // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
+        uint32_t lo = 0, hi = kBlk;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (L.off[mid] <= a) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t i = lo - 1;
+        const int32_t w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
+        const bool app = visit<WW>(P, w, &L.m[i * WW], stamp);
+        append_if(app, w, N, nctr);
+    }
+    if (tid == 0) *arcs += total;
+    __syncthreads();
+}
+
+// Column sums of the new frontier masks of one wave: for every source bit b,
+// gamma(b) += #entries with bit b, tgamma(b) += sum of their out-degrees.
+template <int WW>
+__device__ inline void count_bits(const uint64_t* nb, uint32_t deg, LdsFinish<WW>& L, uint32_t* cg,
+                                  unsigned long long* ct) {
+    const int tid = threadIdx.x;
+    const int lane = (int)lane_id();
+    const int wbase = tid - lane;
+#pragma unroll
+    for (int j = 0; j < WW; ++j) L.nb[tid * WW + j] = nb[j];
+    L.deg[tid] = deg;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < WW; ++j) {
+        unsigned long long nz = __ballot(nb[j] != 0ull);
+        uint32_t g = 0;
+        unsigned long long t = 0;
+        while (nz) {
+            const int i = __ffsll((long long)nz) - 1;
+            nz &= nz - 1ull;
+            const uint64_t x = L.nb[(wbase + i) * WW + j];
+            if ((x >> lane) & 1ull) {
+                g += 1;
+                t += L.deg[wbase + i];
+            }
+        }
+        if (g) {
+            atomicAdd(&cg[j * 64 + lane], g);
+            atomicAdd(&ct[j * 64 + lane], t);
+        }
+    }
+    __syncthreads();
+}
+
+// Zero the dense frontier masks of the list entries [first, len) (stride).
+template <int WW>
+__device__ inline void clear_cur(const SlotPtrs& P, const int32_t* F, uint32_t len, uint32_t first, uint32_t stride) {
+    for (uint32_t i = first + threadIdx.x; i < len; i += stride) {
+        const int32_t u = F[i];
+#pragma unroll
+        for (int j = 0; j < WW; ++j) P.cur[(size_t)u * WW + j] = 0;
+    }
+}
+
+// Build the new frontier from the next list N[0, len): fold the nxt bits into
+// seen and cur, put first-seen nodes on the reset list, and count the
+// per-source bits.  The loop is uniform over the workgroup.
+template <int WW>
+__device__ void finish_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t first,
+                               uint32_t stride, uint32_t* clen, LdsFinish<WW>& L, uint32_t* cg,
+                               unsigned long long* ct, unsigned long long* arcs) {
+    const int tid = threadIdx.x;
+    unsigned long long my_arcs = 0;
+    for (uint32_t rb = first; rb < len; rb += stride) {
+        const uint32_t i = rb + tid;
+        uint64_t nb[WW];
+#pragma unroll
+        for (int j = 0; j < WW; ++j) nb[j] = 0;
+        uint32_t deg = 0;
+        bool fresh = false;
+        int32_t w = 0;
+        if (i < len) {
+            w = N[i];
+            uint64_t old_any = 0;
+#pragma unroll
+            for (int j = 0; j < WW; ++j) {
+                const size_t o = (size_t)w * WW + j;
+                nb[j] = atomicExch((unsigned long long*)&P.nxt[o], 0ull);
+                const uint64_t old = P.seen[o];
+                old_any |= old;
+                P.seen[o] = old | nb[j];
+                P.cur[o] = nb[j];
+            }
+            fresh = old_any == 0;
+            deg = G.deg[w];
+            my_arcs += deg;
+        }
+        append_if(fresh, w, P.clr, clen);
+        count_bits<WW>(nb, deg, L, cg, ct);
+    }
+    if (my_arcs) atomicAdd(arcs, my_arcs);
+}
+
+// The per-level decision for the W sources of a batch (first W threads of one
+// workgroup).  With apply = true, first fold the counters of the level just
+// built (gamma == 0 completes a source).  Then insert completions into the
+// top-k, read the threshold, and cut.  Writes the active masks and returns
+// the live count (to every thread).
+struct CutLds {
+    uint32_t flags[kBlk];
+    ThRec th;
+    uint32_t have_th, live;
+};
+
+template <int WW>
+__device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, bool apply, const uint32_t* cg,
+                             const unsigned long long* ct, bool global_counts, bool locked, QStats* st,
+                             uint64_t* active, CutLds& CL) {
+    uint32_t* s_flags = CL.flags;
+    uint32_t* s_live = &CL.live;
+    const int tid = threadIdx.x;
+    if (tid < W) {
+        SrcState s = S[tid];
+        uint32_t fl = 0;
+        if (s.status == S_LIVE && apply) {
+            uint32_t g;
+            unsigned long long t;
+            if (global_counts) {
+                g = __hip_atomic_load(&cg[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                t = __hip_atomic_load(&ct[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                g = cg[tid];
+                t = ct[tid];
+            }
+            if (g == 0) {
+                s.status = S_DONE;
+                fl = 1;
+            } else {
+                s.nd += g;
+                s.fd += (uint64_t)d * g;
+                s.tg = t;
+            }
+        } else if (s.status == S_TRIVIAL && !apply) {
+            fl = 1;
+        }
+        S[tid] = s;
+        s_flags[tid] = fl;
+    }
+    if (tid == 0) *s_live = 0;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t nd = 0, nt = 0;
+        unsigned long long mv = 0;
+        bool any = false;
+        for (int j = 0; j < W; ++j) any = any || s_flags[j];
+        if (any) {
+            if (locked) lock_acquire(T.lock);
+            for (int j = 0; j < W; ++j) {
+                if (!s_flags[j]) continue;
+                const SrcState& s = S[j];
+                if (s.status == S_TRIVIAL) {
+                    topk_insert(T, 0, 1, 0, s.id, 1);
+                    ++nt;
+                } else {
+                    const uint64_t r = s.nd;
+                    const uint64_t A = r <= 1 ? 0 : (r - 1) * (r - 1);
+                    const uint64_t F = r <= 1 ? 1 : s.fd;
+                    topk_insert(T, A, F, s.fd, s.id, (uint32_t)r);
+                    ++nd;
+                    mv += s.mvis;
+                }
+            }
+            if (locked) lock_release(T.lock);
+            if (nd) atomicAdd(&st->n_done, (unsigned long long)nd);
+            if (nt) atomicAdd(&st->n_trivial, (unsigned long long)nt);
+            if (mv) atomicAdd(&st->m_vis, mv);
+        }
+        ThRec th;
+        CL.have_th = load_threshold(T, &th) ? 1u : 0u;
+        CL.th = th;
+    }
+    __syncthreads();
+    const bool have_th = CL.have_th != 0;
+    bool live = false;
+    if (tid < W) {
+        SrcState s = S[tid];
+        if (s.status == S_LIVE) {
+            if (have_th && cut_rule(s, d, CL.th)) {
+                s.status = S_CUT;
+                atomicAdd(&st->n_cut, 1ull);
+                if (s.mvis) atomicAdd(&st->m_vis, (unsigned long long)s.mvis);
+            } else {
+                s.mvis += s.tg;  // this source scans the out-arcs of Gamma_d
+                live = true;
+            }
+            S[tid] = s;
+        }
+    }
+    const unsigned long long bal = __ballot(live);
+    if (tid < W && lane_id() == 0) {
+        active[tid / 64] = bal;
+        if (bal) atomicAdd(s_live, (uint32_t)__popcll(bal));
+    }
+    __syncthreads();
+    const uint32_t nlive = *s_live;
+    __syncthreads();
+    return nlive;
+}
+
+// Initialise the W sources of batch b: the frontier list (qa) and the reset
+// list hold the sources themselves, each with its one-hot mask.
+template <int WW>
+__device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, uint32_t b, int W, const SlotPtrs& P,
+                           SrcState* S, uint32_t* flen_lds, unsigned long long* arcs_lds) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        *flen_lds = 0;
+        *arcs_lds = 0;
+    }
+    __syncthreads();
+    if (tid < W) {
+        const int64_t i = (int64_t)b * W + tid;
+        SrcState s;
+        s.nd = 1;
+        s.fd = 0;
+        s.mvis = 0;
+        if (i < n) {
+            const int32_t v = order[i];
+            s.id = v;
+            s.x0 = G.x0[v];
+            s.x1 = G.x1[v];
+            s.tg = G.deg[v];
+            s.status = s.x0 <= 1 ? S_TRIVIAL : S_LIVE;
+            if (s.status == S_LIVE) {
+                const uint64_t bit = 1ull << (tid & 63);
+#pragma unroll
+                for (int j = 0; j < WW; ++j) {
+                    const size_t o = (size_t)v * WW + j;
+                    const uint64_t x = (j == (tid >> 6)) ? bit : 0ull;
+                    P.seen[o] = x;
+                    P.cur[o] = x;
+                }
+                const uint32_t pos = atomicAdd(flen_lds, 1u);
+                P.qa[pos] = v;
+                P.clr[pos] = v;
+                atomicAdd(arcs_lds, (unsigned long long)s.tg);
+            }
+        } else {
+            s.id = -1;
+            s.x0 = s.x1 = 0;
+            s.tg = 0;
+            s.status = S_EMPTY;
+        }
+        S[tid] = s;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------- plain kernels
+//
+// One batch at a time; per level the host launches
+//   push (or pull) -> clearcur -> finish
+// and reads the control block to see whether any source is still live.
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* order, uint32_t b, int W,
+                                                    SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st) {
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_flen;
+    __shared__ unsigned long long s_arcs;
+    __shared__ uint64_t s_act[4];
+    init_batch<WW>(G, order, G.n, b, W, P, S, &s_flen, &s_arcs);
+    const uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, false, st, s_act, CL);
+    if (threadIdx.x == 0) {
+        C->stamp = C->stamp + 1;
+        C->d = 0;
+        C->flen = s_flen;
+        C->nlen = 0;
+        C->clen = s_flen;
+        C->parity = 0;
+        C->live = live;
+        C->pull = 0;
+        C->chunk = 0;
+        C->done_blocks = 0;
+        C->front_arcs = s_arcs;
+        C->acc_arcs = 0;
+        for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
+        atomicAdd(&st->batches, 1ull);
+    }
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_push(DevGraph G, SlotPtrs P, Ctl* C, QStats* st) {
+    __shared__ LdsExpand<WW> L;
+    __shared__ uint64_t s_act[WW];
+    __shared__ unsigned long long s_arcs;
+    const uint32_t flen = C->flen, stamp = C->stamp;
+    const int32_t* F = C->parity ? P.qb : P.qa;
+    int32_t* N = C->parity ? P.qa : P.qb;
+    if (threadIdx.x < WW) s_act[threadIdx.x] = C->active[threadIdx.x];
+    if (threadIdx.x == 0) s_arcs = 0;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) L.chunk = atomicAdd(&C->chunk, 1u);
+        __syncthreads();
+        const uint32_t e0 = L.chunk * kBlk;
+        __syncthreads();
+        if (e0 >= flen) break;
+        expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &C->nlen, stamp, L, &s_arcs);
+    }
+    if (threadIdx.x == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
+}
+
+// Bottom-up step: every node not yet seen by some live source looks for an
+// in-neighbour in the frontier of that source (early exit once all of its
+// unseen live bits are found).
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Ctl* C, QStats* st) {
+    uint64_t act[WW];
+#pragma unroll
+    for (int j = 0; j < WW; ++j) act[j] = C->active[j];
+    int32_t* N = C->parity ? P.qa : P.qb;
+    unsigned long long scanned = 0;
+    const uint32_t stride = gridDim.x * kBlk;
+    for (uint32_t base = blockIdx.x * kBlk; base < (uint32_t)G.n; base += stride) {
+        const int32_t w = (int32_t)(base + threadIdx.x);
+        bool app = false;
+        if (w < G.n) {
+            uint64_t unv[WW], acc[WW];
+            uint64_t any = 0;
+#pragma unroll
+            for (int j = 0; j < WW; ++j) {
+                unv[j] = act[j] & ~P.seen[(size_t)w * WW + j];
+                acc[j] = 0;
+                any |= unv[j];
+            }
+            if (any) {
+                const int32_t e1 = G.irp[w + 1];
+                for (int32_t e = G.irp[w]; e < e1; ++e) {
+                    const int32_t u = G.icol[e];
+                    ++scanned;
+                    bool full = true;
+#pragma unroll
+                    for (int j = 0; j < WW; ++j) {
+                        acc[j] |= P.cur[(size_t)u * WW + j] & unv[j];
+                        full = full && (acc[j] == unv[j]);
+                    }
+                    if (full) break;
+                }
+                uint64_t got = 0;
+#pragma unroll
+                for (int j = 0; j < WW; ++j) got |= acc[j];
+                if (got) {
+#pragma unroll
+                    for (int j = 0; j < WW; ++j) P.nxt[(size_t)w * WW + j] = acc[j];
+                    app = true;
+                }
+            }
+        }
+        append_if(app, w, N, &C->nlen);
+    }
+    if (scanned) atomicAdd(&st->node_arcs, scanned);
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C) {
+    const int32_t* F = C->parity ? P.qb : P.qa;
+    clear_cur<WW>(P, F, C->flen, blockIdx.x * kBlk, gridDim.x * kBlk);
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_finish(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
+                                                      QStats* st, int W, LevelParams lp) {
+    __shared__ LdsFinish<WW> L;
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_last;
+    __shared__ uint64_t s_act[4];
+    __shared__ unsigned long long s_arcs;
+    const int tid = threadIdx.x;
+    const uint32_t nlen = C->nlen, d = C->d;
+    const int32_t* N = C->parity ? P.qa : P.qb;
+    cg[tid] = 0;
+    ct[tid] = 0;
+    if (tid == 0) s_arcs = 0;
+    __syncthreads();
+    finish_entries<WW>(G, P, N, nlen, blockIdx.x * kBlk, gridDim.x * kBlk, &C->clen, L, cg, ct, &s_arcs);
+    __syncthreads();
+    if (tid < W && cg[tid]) {
+        atomicAdd(&C->cnt_g[tid], cg[tid]);
+        atomicAdd(&C->cnt_t[tid], ct[tid]);
+    }
+    if (tid == 0 && s_arcs) atomicAdd(&C->acc_arcs, s_arcs);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&C->done_blocks, 1u) == gridDim.x - 1) ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const uint32_t live = cut_step<WW>(T, S, W, d + 1, true, C->cnt_g, C->cnt_t, true, false, st, s_act, CL);
+    if (tid < W) {
+        C->cnt_g[tid] = 0;
+        C->cnt_t[tid] = 0;
+    }
+    if (tid == 0) {
+        const unsigned long long fa = __hip_atomic_load(&C->acc_arcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t pull = C->pull;
+        if (pull) atomicAdd(&st->pull_levels, 1ull);
+        if (lp.can_pull) {
+            if (!pull && lp.pull_alpha > 0.f && (double)fa > (double)G.m / lp.pull_alpha) pull = 1;
+            else if (pull && (double)nlen < (double)G.n / lp.pull_beta) pull = 0;
+        }
+        C->pull = pull;
+        C->d = d + 1;
+        C->flen = nlen;
+        C->nlen = 0;
+        C->parity ^= 1u;
+        C->live = live;
+        C->chunk = 0;
+        C->front_arcs = fa;
+        C->acc_arcs = 0;
+        C->stamp = C->stamp + 1;
+        for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
+        atomicAdd(&st->levels, 1ull);
+        __threadfence();
+        C->done_blocks = 0;
+    }
+}
+
+// End of a batch: reset seen and cur of every node the batch reached.
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
+    const uint32_t nc = C->clen;
+    for (uint32_t i = blockIdx.x * kBlk + threadIdx.x; i < nc; i += gridDim.x * kBlk) {
+        const int32_t w = P.clr[i];
+#pragma unroll
+        for (int j = 0; j < WW; ++j) {
+            P.seen[(size_t)w * WW + j] = 0;
+            P.cur[(size_t)w * WW + j] = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------ batched kernel
+
+// Persistent: every workgroup owns one slot and runs whole batches, pulling
+// batch indices from a device counter, with every level inside the workgroup.
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* order, int W, uint32_t nbatches,
+                                                 uint32_t* next_batch, SlotPtrs base, TopKDev T, QStats* st) {
+    __shared__ LdsExpand<WW> LE;
+    __shared__ LdsFinish<WW> LF;
+    __shared__ SrcState S[kBlk];
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b;
+    __shared__ uint64_t s_act[4];
+    __shared__ unsigned long long s_arcs, s_narcs;
+    const int tid = threadIdx.x;
+    const size_t slot = blockIdx.x;
+    const size_t words = (size_t)G.n * WW;
+    SlotPtrs P;
+    P.seen = base.seen + slot * words;
+    P.nxt = base.nxt + slot * words;
+    P.cur = base.cur + slot * words;
+    P.touched = WW > 1 ? base.touched + slot * (size_t)G.n : nullptr;
+    P.qa = base.qa + slot * (size_t)G.n;
+    P.qb = base.qb + slot * (size_t)G.n;
+    P.clr = base.clr + slot * (size_t)G.n;
+    uint32_t stamp = 0;
+    unsigned long long levels = 0, batches = 0;
+    if (tid == 0) s_narcs = 0;
+    for (;;) {
+        if (tid == 0) s_b = atomicAdd(next_batch, 1u);
+        __syncthreads();
+        const uint32_t b = s_b;
+        __syncthreads();
+        if (b >= nbatches) break;
+        ++batches;
+        init_batch<WW>(G, order, G.n, b, W, P, S, &s_flen, &s_arcs);
+        if (tid == 0) s_clen = s_flen;
+        uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL);
+        uint32_t flen = s_flen, d = 0, parity = 0;
+        while (live) {
+            ++stamp;
+            const int32_t* F = parity ? P.qb : P.qa;
+            int32_t* N = parity ? P.qa : P.qb;
+            if (tid == 0) s_nlen = 0;
+            __syncthreads();
+            for (uint32_t e0 = 0; e0 < flen; e0 += kBlk)
+                expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &s_nlen, stamp, LE, &s_narcs);
+            __syncthreads();
+            clear_cur<WW>(P, F, flen, 0, kBlk);
+            const uint32_t nlen = s_nlen;
+            cg[tid] = 0;
+            ct[tid] = 0;
+            if (tid == 0) s_arcs = 0;
+            __syncthreads();
+            finish_entries<WW>(G, P, N, nlen, 0, kBlk, &s_clen, LF, cg, ct, &s_arcs);
+            __syncthreads();
+            ++d;
+            ++levels;
+            live = cut_step<WW>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL);
+            flen = nlen;
+            parity ^= 1u;
+        }
+        // reset the marks of every node this batch reached
+        const uint32_t nc = s_clen;
+        for (uint32_t i = tid; i < nc; i += kBlk) {
+            const int32_t w = P.clr[i];
+#pragma unroll
+            for (int j = 0; j < WW; ++j) {
+                P.seen[(size_t)w * WW + j] = 0;
+                P.cur[(size_t)w * WW + j] = 0;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        atomicAdd(&st->levels, levels);
+        atomicAdd(&st->batches, batches);
+        if (s_narcs) atomicAdd(&st->node_arcs, s_narcs);
+    }
+}
+
+// --------------------------------------------------------- host side
+
+struct QueryBufs {
+    DevBuf order, topk, ring, stats, srcs, ctl, nextb;
+    DevBuf seen, nxt, cur, touched, qa, qb, clr;          // plain slot
+    DevBuf bseen, bnxt, bcur, btouched, bqa, bqb, bclr;   // batched slots
+};
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+unsigned clamp_grid(int64_t work_items, int64_t cap) {
+    int64_t b = (work_items + kBlk - 1) / kBlk;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+template <int WW>
+bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_order, TopKDev T, QStats* d_st,
+                 QueryBufs& B, int W) {
+    const DevGraph& G = g->dg;
+    hipStream_t s = g->stream;
+    const int32_t n = G.n;
+    const size_t N = (size_t)n;
+    const size_t words = N * WW;
+    const uint32_t nbatches = (uint32_t)((n + W - 1) / W);
+    const bool batched = o.mode == BC_MODE_BATCHED;
+    uint32_t seed = nbatches;
+    if (batched) {
+        int64_t sb = o.seed_batches >= 0 ? o.seed_batches : ((int64_t)k + W - 1) / W;
+        seed = (uint32_t)std::min<int64_t>(std::max<int64_t>(sb, 0), nbatches);
+    }
+    LevelParams lp{o.pull_alpha, o.pull_beta > 0.f ? o.pull_beta : 24.f, o.pull_alpha > 0.f ? 1 : 0};
+    const int cus = device_cus();
+
+    if (seed > 0) {
+        BC_TRY(B.seen.alloc(sizeof(uint64_t) * words));
+        BC_TRY(B.nxt.alloc(sizeof(uint64_t) * words));
+        BC_TRY(B.cur.alloc(sizeof(uint64_t) * words));
+        BC_TRY(B.qa.alloc(sizeof(int32_t) * N));
+        BC_TRY(B.qb.alloc(sizeof(int32_t) * N));
+        BC_TRY(B.clr.alloc(sizeof(int32_t) * N));
+        BC_HIP(hipMemsetAsync(B.seen.p, 0, sizeof(uint64_t) * words, s));
+        BC_HIP(hipMemsetAsync(B.nxt.p, 0, sizeof(uint64_t) * words, s));
+        BC_HIP(hipMemsetAsync(B.cur.p, 0, sizeof(uint64_t) * words, s));
+        if (WW > 1) {
+            BC_TRY(B.touched.alloc(sizeof(uint32_t) * N));
+            BC_HIP(hipMemsetAsync(B.touched.p, 0, sizeof(uint32_t) * N, s));
+        }
+        BC_TRY(B.srcs.alloc(sizeof(SrcState) * kBlk));
+        BC_TRY(B.ctl.alloc(sizeof(Ctl)));
+        BC_HIP(hipMemsetAsync(B.ctl.p, 0, sizeof(Ctl), s));
+        SlotPtrs P{B.seen.as<uint64_t>(), B.nxt.as<uint64_t>(), B.cur.as<uint64_t>(),
+                   WW > 1 ? B.touched.as<uint32_t>() : nullptr, B.qa.as<int32_t>(), B.qb.as<int32_t>(),
+                   B.clr.as<int32_t>()};
+        SrcState* S = B.srcs.as<SrcState>();
+        Ctl* C = B.ctl.as<Ctl>();
+        uint32_t* hctl = nullptr;
+        BC_HIP(hipHostMalloc((void**)&hctl, 64, hipHostMallocDefault));
+        struct HostFree {
+            uint32_t* p;
+            ~HostFree() { if (p) (void)hipHostFree(p); }
+        } hf{hctl};
+        for (uint32_t b = 0; b < seed; ++b) {
+            k_plain_init<WW><<<1, kBlk, 0, s>>>(G, d_order, b, W, P, S, C, T, d_st);
+            for (;;) {
+                BC_HIP(hipMemcpyAsync(hctl, C, 64, hipMemcpyDeviceToHost, s));
+                BC_HIP(hipStreamSynchronize(s));
+                // control block words: d, flen, nlen, clen, live, pull, chunk, done, stamp, parity, front_arcs
+                const uint32_t flen = hctl[1], live = hctl[4], pull = hctl[5];
+                unsigned long long fa;
+                std::memcpy(&fa, hctl + 10, sizeof(fa));
+                if (!live) break;
+                if (pull) k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st);
+                else k_plain_push<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st);
+                k_plain_clearcur<WW><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C);
+                // new entries <= arcs out of the frontier (push) or n (pull)
+                const int64_t bound = pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
+                k_plain_finish<WW><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, lp);
+            }
+            k_plain_clear<WW><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
+        }
+        BC_HIP(hipGetLastError());
+    }
+
+    if (batched && seed < nbatches) {
+        int slots = o.slots > 0 ? o.slots : 2 * cus;
+        // per-slot bytes: seen, nxt, cur (8 B x WW each per node), qa, qb, clr (4 B each), touched (WW > 1)
+        const size_t per_slot = N * (24 * WW + 12 + (WW > 1 ? 4 : 0));
+        size_t freeb = 0, totalb = 0;
+        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && per_slot > 0) {
+            const size_t cap = (size_t)(0.45 * (double)freeb) / per_slot;
+            if ((size_t)slots > cap) slots = (int)std::max<size_t>(cap, 1);
+        }
+        if ((uint32_t)slots > nbatches - seed) slots = (int)(nbatches - seed);
+        const size_t S_ = (size_t)slots;
+        BC_TRY(B.bseen.alloc(sizeof(uint64_t) * words * S_));
+        BC_TRY(B.bnxt.alloc(sizeof(uint64_t) * words * S_));
+        BC_TRY(B.bcur.alloc(sizeof(uint64_t) * words * S_));
+        BC_TRY(B.bqa.alloc(sizeof(int32_t) * N * S_));
+        BC_TRY(B.bqb.alloc(sizeof(int32_t) * N * S_));
+        BC_TRY(B.bclr.alloc(sizeof(int32_t) * N * S_));
+        BC_HIP(hipMemsetAsync(B.bseen.p, 0, sizeof(uint64_t) * words * S_, s));
+        BC_HIP(hipMemsetAsync(B.bnxt.p, 0, sizeof(uint64_t) * words * S_, s));
+        BC_HIP(hipMemsetAsync(B.bcur.p, 0, sizeof(uint64_t) * words * S_, s));
+        if (WW > 1) {
+            BC_TRY(B.btouched.alloc(sizeof(uint32_t) * N * S_));
+            BC_HIP(hipMemsetAsync(B.btouched.p, 0, sizeof(uint32_t) * N * S_, s));
+        }
+        BC_TRY(B.nextb.alloc(sizeof(uint32_t)));
+        BC_HIP(hipMemcpyAsync(B.nextb.p, &seed, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        SlotPtrs base{B.bseen.as<uint64_t>(), B.bnxt.as<uint64_t>(), B.bcur.as<uint64_t>(),
+                      WW > 1 ? B.btouched.as<uint32_t>() : nullptr, B.bqa.as<int32_t>(), B.bqb.as<int32_t>(),
+                      B.bclr.as<int32_t>()};
+        k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, B.nextb.as<uint32_t>(), base, T, d_st);
+        BC_HIP(hipGetLastError());
+    }
+    BC_HIP(hipStreamSynchronize(s));
+    return BC_OK;
+}
+
+}  // namespace
+
+bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness, uint32_t* reach,
+                   int32_t* count, bc_stats* st_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int32_t n = g->dg.n;
+    hipStream_t s = g->stream;
+    const int W = o.width;
+    if (W != 64 && W != 128 && W != 256) {
+        set_error("width must be 64, 128 or 256 (got %d)", W);
+        return BC_EINVAL;
+    }
+    if (o.mode != BC_MODE_PLAIN && o.mode != BC_MODE_BATCHED) {
+        set_error("unknown mode %d", o.mode);
+        return BC_EINVAL;
+    }
+    const int32_t kk = std::min(k, n);
+    QStats hst;
+    std::memset(&hst, 0, sizeof(hst));
+    if (kk > 0) {
+        QueryBufs B;
+        BC_TRY(B.order.alloc(sizeof(int32_t) * (size_t)n));
+        int32_t* d_order = B.order.as<int32_t>();
+        if (o.order == BC_ORDER_DEGREE) {
+            BC_TRY(order_by_degree(g, d_order));
+        } else if (o.order == BC_ORDER_GIVEN) {
+            if (!o.perm) { set_error("BC_ORDER_GIVEN needs opts.perm"); return BC_EINVAL; }
+            BC_TRY(order_given(g, o.perm, d_order));
+        } else if (o.order == BC_ORDER_SCORES) {
+            if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
+            BC_TRY(order_by_scores(g, o.scores, d_order));
+        } else {
+            set_error("unknown order %d", o.order);
+            return BC_EINVAL;
+        }
+        // top-k list: cnt, lock, seq (16 B header) + k records; ring of n + 1 records
+        const size_t hdr = 64;
+        BC_TRY(B.topk.alloc(hdr + sizeof(Rec) * (size_t)kk));
+        BC_TRY(B.ring.alloc(sizeof(ThRec) * ((size_t)n + 1)));
+        BC_TRY(B.stats.alloc(sizeof(QStats)));
+        BC_HIP(hipMemsetAsync(B.topk.p, 0, hdr + sizeof(Rec) * (size_t)kk, s));
+        BC_HIP(hipMemsetAsync(B.stats.p, 0, sizeof(QStats), s));
+        TopKDev T;
+        T.k = kk;
+        char* hb = B.topk.as<char>();
+        T.cnt = (int32_t*)hb;
+        T.lock = (uint32_t*)(hb + 4);
+        T.seq = (uint32_t*)(hb + 8);
+        T.list = (Rec*)(hb + hdr);
+        T.ring = B.ring.as<ThRec>();
+        QStats* d_st = B.stats.as<QStats>();
+        bc_status rs;
+        if (W == 64) rs = run_ww<1>(g, kk, o, d_order, T, d_st, B, W);
+        else if (W == 128) rs = run_ww<2>(g, kk, o, d_order, T, d_st, B, W);
+        else rs = run_ww<4>(g, kk, o, d_order, T, d_st, B, W);
+        if (rs != BC_OK) return rs;
+        int32_t cnt = 0;
+        std::vector<Rec> recs((size_t)kk);
+        BC_HIP(hipMemcpyAsync(&cnt, T.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(recs.data(), T.list, sizeof(Rec) * (size_t)kk, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(&hst, d_st, sizeof(QStats), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        if (cnt != kk) {
+            set_error("internal: top-k list holds %d of %d entries", cnt, kk);
+            return BC_EDEVICE;
+        }
+        for (int32_t i = 0; i < cnt; ++i) {
+            ids[i] = (int32_t)(uint32_t)(recs[i].idr & 0xFFFFFFFFu);
+            reach[i] = (uint32_t)(recs[i].idr >> 32);
+            farness[i] = recs[i].f;
+        }
+    }
+    *count = kk > 0 ? kk : 0;
+    auto t1 = std::chrono::steady_clock::now();
+    if (st_out) {
+        const uint32_t sz = st_out->size;
+        bc_stats o2;
+        std::memset(&o2, 0, sizeof(o2));
+        o2.size = sizeof(bc_stats);
+        o2.batches = (uint32_t)hst.batches;
+        o2.m_vis = hst.m_vis;
+        o2.node_arcs = hst.node_arcs;
+        o2.levels = hst.levels;
+        o2.pull_levels = hst.pull_levels;
+        o2.n_cut = hst.n_cut;
+        o2.n_done = hst.n_done;
+        o2.n_trivial = hst.n_trivial;
+        o2.preprocess_ms = g->preprocess_ms;
+        o2.query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        std::memcpy(st_out, &o2, std::min<size_t>(sz ? sz : sizeof(bc_stats), sizeof(bc_stats)));
+    }
+    return BC_OK;
+}
+
+}  // namespace bc

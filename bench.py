@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Top-k closeness benchmark on one MI355X.
+
+One step = the top-k queries of the workload for every k it is queried with
+(BA n=1,000,000, m=5: k = 1, 10, 100), on a graph already resident in HBM.
+Reported throughput is GTEPS: the visited arcs of the sequential method in
+decreasing-degree order (m_vis from the oracle, stored with the expected
+results) divided by the wall time of the step, so every variant is measured
+against the same work.
+
+Prints one JSON line with the batched (persistent) mode as `value`, the plain
+comparator (one batch of 64 sources per host-loop iteration), the roofline
+of the persistent level kernel (algorithmic bytes over its HIP-event time),
+and the CPU oracle timed on the host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "top-k closeness wall time & GTEPS on 1 MI355X; batched+learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(arcs: int, entries: int, discovered: int, W: int) -> int:
+    """Minimal HBM bytes of the level work (roofline):
+    per scanned arc: col[e] (4 B) + seen[w] gather (W/8 B);
+    per expanded frontier entry: list entry (4 B) + row_ptr pair (8 B) + cur[u] (W/8 B);
+    per discovered entry: list entry (4 B) + deg (4 B) + nxt read+reset (2 W/8 B)
+    + seen read+write (2 W/8 B) + cur write (W/8 B)."""
+    wb = W // 8
+    return arcs * (4 + wb) + entries * (12 + wb) + discovered * (8 + 5 * wb)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ba1m")
+    ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--width", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the multi-GPU sharding is a design in DESIGN.md and is not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1507_01490_amd as bc
+    from paper_1507_01490_amd import workloads
+
+    t0 = time.time()
+    g = workloads.build(args.workload)
+    log(f"[bench] built {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
+    gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    gold = None
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        if gold["sha256"] != g.sha256():
+            log("[bench] WARNING: generated graph differs from the stored one; parity not checked")
+            gold = None
+    ks = list(workloads.KS[args.workload])
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    G = bc.Graph(rp, col, directed=g.directed, stream=stream)
+    del rp, col
+    log(f"[bench] graph resident on GPU, pre-processing {G.preprocess_ms:.1f} ms")
+
+    def step(mode):
+        return [G.topk(k, mode=mode, width=args.width, slots=args.slots) for k in ks]
+
+    def check(results):
+        if gold is None:
+            return None
+        ok = True
+        for k, res in zip(ks, results):
+            ref = gold["results"][str(k)]
+            ok = ok and res.ids.tolist() == ref["ids"] and [int(x) for x in res.farness] == ref["farness"] \
+                and [int(x) for x in res.reach] == ref["reach"]
+        return ok
+
+    for i in range(args.warmup):
+        step(args.mode)
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    agg = dict(persistent_ms=0.0, seed_ms=0.0, defer_ms=0.0, n_deferred=0, arcs=0, entries=0, disc=0, m_vis=0,
+               node_arcs=0, levels=0)
+    parity = True
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        out = step(args.mode)
+        for r in out:
+            s = r.stats
+            agg["persistent_ms"] += s["persistent_ms"]
+            agg["seed_ms"] += s["seed_ms"]
+            agg["defer_ms"] += s["defer_ms"]
+            agg["n_deferred"] += s["n_deferred"]
+            agg["arcs"] += s["persistent_arcs"]
+            agg["entries"] += s["persistent_entries"]
+            agg["disc"] += s["persistent_discovered"]
+            agg["m_vis"] += s["m_vis"]
+            agg["node_arcs"] += s["node_arcs"]
+            agg["levels"] += s["levels"]
+        c = check(out)
+        parity = parity and (c is not False)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    log(f"[bench] {args.mode}: {ms_per_step:.2f} ms/step, parity={parity}")
+
+    work = sum(gold["results"][str(k)]["m_vis_seq"] for k in ks) if gold else agg["m_vis"] // args.steps
+    gteps = work / (ms_per_step / 1e3) / 1e9
+
+    plain = None
+    if args.plain_steps > 0 and args.mode != "plain":
+        step("plain")  # plain-mode workspace already sized; one untimed pass
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            pout = step("plain")
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - tp0) * 1e3 / args.plain_steps
+        pc = check(pout)
+        plain = dict(ms_per_step=round(pms, 3), value=round(work / (pms / 1e3) / 1e9, 4), unit="GTEPS",
+                     parity=pc, speedup_of_value=round(pms / ms_per_step, 2),
+                     config="one batch of 64 sources per host-loop iteration, degree order")
+        log(f"[bench] plain: {pms:.1f} ms/step, batched speed-up {pms / ms_per_step:.2f}x")
+
+    roofline = None
+    if args.mode == "batched" and agg["persistent_ms"] > 0:
+        nlaunch = args.steps * len(ks)
+        bytes_per_launch = algorithmic_bytes(agg["arcs"], agg["entries"], agg["disc"], args.width) / nlaunch
+        avg_ms = agg["persistent_ms"] / nlaunch
+        achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+        roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                        kernel="k_batched<1>", avg_launch_ms=round(avg_ms, 4),
+                        bytes_per_launch=int(bytes_per_launch),
+                        arcs_per_launch=int(agg["arcs"] / nlaunch))
+
+    cpu = None
+    if not args.skip_cpu and gold is not None:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        tc0 = time.perf_counter()
+        for k in ks:
+            oracle.topk(g, k, nthreads=threads)
+        tc = time.perf_counter() - tc0
+        cpu = dict(value=round(work / tc / 1e9, 4), unit="GTEPS", cores=threads, kind="oracle",
+                   sample=f"the full step (k={','.join(map(str, ks))}) on the same graph, "
+                          f"{threads} threads, {tc:.1f} s")
+        log(f"[bench] cpu oracle: {tc:.1f}s with {threads} threads")
+
+    line = dict(metric=METRIC, value=round(gteps, 4), unit="GTEPS", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="int64", data="synthetic",
+                config=dict(workload=workloads.DESCRIPTION[args.workload], k=ks, mode=args.mode,
+                            width=args.width, order="degree", parity_vs_oracle=parity,
+                            work_m_vis=int(work)),
+                breakdown_ms_per_step=dict(seed=round(agg["seed_ms"] / args.steps, 3),
+                                           persistent=round(agg["persistent_ms"] / args.steps, 3),
+                                           deferred=round(agg["defer_ms"] / args.steps, 3),
+                                           n_deferred=agg["n_deferred"] // args.steps,
+                                           node_arcs=agg["node_arcs"] // args.steps,
+                                           m_vis_gpu=agg["m_vis"] // args.steps),
+                roofline=roofline, cpu_baseline=cpu, plain=plain)
+    print(json.dumps(line), flush=True)
+    G.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -73,8 +73,10 @@ typedef struct bc_opts {
     float pull_beta;        /* pull -> push when frontier nodes < n / pull_beta          */
     int32_t slots;          /* BC_MODE_BATCHED: concurrent workgroup batches (0 = auto)  */
     int32_t seed_batches;   /* BC_MODE_BATCHED: level-synchronous batches first (-1 = auto) */
-    int32_t block;          /* threads per workgroup in the level kernels (0 = auto)     */
-    int32_t reserved;
+    int32_t block;          /* reserved, 0                                               */
+    int32_t defer_arcs;     /* BC_MODE_BATCHED: a source whose next level scans more arcs
+                               than this leaves its workgroup batch and is re-run by the
+                               level-synchronous kernels afterwards (0 = 65536, -1 = never) */
 } bc_opts;
 
 typedef struct bc_stats {
@@ -89,6 +91,17 @@ typedef struct bc_stats {
     uint64_t n_cut, n_done, n_trivial;  /* per-source outcomes                            */
     double preprocess_ms;   /* bc_graph_create time (canonical CSR and reach data)       */
     double query_ms;        /* bc_topk time, call to return                              */
+    double seed_ms;         /* level-synchronous part (all of it in plain mode), HIP events */
+    double persistent_ms;   /* persistent batched kernel, HIP events on its stream       */
+    uint64_t frontier_entries; /* frontier nodes expanded (each once per level)          */
+    uint64_t discovered;    /* nodes appended to a new level (each once per level)       */
+    uint64_t persistent_arcs;    /* node_arcs of the persistent kernel alone             */
+    uint64_t persistent_entries; /* frontier_entries of the persistent kernel alone      */
+    uint64_t persistent_discovered; /* discovered of the persistent kernel alone         */
+    double defer_ms;        /* level-synchronous re-run of deferred sources, HIP events  */
+    uint64_t n_deferred;    /* sources deferred out of the persistent kernel             */
+    double phase_ms[5];     /* persistent kernel, summed over its workgroups: batch set-up,
+                               level expansion, level build, cut step, mark reset        */
 } bc_stats;
 
 /* Fill *opts with the defaults (plain mode, degree order, W = 64). */

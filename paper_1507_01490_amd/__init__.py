@@ -46,7 +46,7 @@ class Opts(ctypes.Structure):
                 ("width", ctypes.c_int32), ("perm", ctypes.c_void_p), ("scores", ctypes.c_void_p),
                 ("pull_alpha", ctypes.c_float), ("pull_beta", ctypes.c_float),
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("defer_arcs", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -54,10 +54,17 @@ class Stats(ctypes.Structure):
                 ("node_arcs", ctypes.c_uint64), ("levels", ctypes.c_uint64),
                 ("pull_levels", ctypes.c_uint64), ("n_cut", ctypes.c_uint64),
                 ("n_done", ctypes.c_uint64), ("n_trivial", ctypes.c_uint64),
-                ("preprocess_ms", ctypes.c_double), ("query_ms", ctypes.c_double)]
+                ("preprocess_ms", ctypes.c_double), ("query_ms", ctypes.c_double),
+                ("seed_ms", ctypes.c_double), ("persistent_ms", ctypes.c_double),
+                ("frontier_entries", ctypes.c_uint64), ("discovered", ctypes.c_uint64),
+                ("persistent_arcs", ctypes.c_uint64), ("persistent_entries", ctypes.c_uint64),
+                ("persistent_discovered", ctypes.c_uint64), ("defer_ms", ctypes.c_double),
+                ("n_deferred", ctypes.c_uint64), ("phase_ms", ctypes.c_double * 5)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
 
 
 _lib = None
@@ -191,7 +198,7 @@ class Graph:
 
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
              pull_alpha: float = 0.0, pull_beta: float = 24.0, slots: int = 0,
-             seed_batches: int = -1) -> TopK:
+             seed_batches: int = -1, defer_arcs: int = 0) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach."""
         lib = load_library()
         o = Opts()
@@ -204,6 +211,7 @@ class Graph:
         o.pull_beta = float(pull_beta)
         o.slots = int(slots)
         o.seed_batches = int(seed_batches)
+        o.defer_arcs = int(defer_arcs)
         keep = []
         if order is not None:
             perm = np.ascontiguousarray(order, dtype=np.int32)

@@ -54,6 +54,7 @@ void bc_opts_default(bc_opts* o) {
     o->slots = 0;
     o->seed_batches = -1;
     o->block = 0;
+    o->defer_arcs = 0;
 }
 
 bc_status bc_graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -80,6 +82,22 @@ struct DevBuf {
 
 }  // namespace bc
 
+namespace bc {
+
+// Working memory of top-k queries on one graph, kept between queries.  Every
+// query leaves seen/nxt/cur all zero (each batch resets the nodes it
+// reached), so a cached workspace is reused without clearing.
+struct Workspace {
+    int ww = 0;        // mask words per node the buffers were sized for
+    int slots = 0;     // batched slots allocated
+    DevBuf seen, nxt, cur, touched, qa, qb, clr;         // level-synchronous slot
+    DevBuf bseen, bnxt, bcur, btouched, bqa, bqb, bclr;  // persistent slots
+    DevBuf srcs, ctl, nextb, slot_stamp, defer;
+    bool plain_ready = false;
+};
+
+}  // namespace bc
+
 struct bc_graph {
     bc::DevGraph dg{};
     bc::DevBuf rp, col, irp, icol, deg, x0, x1;
@@ -88,6 +106,9 @@ struct bc_graph {
     hipStream_t stream = nullptr;
     double preprocess_ms = 0.0;
     int device = 0;
+    std::mutex ws_mu;                       // guards ws_busy
+    bool ws_busy = false;
+    std::unique_ptr<bc::Workspace> ws;      // cached workspace (one query at a time)
 };
 
 namespace bc {

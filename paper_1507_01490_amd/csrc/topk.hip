@@ -38,7 +38,7 @@ namespace {
 
 constexpr int kBlk = 256;  // threads per workgroup in every level kernel
 
-enum : int32_t { S_EMPTY = 0, S_LIVE = 1, S_CUT = 2, S_DONE = 3, S_TRIVIAL = 4 };
+enum : int32_t { S_EMPTY = 0, S_LIVE = 1, S_CUT = 2, S_DONE = 3, S_TRIVIAL = 4, S_DEFER = 5 };
 
 struct SrcState {
     int32_t id, status;
@@ -59,6 +59,16 @@ struct ThRec {         // immutable threshold record
 
 struct QStats {
     unsigned long long m_vis, node_arcs, levels, pull_levels, n_cut, n_done, n_trivial, batches;
+    unsigned long long frontier_entries, discovered, n_deferred;
+    unsigned long long phase_ticks[5];  // persistent kernel: init+cut0, expand, finish, cut, reset (100 MHz)
+};
+
+// Sources handed from the persistent kernel to the level-synchronous kernels
+// (a source whose next level would scan more than the budget of arcs).
+struct DeferList {
+    int32_t* ids;       // capacity n
+    uint32_t* cnt;
+    uint64_t budget;    // 0: never defer
 };
 
 struct TopKDev {
@@ -160,8 +170,11 @@ __device__ void topk_insert(const TopKDev& T, uint64_t A, uint64_t F, uint64_t f
     }
 }
 
+// The record at seq-1 was written before seq was published (release); its
+// address depends on the loaded seq, and device-scope loads read past the
+// non-coherent caches, so a relaxed read of seq is enough here.
 __device__ inline bool load_threshold(const TopKDev& T, ThRec* th) {
-    uint32_t s = __hip_atomic_load(T.seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t s = __hip_atomic_load(T.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (s == 0) return false;
     ThRec* r = &T.ring[s - 1];
     th->A = ld64(&r->A);
@@ -285,7 +298,7 @@ struct LdsFinish {
 template <int WW>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
                                const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW>& L,
-                               unsigned long long* arcs) {
+                               unsigned long long* arcs, unsigned long long* entries) {
     const int tid = threadIdx.x;
     const uint32_t e = e0 + tid;
     uint32_t deg = 0;
@@ -306,6 +319,8 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
             deg = (uint32_t)(G.rp[u + 1] - beg);
         }
     }
+    const unsigned long long nlive = __ballot(deg != 0);
+    if ((tid & 63) == 0 && nlive) atomicAdd(entries, (unsigned long long)__popcll(nlive));
     L.beg[tid] = beg;
 #pragma unroll
     for (int j = 0; j < WW; ++j) L.m[tid * WW + j] = m[j];
@@ -426,7 +441,7 @@ struct CutLds {
 template <int WW>
 __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, bool apply, const uint32_t* cg,
                              const unsigned long long* ct, bool global_counts, bool locked, QStats* st,
-                             uint64_t* active, CutLds& CL) {
+                             uint64_t* active, CutLds& CL, const DeferList* D = nullptr) {
     uint32_t* s_flags = CL.flags;
     uint32_t* s_live = &CL.live;
     const int tid = threadIdx.x;
@@ -458,12 +473,10 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
         s_flags[tid] = fl;
     }
     if (tid == 0) *s_live = 0;
-    __syncthreads();
+    const int any = __syncthreads_or(tid < W ? (int)s_flags[tid] : 0);
     if (tid == 0) {
         uint32_t nd = 0, nt = 0;
         unsigned long long mv = 0;
-        bool any = false;
-        for (int j = 0; j < W; ++j) any = any || s_flags[j];
         if (any) {
             if (locked) lock_acquire(T.lock);
             for (int j = 0; j < W; ++j) {
@@ -499,6 +512,12 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
             if (have_th && cut_rule(s, d, CL.th)) {
                 s.status = S_CUT;
                 atomicAdd(&st->n_cut, 1ull);
+                if (s.mvis) atomicAdd(&st->m_vis, (unsigned long long)s.mvis);
+            } else if (D && D->budget && s.tg > D->budget) {
+                // too deep for one workgroup: restart it on the whole GPU later
+                s.status = S_DEFER;
+                D->ids[atomicAdd(D->cnt, 1u)] = s.id;
+                atomicAdd(&st->n_deferred, 1ull);
                 if (s.mvis) atomicAdd(&st->m_vis, (unsigned long long)s.mvis);
             } else {
                 s.mvis += s.tg;  // this source scans the out-arcs of Gamma_d
@@ -574,13 +593,13 @@ __device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, u
 // and reads the control block to see whether any source is still live.
 
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* order, uint32_t b, int W,
-                                                    SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st) {
+__global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* order, int32_t count, uint32_t b,
+                                                    int W, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st) {
     __shared__ CutLds CL;
     __shared__ uint32_t s_flen;
     __shared__ unsigned long long s_arcs;
     __shared__ uint64_t s_act[4];
-    init_batch<WW>(G, order, G.n, b, W, P, S, &s_flen, &s_arcs);
+    init_batch<WW>(G, order, count, b, W, P, S, &s_flen, &s_arcs);
     const uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, false, st, s_act, CL);
     if (threadIdx.x == 0) {
         C->stamp = C->stamp + 1;
@@ -604,12 +623,15 @@ template <int WW>
 __global__ __launch_bounds__(kBlk) void k_plain_push(DevGraph G, SlotPtrs P, Ctl* C, QStats* st) {
     __shared__ LdsExpand<WW> L;
     __shared__ uint64_t s_act[WW];
-    __shared__ unsigned long long s_arcs;
+    __shared__ unsigned long long s_arcs, s_ent;
     const uint32_t flen = C->flen, stamp = C->stamp;
     const int32_t* F = C->parity ? P.qb : P.qa;
     int32_t* N = C->parity ? P.qa : P.qb;
     if (threadIdx.x < WW) s_act[threadIdx.x] = C->active[threadIdx.x];
-    if (threadIdx.x == 0) s_arcs = 0;
+    if (threadIdx.x == 0) {
+        s_arcs = 0;
+        s_ent = 0;
+    }
     __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) L.chunk = atomicAdd(&C->chunk, 1u);
@@ -617,9 +639,10 @@ __global__ __launch_bounds__(kBlk) void k_plain_push(DevGraph G, SlotPtrs P, Ctl
         const uint32_t e0 = L.chunk * kBlk;
         __syncthreads();
         if (e0 >= flen) break;
-        expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &C->nlen, stamp, L, &s_arcs);
+        expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &C->nlen, stamp, L, &s_arcs, &s_ent);
     }
     if (threadIdx.x == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
+    if (threadIdx.x == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
 }
 
 // Bottom-up step: every node not yet seen by some live source looks for an
@@ -734,6 +757,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_finish(DevGraph G, SlotPtrs P, S
         C->stamp = C->stamp + 1;
         for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
         atomicAdd(&st->levels, 1ull);
+        atomicAdd(&st->discovered, (unsigned long long)nlen);
         __threadfence();
         C->done_blocks = 0;
     }
@@ -759,7 +783,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
 // batch indices from a device counter, with every level inside the workgroup.
 template <int WW>
 __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* order, int W, uint32_t nbatches,
-                                                 uint32_t* next_batch, SlotPtrs base, TopKDev T, QStats* st) {
+                                                 uint32_t* next_batch, SlotPtrs base, uint32_t* slot_stamp,
+                                                 TopKDev T, QStats* st, DeferList D) {
     __shared__ LdsExpand<WW> LE;
     __shared__ LdsFinish<WW> LF;
     __shared__ SrcState S[kBlk];
@@ -768,7 +793,7 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
     __shared__ CutLds CL;
     __shared__ uint32_t s_flen, s_nlen, s_clen, s_b;
     __shared__ uint64_t s_act[4];
-    __shared__ unsigned long long s_arcs, s_narcs;
+    __shared__ unsigned long long s_arcs, s_narcs, s_ent;
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
     const size_t words = (size_t)G.n * WW;
@@ -780,9 +805,14 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
     P.qa = base.qa + slot * (size_t)G.n;
     P.qb = base.qb + slot * (size_t)G.n;
     P.clr = base.clr + slot * (size_t)G.n;
-    uint32_t stamp = 0;
-    unsigned long long levels = 0, batches = 0;
-    if (tid == 0) s_narcs = 0;
+    // first-touch stamps keep growing across queries (the touched array is never cleared)
+    uint32_t stamp = slot_stamp[slot];
+    unsigned long long levels = 0, batches = 0, disc = 0;
+    unsigned long long ticks[5] = {0, 0, 0, 0, 0};
+    if (tid == 0) {
+        s_narcs = 0;
+        s_ent = 0;
+    }
     for (;;) {
         if (tid == 0) s_b = atomicAdd(next_batch, 1u);
         __syncthreads();
@@ -790,10 +820,13 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
         __syncthreads();
         if (b >= nbatches) break;
         ++batches;
+        const uint64_t tb = __builtin_amdgcn_s_memrealtime();
         init_batch<WW>(G, order, G.n, b, W, P, S, &s_flen, &s_arcs);
         if (tid == 0) s_clen = s_flen;
-        uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL);
+        uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D);
         uint32_t flen = s_flen, d = 0, parity = 0;
+        uint64_t tp = __builtin_amdgcn_s_memrealtime();
+        ticks[0] += tp - tb;
         while (live) {
             ++stamp;
             const int32_t* F = parity ? P.qb : P.qa;
@@ -801,21 +834,32 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
             if (tid == 0) s_nlen = 0;
             __syncthreads();
             for (uint32_t e0 = 0; e0 < flen; e0 += kBlk)
-                expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &s_nlen, stamp, LE, &s_narcs);
+                expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &s_nlen, stamp, LE, &s_narcs,
+                                   &s_ent);
             __syncthreads();
+            uint64_t tq = __builtin_amdgcn_s_memrealtime();
+            ticks[1] += tq - tp;
+            tp = tq;
             clear_cur<WW>(P, F, flen, 0, kBlk);
             const uint32_t nlen = s_nlen;
+            disc += nlen;
             cg[tid] = 0;
             ct[tid] = 0;
             if (tid == 0) s_arcs = 0;
             __syncthreads();
             finish_entries<WW>(G, P, N, nlen, 0, kBlk, &s_clen, LF, cg, ct, &s_arcs);
             __syncthreads();
+            tq = __builtin_amdgcn_s_memrealtime();
+            ticks[2] += tq - tp;
+            tp = tq;
             ++d;
             ++levels;
-            live = cut_step<WW>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL);
+            live = cut_step<WW>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
             flen = nlen;
             parity ^= 1u;
+            tq = __builtin_amdgcn_s_memrealtime();
+            ticks[3] += tq - tp;
+            tp = tq;
         }
         // reset the marks of every node this batch reached
         const uint32_t nc = s_clen;
@@ -828,20 +872,28 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
             }
         }
         __syncthreads();
+        ticks[4] += __builtin_amdgcn_s_memrealtime() - tp;
     }
     if (tid == 0) {
         atomicAdd(&st->levels, levels);
         atomicAdd(&st->batches, batches);
+        atomicAdd(&st->discovered, disc);
         if (s_narcs) atomicAdd(&st->node_arcs, s_narcs);
+        if (s_ent) atomicAdd(&st->frontier_entries, s_ent);
+        for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], ticks[i]);
+        slot_stamp[slot] = stamp;
     }
 }
 
 // --------------------------------------------------------- host side
 
 struct QueryBufs {
-    DevBuf order, topk, ring, stats, srcs, ctl, nextb;
-    DevBuf seen, nxt, cur, touched, qa, qb, clr;          // plain slot
-    DevBuf bseen, bnxt, bcur, btouched, bqa, bqb, bclr;   // batched slots
+    DevBuf order, topk, ring, stats;
+};
+
+struct Timing {
+    double seed_ms = 0, persistent_ms = 0, defer_ms = 0;
+    QStats seed_stats{}, persist_stats{};
 };
 
 int device_cus() {
@@ -858,14 +910,85 @@ unsigned clamp_grid(int64_t work_items, int64_t cap) {
     return (unsigned)b;
 }
 
+// RAII pair of HIP events recorded on the query stream.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    bc_status create() {
+        BC_HIP(hipEventCreate(&a));
+        BC_HIP(hipEventCreate(&b));
+        return BC_OK;
+    }
+    bc_status ms(double* out) {
+        float t = 0.f;
+        BC_HIP(hipEventSynchronize(b));
+        BC_HIP(hipEventElapsedTime(&t, a, b));
+        *out = t;
+        return BC_OK;
+    }
+};
+
+// Level-synchronous slot of the workspace (sized for WW words per node).
+bc_status ensure_plain(Workspace& W_, int32_t n, int ww, hipStream_t s) {
+    if (W_.plain_ready && W_.ww == ww) return BC_OK;
+    const size_t N = (size_t)n, words = N * ww;
+    BC_TRY(W_.seen.alloc(sizeof(uint64_t) * words));
+    BC_TRY(W_.nxt.alloc(sizeof(uint64_t) * words));
+    BC_TRY(W_.cur.alloc(sizeof(uint64_t) * words));
+    BC_TRY(W_.qa.alloc(sizeof(int32_t) * N));
+    BC_TRY(W_.qb.alloc(sizeof(int32_t) * N));
+    BC_TRY(W_.clr.alloc(sizeof(int32_t) * N));
+    BC_TRY(W_.touched.alloc(sizeof(uint32_t) * N));
+    BC_TRY(W_.srcs.alloc(sizeof(SrcState) * kBlk));
+    BC_TRY(W_.ctl.alloc(sizeof(Ctl)));
+    BC_HIP(hipMemsetAsync(W_.seen.p, 0, sizeof(uint64_t) * words, s));
+    BC_HIP(hipMemsetAsync(W_.nxt.p, 0, sizeof(uint64_t) * words, s));
+    BC_HIP(hipMemsetAsync(W_.cur.p, 0, sizeof(uint64_t) * words, s));
+    BC_HIP(hipMemsetAsync(W_.touched.p, 0, sizeof(uint32_t) * N, s));
+    BC_HIP(hipMemsetAsync(W_.ctl.p, 0, sizeof(Ctl), s));
+    W_.plain_ready = true;
+    return BC_OK;
+}
+
+// Persistent slots of the workspace; returns the slot count in *slots.
+bc_status ensure_batched(Workspace& W_, int32_t n, int ww, int want, hipStream_t s, int* slots) {
+    const size_t N = (size_t)n, words = N * ww;
+    if (W_.slots >= want && W_.ww == ww) {
+        *slots = want;
+        return BC_OK;
+    }
+    const size_t S_ = (size_t)want;
+    W_.bseen.release(); W_.bnxt.release(); W_.bcur.release(); W_.btouched.release();
+    W_.bqa.release(); W_.bqb.release(); W_.bclr.release(); W_.slot_stamp.release();
+    W_.slots = 0;
+    BC_TRY(W_.bseen.alloc(sizeof(uint64_t) * words * S_));
+    BC_TRY(W_.bnxt.alloc(sizeof(uint64_t) * words * S_));
+    BC_TRY(W_.bcur.alloc(sizeof(uint64_t) * words * S_));
+    BC_TRY(W_.bqa.alloc(sizeof(int32_t) * N * S_));
+    BC_TRY(W_.bqb.alloc(sizeof(int32_t) * N * S_));
+    BC_TRY(W_.bclr.alloc(sizeof(int32_t) * N * S_));
+    BC_TRY(W_.btouched.alloc(sizeof(uint32_t) * N * S_));
+    BC_TRY(W_.slot_stamp.alloc(sizeof(uint32_t) * S_));
+    BC_HIP(hipMemsetAsync(W_.bseen.p, 0, sizeof(uint64_t) * words * S_, s));
+    BC_HIP(hipMemsetAsync(W_.bnxt.p, 0, sizeof(uint64_t) * words * S_, s));
+    BC_HIP(hipMemsetAsync(W_.bcur.p, 0, sizeof(uint64_t) * words * S_, s));
+    BC_HIP(hipMemsetAsync(W_.btouched.p, 0, sizeof(uint32_t) * N * S_, s));
+    BC_HIP(hipMemsetAsync(W_.slot_stamp.p, 0, sizeof(uint32_t) * S_, s));
+    W_.slots = want;
+    *slots = want;
+    return BC_OK;
+}
+
 template <int WW>
 bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_order, TopKDev T, QStats* d_st,
-                 QueryBufs& B, int W) {
+                 Workspace& Wk, int W, Timing& tm) {
     const DevGraph& G = g->dg;
     hipStream_t s = g->stream;
     const int32_t n = G.n;
     const size_t N = (size_t)n;
-    const size_t words = N * WW;
     const uint32_t nbatches = (uint32_t)((n + W - 1) / W);
     const bool batched = o.mode == BC_MODE_BATCHED;
     uint32_t seed = nbatches;
@@ -875,37 +998,31 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
     }
     LevelParams lp{o.pull_alpha, o.pull_beta > 0.f ? o.pull_beta : 24.f, o.pull_alpha > 0.f ? 1 : 0};
     const int cus = device_cus();
+    if (Wk.ww != WW) {
+        // a different width: drop buffers sized for the old one
+        Wk.plain_ready = false;
+        Wk.slots = 0;
+    }
 
-    if (seed > 0) {
-        BC_TRY(B.seen.alloc(sizeof(uint64_t) * words));
-        BC_TRY(B.nxt.alloc(sizeof(uint64_t) * words));
-        BC_TRY(B.cur.alloc(sizeof(uint64_t) * words));
-        BC_TRY(B.qa.alloc(sizeof(int32_t) * N));
-        BC_TRY(B.qb.alloc(sizeof(int32_t) * N));
-        BC_TRY(B.clr.alloc(sizeof(int32_t) * N));
-        BC_HIP(hipMemsetAsync(B.seen.p, 0, sizeof(uint64_t) * words, s));
-        BC_HIP(hipMemsetAsync(B.nxt.p, 0, sizeof(uint64_t) * words, s));
-        BC_HIP(hipMemsetAsync(B.cur.p, 0, sizeof(uint64_t) * words, s));
-        if (WW > 1) {
-            BC_TRY(B.touched.alloc(sizeof(uint32_t) * N));
-            BC_HIP(hipMemsetAsync(B.touched.p, 0, sizeof(uint32_t) * N, s));
-        }
-        BC_TRY(B.srcs.alloc(sizeof(SrcState) * kBlk));
-        BC_TRY(B.ctl.alloc(sizeof(Ctl)));
-        BC_HIP(hipMemsetAsync(B.ctl.p, 0, sizeof(Ctl), s));
-        SlotPtrs P{B.seen.as<uint64_t>(), B.nxt.as<uint64_t>(), B.cur.as<uint64_t>(),
-                   WW > 1 ? B.touched.as<uint32_t>() : nullptr, B.qa.as<int32_t>(), B.qb.as<int32_t>(),
-                   B.clr.as<int32_t>()};
-        SrcState* S = B.srcs.as<SrcState>();
-        Ctl* C = B.ctl.as<Ctl>();
+    // level-synchronous batches over order[0, count), batches [0, nb)
+    auto run_plain = [&](const int32_t* ord, int32_t count, uint32_t nb, double* ms) -> bc_status {
+        BC_TRY(ensure_plain(Wk, n, WW, s));
+        Wk.ww = WW;
+        SlotPtrs P{Wk.seen.as<uint64_t>(), Wk.nxt.as<uint64_t>(), Wk.cur.as<uint64_t>(), Wk.touched.as<uint32_t>(),
+                   Wk.qa.as<int32_t>(), Wk.qb.as<int32_t>(), Wk.clr.as<int32_t>()};
+        SrcState* S = Wk.srcs.as<SrcState>();
+        Ctl* C = Wk.ctl.as<Ctl>();
         uint32_t* hctl = nullptr;
         BC_HIP(hipHostMalloc((void**)&hctl, 64, hipHostMallocDefault));
         struct HostFree {
             uint32_t* p;
             ~HostFree() { if (p) (void)hipHostFree(p); }
         } hf{hctl};
-        for (uint32_t b = 0; b < seed; ++b) {
-            k_plain_init<WW><<<1, kBlk, 0, s>>>(G, d_order, b, W, P, S, C, T, d_st);
+        EventPair ev;
+        BC_TRY(ev.create());
+        BC_HIP(hipEventRecord(ev.a, s));
+        for (uint32_t b = 0; b < nb; ++b) {
+            k_plain_init<WW><<<1, kBlk, 0, s>>>(G, ord, count, b, W, P, S, C, T, d_st);
             for (;;) {
                 BC_HIP(hipMemcpyAsync(hctl, C, 64, hipMemcpyDeviceToHost, s));
                 BC_HIP(hipStreamSynchronize(s));
@@ -923,40 +1040,59 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
             }
             k_plain_clear<WW><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
         }
+        BC_HIP(hipEventRecord(ev.b, s));
         BC_HIP(hipGetLastError());
+        double t = 0;
+        BC_TRY(ev.ms(&t));
+        *ms += t;
+        return BC_OK;
+    };
+
+    if (seed > 0) {
+        BC_TRY(run_plain(d_order, n, seed, &tm.seed_ms));
+        BC_HIP(hipMemcpyAsync(&tm.seed_stats, d_st, sizeof(QStats), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
     }
 
     if (batched && seed < nbatches) {
-        int slots = o.slots > 0 ? o.slots : 2 * cus;
-        // per-slot bytes: seen, nxt, cur (8 B x WW each per node), qa, qb, clr (4 B each), touched (WW > 1)
-        const size_t per_slot = N * (24 * WW + 12 + (WW > 1 ? 4 : 0));
+        int slots = o.slots > 0 ? o.slots : 4 * cus;
+        // per-slot bytes: seen, nxt, cur (8 B x WW each per node), qa, qb, clr, touched (4 B each)
+        const size_t per_slot = N * (24 * WW + 16);
         size_t freeb = 0, totalb = 0;
-        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && per_slot > 0) {
-            const size_t cap = (size_t)(0.45 * (double)freeb) / per_slot;
+        if (Wk.slots < slots && hipMemGetInfo(&freeb, &totalb) == hipSuccess && per_slot > 0) {
+            const size_t have = (Wk.ww == WW) ? (size_t)Wk.slots * per_slot : 0;
+            const size_t cap = ((size_t)(0.45 * (double)freeb) + have) / per_slot;
             if ((size_t)slots > cap) slots = (int)std::max<size_t>(cap, 1);
         }
         if ((uint32_t)slots > nbatches - seed) slots = (int)(nbatches - seed);
-        const size_t S_ = (size_t)slots;
-        BC_TRY(B.bseen.alloc(sizeof(uint64_t) * words * S_));
-        BC_TRY(B.bnxt.alloc(sizeof(uint64_t) * words * S_));
-        BC_TRY(B.bcur.alloc(sizeof(uint64_t) * words * S_));
-        BC_TRY(B.bqa.alloc(sizeof(int32_t) * N * S_));
-        BC_TRY(B.bqb.alloc(sizeof(int32_t) * N * S_));
-        BC_TRY(B.bclr.alloc(sizeof(int32_t) * N * S_));
-        BC_HIP(hipMemsetAsync(B.bseen.p, 0, sizeof(uint64_t) * words * S_, s));
-        BC_HIP(hipMemsetAsync(B.bnxt.p, 0, sizeof(uint64_t) * words * S_, s));
-        BC_HIP(hipMemsetAsync(B.bcur.p, 0, sizeof(uint64_t) * words * S_, s));
-        if (WW > 1) {
-            BC_TRY(B.btouched.alloc(sizeof(uint32_t) * N * S_));
-            BC_HIP(hipMemsetAsync(B.btouched.p, 0, sizeof(uint32_t) * N * S_, s));
-        }
-        BC_TRY(B.nextb.alloc(sizeof(uint32_t)));
-        BC_HIP(hipMemcpyAsync(B.nextb.p, &seed, sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        SlotPtrs base{B.bseen.as<uint64_t>(), B.bnxt.as<uint64_t>(), B.bcur.as<uint64_t>(),
-                      WW > 1 ? B.btouched.as<uint32_t>() : nullptr, B.bqa.as<int32_t>(), B.bqb.as<int32_t>(),
-                      B.bclr.as<int32_t>()};
-        k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, B.nextb.as<uint32_t>(), base, T, d_st);
+        if (Wk.ww != WW) Wk.slots = 0;
+        BC_TRY(ensure_batched(Wk, n, WW, slots, s, &slots));
+        Wk.ww = WW;
+        BC_TRY(Wk.nextb.alloc(sizeof(uint32_t)));
+        BC_HIP(hipMemcpyAsync(Wk.nextb.p, &seed, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        SlotPtrs base{Wk.bseen.as<uint64_t>(), Wk.bnxt.as<uint64_t>(), Wk.bcur.as<uint64_t>(),
+                      Wk.btouched.as<uint32_t>(), Wk.bqa.as<int32_t>(), Wk.bqb.as<int32_t>(), Wk.bclr.as<int32_t>()};
+        EventPair ev;
+        BC_TRY(ev.create());
+        BC_HIP(hipEventRecord(ev.a, s));
+        BC_TRY(Wk.defer.alloc(sizeof(int32_t) * N + 64));
+        uint32_t* dcnt = (uint32_t*)(Wk.defer.as<char>() + sizeof(int32_t) * N);
+        BC_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t), s));
+        DeferList D{Wk.defer.as<int32_t>(), dcnt, o.defer_arcs < 0 ? 0ull
+                    : (uint64_t)(o.defer_arcs > 0 ? o.defer_arcs : 65536)};
+        k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
+                                              Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
+        BC_HIP(hipEventRecord(ev.b, s));
         BC_HIP(hipGetLastError());
+        BC_TRY(ev.ms(&tm.persistent_ms));
+        BC_HIP(hipMemcpyAsync(&tm.persist_stats, d_st, sizeof(QStats), hipMemcpyDeviceToHost, s));
+        uint32_t ndef = 0;
+        BC_HIP(hipMemcpyAsync(&ndef, dcnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        if (ndef > 0) {
+            // deferred sources, restarted level-synchronously against the final-ish threshold
+            BC_TRY(run_plain(Wk.defer.as<int32_t>(), (int32_t)ndef, (ndef + W - 1) / W, &tm.defer_ms));
+        }
     }
     BC_HIP(hipStreamSynchronize(s));
     return BC_OK;
@@ -981,6 +1117,7 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
     const int32_t kk = std::min(k, n);
     QStats hst;
     std::memset(&hst, 0, sizeof(hst));
+    Timing tm;
     if (kk > 0) {
         QueryBufs B;
         BC_TRY(B.order.alloc(sizeof(int32_t) * (size_t)n));
@@ -1013,11 +1150,41 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
         T.list = (Rec*)(hb + hdr);
         T.ring = B.ring.as<ThRec>();
         QStats* d_st = B.stats.as<QStats>();
+        // the graph's cached workspace, or a private one when another query holds it
+        std::unique_ptr<Workspace> own;
+        Workspace* wk = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g->ws_mu);
+            if (!g->ws_busy) {
+                if (!g->ws) g->ws.reset(new Workspace());
+                g->ws_busy = true;
+                wk = g->ws.get();
+            }
+        }
+        if (!wk) {
+            own.reset(new Workspace());
+            wk = own.get();
+        }
+        struct Release {
+            bc_graph* g;
+            bool shared;
+            ~Release() {
+                if (shared) {
+                    std::lock_guard<std::mutex> lk(g->ws_mu);
+                    g->ws_busy = false;
+                }
+            }
+        } rel{g, own == nullptr};
         bc_status rs;
-        if (W == 64) rs = run_ww<1>(g, kk, o, d_order, T, d_st, B, W);
-        else if (W == 128) rs = run_ww<2>(g, kk, o, d_order, T, d_st, B, W);
-        else rs = run_ww<4>(g, kk, o, d_order, T, d_st, B, W);
-        if (rs != BC_OK) return rs;
+        if (W == 64) rs = run_ww<1>(g, kk, o, d_order, T, d_st, *wk, W, tm);
+        else if (W == 128) rs = run_ww<2>(g, kk, o, d_order, T, d_st, *wk, W, tm);
+        else rs = run_ww<4>(g, kk, o, d_order, T, d_st, *wk, W, tm);
+        if (rs != BC_OK) {
+            // a failed query may leave marks behind: never reuse its workspace
+            std::lock_guard<std::mutex> lk(g->ws_mu);
+            if (own == nullptr) g->ws.reset();
+            return rs;
+        }
         int32_t cnt = 0;
         std::vector<Rec> recs((size_t)kk);
         BC_HIP(hipMemcpyAsync(&cnt, T.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1051,6 +1218,17 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
         o2.n_trivial = hst.n_trivial;
         o2.preprocess_ms = g->preprocess_ms;
         o2.query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        o2.seed_ms = tm.seed_ms;
+        o2.persistent_ms = tm.persistent_ms;
+        o2.frontier_entries = hst.frontier_entries;
+        o2.discovered = hst.discovered;
+        const bool pers = tm.persistent_ms > 0;
+        o2.persistent_arcs = pers ? tm.persist_stats.node_arcs - tm.seed_stats.node_arcs : 0;
+        o2.persistent_entries = pers ? tm.persist_stats.frontier_entries - tm.seed_stats.frontier_entries : 0;
+        o2.persistent_discovered = pers ? tm.persist_stats.discovered - tm.seed_stats.discovered : 0;
+        o2.defer_ms = tm.defer_ms;
+        o2.n_deferred = hst.n_deferred;
+        for (int i = 0; i < 5; ++i) o2.phase_ms[i] = (double)hst.phase_ticks[i] / 1e5;
         std::memcpy(st_out, &o2, std::min<size_t>(sz ? sz : sizeof(bc_stats), sizeof(bc_stats)));
     }
     return BC_OK;

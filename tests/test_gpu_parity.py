@@ -24,6 +24,8 @@ VARIANTS = [
     dict(mode="batched", width=64),
     dict(mode="batched", width=128, seed_batches=0),
     dict(mode="batched", width=256, slots=3),
+    dict(mode="batched", width=64, defer_arcs=1),    # nearly every source re-run level-synchronously
+    dict(mode="batched", width=128, defer_arcs=40, slots=5),
 ]
 
 

@@ -55,6 +55,9 @@ typedef struct bc_graph bc_graph;
 #define BC_ORDER_DEGREE 0    /* decreasing out-degree, ties by increasing id (the paper's order) */
 #define BC_ORDER_GIVEN  1    /* opts.perm: a permutation of [0, n) (host pointer)                */
 #define BC_ORDER_SCORES 2    /* opts.scores: decreasing score, ties by out-degree then id        */
+#define BC_ORDER_GROUPED 3   /* decreasing out-degree; equal degrees grouped by their highest-degree
+                                neighbour (then id), so that a batch shares neighbourhoods       */
+#define BC_ORDER_AUTO   -1   /* BC_ORDER_GROUPED in batched mode, BC_ORDER_DEGREE in plain mode   */
 
 /* Execution mode.  Neither changes the result, only the speed. */
 #define BC_MODE_PLAIN   0    /* one batch of W sources at a time, level-synchronous
@@ -65,7 +68,7 @@ typedef struct bc_graph bc_graph;
 typedef struct bc_opts {
     uint32_t size;          /* sizeof(bc_opts): versioning                               */
     int32_t mode;           /* BC_MODE_*                                                 */
-    int32_t order;          /* BC_ORDER_*                                                */
+    int32_t order;          /* BC_ORDER_* (default BC_ORDER_AUTO)                        */
     int32_t width;          /* W: sources per bit-parallel batch, 64, 128 or 256         */
     const int32_t* perm;    /* BC_ORDER_GIVEN: host, n entries                           */
     const float* scores;    /* BC_ORDER_SCORES: host, n entries                          */
@@ -104,7 +107,8 @@ typedef struct bc_stats {
                                level expansion, level build, cut step, mark reset        */
 } bc_stats;
 
-/* Fill *opts with the defaults (plain mode, degree order, W = 64). */
+/* Fill *opts with the defaults (plain mode, automatic order, W = 64, bottom-up
+ * steps when the frontier holds more than m/14 arcs). */
 void bc_opts_default(bc_opts* opts);
 
 /* Message of the last failure on this thread ("" if none). */

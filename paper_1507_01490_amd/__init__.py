@@ -23,13 +23,13 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Graph", "TopK", "Opts", "Stats", "BcError", "load_library", "closeness",
-           "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES",
+           "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES", "ORDER_GROUPED",
            "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.so")
 
 BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS = 0x1, 0x2, 0x4
-ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES = 0, 1, 2
+ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_AUTO = 0, 1, 2, 3, -1
 MODE_PLAIN, MODE_BATCHED = 0, 1
 _STATUS = {0: "BC_OK", -1: "BC_EINVAL", -2: "BC_EGRAPH", -3: "BC_ENOMEM", -4: "BC_EDEVICE",
            -5: "BC_EAGAIN", -6: "BC_ECANCELED"}
@@ -197,9 +197,12 @@ class Graph:
         return rp, col[:self.m]
 
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
-             pull_alpha: float = 0.0, pull_beta: float = 24.0, slots: int = 0,
+             pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
              seed_batches: int = -1, defer_arcs: int = 0) -> TopK:
-        """The k nodes of largest closeness: ids, exact farness, exact reach."""
+        """The k nodes of largest closeness: ids, exact farness, exact reach.
+
+        order: None (automatic), "degree", "grouped", or a permutation of
+        range(n); scores: per-node floats (decreasing score first)."""
         lib = load_library()
         o = Opts()
         lib.bc_opts_default(ctypes.byref(o))
@@ -213,7 +216,9 @@ class Graph:
         o.seed_batches = int(seed_batches)
         o.defer_arcs = int(defer_arcs)
         keep = []
-        if order is not None:
+        if isinstance(order, str):
+            o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "auto": ORDER_AUTO}[order]
+        elif order is not None:
             perm = np.ascontiguousarray(order, dtype=np.int32)
             if perm.shape[0] != self.n:
                 raise ValueError("order must hold n entries")

@@ -45,11 +45,11 @@ void bc_opts_default(bc_opts* o) {
     std::memset(o, 0, sizeof(*o));
     o->size = sizeof(bc_opts);
     o->mode = BC_MODE_PLAIN;
-    o->order = BC_ORDER_DEGREE;
+    o->order = BC_ORDER_AUTO;
     o->width = 64;
     o->perm = nullptr;
     o->scores = nullptr;
-    o->pull_alpha = 0.f;
+    o->pull_alpha = 14.f;
     o->pull_beta = 24.f;
     o->slots = 0;
     o->seed_batches = -1;

@@ -90,8 +90,8 @@ namespace bc {
 struct Workspace {
     int ww = 0;        // mask words per node the buffers were sized for
     int slots = 0;     // batched slots allocated
-    DevBuf seen, nxt, cur, touched, qa, qb, clr;         // level-synchronous slot
-    DevBuf bseen, bnxt, bcur, btouched, bqa, bqb, bclr;  // persistent slots
+    DevBuf seen, qa, qb, clr;     // level-synchronous slot: node records and lists
+    DevBuf bseen, bqa, bqb, bclr;  // persistent slots
     DevBuf srcs, ctl, nextb, slot_stamp, defer;
     bool plain_ready = false;
 };
@@ -103,6 +103,8 @@ struct bc_graph {
     bc::DevBuf rp, col, irp, icol, deg, x0, x1;
     bc::DevBuf order_deg;  // cached degree order (int32 n), built on first use
     bool have_order_deg = false;
+    bc::DevBuf order_grp;  // cached grouped degree order
+    bool have_order_grp = false;
     hipStream_t stream = nullptr;
     double preprocess_ms = 0.0;
     int device = 0;
@@ -121,6 +123,7 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp, cons
 // Source orders (preprocess.hip): decreasing out-degree (ties by id), or a
 // given permutation, or decreasing score (ties by degree, then id).
 bc_status order_by_degree(bc_graph* g, int32_t* d_order);
+bc_status order_grouped(bc_graph* g, int32_t* d_order);
 bc_status order_by_scores(bc_graph* g, const float* h_scores, int32_t* d_order);
 bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order);
 

@@ -188,6 +188,33 @@ __global__ void k_low32(int32_t n, const uint64_t* __restrict__ key, int32_t* __
         out[u] = (int32_t)(key[u] & 0xFFFFFFFFu);
 }
 
+// hub(v): the out-neighbour of largest out-degree (ties by smaller id), n when
+// v has no out-neighbour; key = hub << 32 | v
+__global__ void k_hub_keys(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const uint32_t* __restrict__ deg, uint64_t* __restrict__ key) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int32_t best = n;
+        uint32_t bd = 0;
+        for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+            const int32_t w = col[i];
+            const uint32_t d = deg[w];
+            if (best == n || d > bd || (d == bd && w < best)) {
+                best = w;
+                bd = d;
+            }
+        }
+        key[u] = ((uint64_t)(uint32_t)best << 32) | (uint32_t)u;
+    }
+}
+
+__global__ void k_degkey_of(int32_t n, const int32_t* __restrict__ perm, const uint32_t* __restrict__ deg,
+                            uint32_t* __restrict__ key) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        key[i] = 0xFFFFFFFFu - deg[perm[i]];
+}
+
 // score -> unsigned key whose ascending order is decreasing score
 __global__ void k_score_keys(int32_t n, const float* __restrict__ s, const int32_t* __restrict__ order,
                              uint32_t* __restrict__ key) {
@@ -344,6 +371,39 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order) {
         g->have_order_deg = true;
     }
     BC_HIP(hipMemcpyAsync(d_order, g->order_deg.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    return BC_OK;
+}
+
+// Decreasing out-degree; among equal degrees, sources sharing their
+// highest-degree neighbour are adjacent (then by id), so a batch of
+// consecutive sources expands common neighbourhoods once.
+bc_status order_grouped(bc_graph* g, int32_t* d_order) {
+    int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    hipStream_t s = g->stream;
+    if (!g->have_order_grp) {
+        DevBuf k0, k1, perm, dk0, dk1, tmp;
+        BC_TRY(k0.alloc(sizeof(uint64_t) * (size_t)n));
+        BC_TRY(k1.alloc(sizeof(uint64_t) * (size_t)n));
+        BC_TRY(perm.alloc(sizeof(int32_t) * (size_t)n));
+        BC_TRY(dk0.alloc(sizeof(uint32_t) * (size_t)n));
+        BC_TRY(dk1.alloc(sizeof(uint32_t) * (size_t)n));
+        BC_TRY(g->order_grp.alloc(sizeof(int32_t) * (size_t)n));
+        k_hub_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, g->dg.deg, k0.as<uint64_t>());
+        BC_TRY(cub_call([&](void* t, size_t& b) {
+            return hipcub::DeviceRadixSort::SortKeys(t, b, k0.as<uint64_t>(), k1.as<uint64_t>(), n, 0, 64, s);
+        }, s, tmp));
+        k_low32<<<grid_for(n), kBlk, 0, s>>>(n, k1.as<uint64_t>(), perm.as<int32_t>());
+        k_degkey_of<<<grid_for(n), kBlk, 0, s>>>(n, perm.as<int32_t>(), g->dg.deg, dk0.as<uint32_t>());
+        // stable: equal degrees keep the (hub, id) order
+        BC_TRY(cub_call([&](void* t, size_t& b) {
+            return hipcub::DeviceRadixSort::SortPairs(t, b, dk0.as<uint32_t>(), dk1.as<uint32_t>(), perm.as<int32_t>(),
+                                                      g->order_grp.as<int32_t>(), n, 0, 32, s);
+        }, s, tmp));
+        BC_HIP(hipStreamSynchronize(s));
+        g->have_order_grp = true;
+    }
+    BC_HIP(hipMemcpyAsync(d_order, g->order_grp.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     return BC_OK;
 }
 

@@ -1,32 +1,38 @@
 // Top-k closeness on gfx950: Algorithm 1 with the BFSCut function
 // (Section 2.5), run as bit-parallel multi-source BFS.
 //
-// A batch holds W = 64 * WW sources, one bit each.  Per node the level
-// kernels keep three dense W-bit masks (WW uint64 words, node-major):
-//   seen[v]   sources that have reached v          (the "visited" marks)
-//   cur[v]    sources for which v is in the current frontier Gamma_d
-//   nxt[v]    sources reaching v in the level being built
-// and three node lists of capacity n: the current frontier and the next one
-// (double-buffered; a node appears once per level), and the reset list
-// (each node once, when its seen mask first becomes non-zero) that clears
-// the marks when the batch ends.
+// A batch holds W = 64 * WW sources, one bit each.  Every node has one
+// record per batch slot (SW uint64 words, node-major, one 32/64/128-byte
+// block so that every per-node access touches one cache line):
+//   seen[WW]   sources that have reached the node      (the "visited" marks)
+//   nxt[WW]    sources reaching it in the level being built
+//   cur[WW]    sources for which it is in the current frontier Gamma_d
+//   meta       low 32 bits: first-touch stamp (WW > 1); high 32 bits: out-degree
+// plus three node lists of capacity n: the current frontier F (compacted to
+// nodes with a live source bit), the nodes reached by the level being built
+// N (each once per level), and the reset list (each node once, when its seen
+// mask first becomes non-zero) that clears the marks when the batch ends.
 //
 // Per source (SrcState) the counters of Table 1 are kept exactly:
 //   nd = n_d (nodes within distance d), fd = f_d (distance sum over them),
 //   tg = ~gamma_{d+1} (sum of out-degrees over Gamma_d), mvis (arcs a
 //   sequential search of this source scans).
-// After a level is built, gamma_{d+1}(b) and ~gamma_{d+2}(b) are column sums
-// over the new frontier masks; a source whose gamma is 0 is complete
-// (r = nd, f = fd).  Every live source is then tested against the current
+// One level: expand F (every arc u->w with a live bit of cur[u] not yet in
+// seen[w] ORs it into nxt[w]); the thread whose atomic OR newly sets bit b of
+// nxt[w] adds 1 to gamma_{d+1}(b) and deg(w) to ~gamma_{d+2}(b), so each
+// (node, source) pair is counted once.  A source with gamma = 0 is complete
+// (r = nd, f = fd); every other live source is tested against the current
 // k-th best record with the bound of Lemma 1 (undirected, x = r(v)) or
-// Lemma 2 (directed, x in {alpha(v), omega(v)}), and retired from the batch
-// (its bit cleared from `active`) when it cannot enter the top-k.
+// Lemma 2 (directed, x in {alpha(v), omega(v)}), and its bit is retired when
+// it cannot enter the top-k.  Only then is the new level materialised
+// (seen |= nxt & live, cur = nxt & live), and only for live bits; when no
+// source of the batch is left, the pass just resets nxt.
 //
 // The k-th best record: a device top-k list guarded by a lock, plus an
 // append-only ring of immutable threshold records and a monotone sequence
-// number.  A reader takes the record at seq-1 (acquire); any record it can
-// see is <= the true k-th best, and a stale one only weakens the cut (the
-// shared value of the parallel loop, Section 2.1), so results never change.
+// number.  A reader takes the record at seq-1; any record it can see is <=
+// the true k-th best, and a stale one only weakens the cut (the shared value
+// of the parallel loop, Section 2.1), so results never change.
 #include <chrono>
 #include <cstring>
 
@@ -37,6 +43,13 @@ namespace bc {
 namespace {
 
 constexpr int kBlk = 256;  // threads per workgroup in every level kernel
+
+// words per node record: seen, nxt, cur (WW each) + meta, padded to 32/64/128 B
+template <int WW>
+struct Layout {
+    static constexpr int SW = WW == 1 ? 4 : (WW == 2 ? 8 : 16);
+    static constexpr int NXT = WW, CUR = 2 * WW, META = 3 * WW;
+};
 
 enum : int32_t { S_EMPTY = 0, S_LIVE = 1, S_CUT = 2, S_DONE = 3, S_TRIVIAL = 4, S_DEFER = 5 };
 
@@ -60,7 +73,7 @@ struct ThRec {         // immutable threshold record
 struct QStats {
     unsigned long long m_vis, node_arcs, levels, pull_levels, n_cut, n_done, n_trivial, batches;
     unsigned long long frontier_entries, discovered, n_deferred;
-    unsigned long long phase_ticks[5];  // persistent kernel: init+cut0, expand, finish, cut, reset (100 MHz)
+    unsigned long long phase_ticks[5];  // persistent kernel: set-up, expand, cut, build, reset (100 MHz)
 };
 
 // Sources handed from the persistent kernel to the level-synchronous kernels
@@ -80,11 +93,11 @@ struct TopKDev {
     ThRec* ring;
 };
 
-// Level-synchronous control block (device memory), one per plain slot.
+// Level-synchronous control block (device memory) of the plain slot.
 struct Ctl {
-    uint32_t d, flen, nlen, clen;  // level, frontier length, next-list and reset-list counters
+    uint32_t d, flen, nlen, clen;  // level, frontier length, reached-list and reset-list counters
     uint32_t live, pull, chunk, done_blocks;
-    uint32_t stamp, parity;        // first-touch stamp; frontier list = parity ? qb : qa
+    uint32_t stamp, pad0;
     unsigned long long front_arcs, acc_arcs;
     unsigned long long active[4];
     uint32_t cnt_g[256];
@@ -92,13 +105,10 @@ struct Ctl {
 };
 
 struct SlotPtrs {
-    uint64_t* seen;     // n * WW
-    uint64_t* nxt;      // n * WW
-    uint64_t* cur;      // n * WW
-    uint32_t* touched;  // n, first-touch stamps (WW > 1 only)
-    int32_t* qa;        // n, frontier lists (double-buffered)
-    int32_t* qb;        // n
-    int32_t* clr;       // n, reset list
+    uint64_t* ns;   // n * SW node records
+    int32_t* qa;    // n, frontier list F
+    int32_t* qb;    // n, reached list N
+    int32_t* clr;   // n, reset list
 };
 
 struct LevelParams {
@@ -226,26 +236,50 @@ __device__ inline void append_if(bool app, int32_t w, int32_t* list, uint32_t* c
     if (app) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = w;
 }
 
-// Visit arc (u -> w) for the live source bits m of u.
+// gamma(b) += 1 and tgamma(b) += deg for every bit b of `bits` (word j)
+__device__ inline void count_new(uint64_t bits, int j, uint32_t deg, uint32_t* cg, unsigned long long* ct) {
+    while (bits) {
+        const int b = __ffsll((long long)bits) - 1;
+        bits &= bits - 1ull;
+        atomicAdd(&cg[j * 64 + b], 1u);
+        atomicAdd(&ct[j * 64 + b], (unsigned long long)deg);
+    }
+}
+
+// Arc u->w for the live source bits m of u: OR the unseen ones into nxt[w],
+// count the bits this thread sets first, report whether w is new this level.
 template <int WW>
-__device__ inline bool visit(const SlotPtrs& P, int32_t w, const uint64_t* m, uint32_t stamp) {
+__device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp, uint32_t* cg,
+                             unsigned long long* ct) {
+    using Lo = Layout<WW>;
+    uint64_t nb[WW];
+    uint64_t any = 0;
     if constexpr (WW == 1) {
-        const uint64_t nb = m[0] & ~P.seen[w];
-        if (!nb) return false;
-        return atomicOr((unsigned long long*)&P.nxt[w], (unsigned long long)nb) == 0ull;
+        // seen and nxt share one 16-byte load; a stale nxt only costs an extra atomic
+        const ulonglong2 sn = *reinterpret_cast<const ulonglong2*>(rec);
+        nb[0] = m[0] & ~(sn.x | sn.y);
+        any = nb[0];
     } else {
-        uint64_t nb[WW];
-        uint64_t any = 0;
 #pragma unroll
         for (int j = 0; j < WW; ++j) {
-            nb[j] = m[j] & ~P.seen[(size_t)w * WW + j];
+            nb[j] = m[j] & ~(rec[j] | rec[Lo::NXT + j]);
             any |= nb[j];
         }
-        if (!any) return false;
+    }
+    if (!any) return false;
+    const uint32_t deg = (uint32_t)(rec[Lo::META] >> 32);
+    if constexpr (WW == 1) {
+        const uint64_t old = atomicOr((unsigned long long*)&rec[Lo::NXT], (unsigned long long)nb[0]);
+        count_new(nb[0] & ~old, 0, deg, cg, ct);
+        return old == 0ull;
+    } else {
 #pragma unroll
-        for (int j = 0; j < WW; ++j)
-            if (nb[j]) atomicOr((unsigned long long*)&P.nxt[(size_t)w * WW + j], (unsigned long long)nb[j]);
-        return atomicMax(&P.touched[w], stamp) < stamp;
+        for (int j = 0; j < WW; ++j) {
+            if (!nb[j]) continue;
+            const uint64_t old = atomicOr((unsigned long long*)&rec[Lo::NXT + j], (unsigned long long)nb[j]);
+            count_new(nb[j] & ~old, j, deg, cg, ct);
+        }
+        return atomicMax(reinterpret_cast<uint32_t*>(&rec[Lo::META]), stamp) < stamp;
     }
 }
 
@@ -286,19 +320,15 @@ struct LdsExpand {
     uint32_t chunk;
 };
 
-template <int WW>
-struct LdsFinish {
-    uint64_t nb[kBlk * WW];
-    uint32_t deg[kBlk];
-};
-
 // Expand entries [e0, e1) (at most kBlk) of the frontier list F: every arc of
 // every entry with a live bit, balanced over the workgroup by a scan of the
-// degrees.  Newly reached nodes are appended once to the next list N.
+// degrees.  Nodes reached for the first time this level go to N once.
 template <int WW>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
                                const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW>& L,
-                               unsigned long long* arcs, unsigned long long* entries) {
+                               uint32_t* cg, unsigned long long* ct, unsigned long long* arcs,
+                               unsigned long long* entries) {
+    using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     const uint32_t e = e0 + tid;
     uint32_t deg = 0;
@@ -308,10 +338,11 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
     for (int j = 0; j < WW; ++j) m[j] = 0;
     if (e < e1) {
         const int32_t u = F[e];
+        const uint64_t* rec = &P.ns[(size_t)u * Lo::SW];
         uint64_t any = 0;
 #pragma unroll
         for (int j = 0; j < WW; ++j) {
-            m[j] = P.cur[(size_t)u * WW + j] & act[j];
+            m[j] = rec[Lo::CUR + j] & act[j];
             any |= m[j];
         }
         if (any) {
@@ -337,101 +368,81 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
         }
         const uint32_t i = lo - 1;
         const int32_t w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
-        const bool app = visit<WW>(P, w, &L.m[i * WW], stamp);
+        const bool app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp, cg, ct);
         append_if(app, w, N, nctr);
     }
     if (tid == 0) *arcs += total;
     __syncthreads();
 }
 
-// Column sums of the new frontier masks of one wave: for every source bit b,
-// gamma(b) += #entries with bit b, tgamma(b) += sum of their out-degrees.
-template <int WW>
-__device__ inline void count_bits(const uint64_t* nb, uint32_t deg, LdsFinish<WW>& L, uint32_t* cg,
-                                  unsigned long long* ct) {
-    const int tid = threadIdx.x;
-    const int lane = (int)lane_id();
-    const int wbase = tid - lane;
-#pragma unroll
-    for (int j = 0; j < WW; ++j) L.nb[tid * WW + j] = nb[j];
-    L.deg[tid] = deg;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < WW; ++j) {
-        unsigned long long nz = __ballot(nb[j] != 0ull);
-        uint32_t g = 0;
-        unsigned long long t = 0;
-        while (nz) {
-            const int i = __ffsll((long long)nz) - 1;
-            nz &= nz - 1ull;
-            const uint64_t x = L.nb[(wbase + i) * WW + j];
-            if ((x >> lane) & 1ull) {
-                g += 1;
-                t += L.deg[wbase + i];
-            }
-        }
-        if (g) {
-            atomicAdd(&cg[j * 64 + lane], g);
-            atomicAdd(&ct[j * 64 + lane], t);
-        }
-    }
-    __syncthreads();
-}
-
-// Zero the dense frontier masks of the list entries [first, len) (stride).
+// Zero the cur masks of the list entries [first, len) (stride).
 template <int WW>
 __device__ inline void clear_cur(const SlotPtrs& P, const int32_t* F, uint32_t len, uint32_t first, uint32_t stride) {
+    using Lo = Layout<WW>;
     for (uint32_t i = first + threadIdx.x; i < len; i += stride) {
-        const int32_t u = F[i];
+        uint64_t* rec = &P.ns[(size_t)F[i] * Lo::SW];
 #pragma unroll
-        for (int j = 0; j < WW; ++j) P.cur[(size_t)u * WW + j] = 0;
+        for (int j = 0; j < WW; ++j) rec[Lo::CUR + j] = 0;
     }
 }
 
-// Build the new frontier from the next list N[0, len): fold the nxt bits into
-// seen and cur, put first-seen nodes on the reset list, and count the
-// per-source bits.  The loop is uniform over the workgroup.
+// Build the new frontier from the reached list N[0, len) once the cut step
+// has run: nxt is reset everywhere; the live bits go to seen and cur, nodes
+// with a live bit go to the frontier list F, first-seen nodes to the reset
+// list.  With no live bit at all only nxt is reset.  Block-uniform loop.
 template <int WW>
-__device__ void finish_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t first,
-                               uint32_t stride, uint32_t* clen, LdsFinish<WW>& L, uint32_t* cg,
-                               unsigned long long* ct, unsigned long long* arcs) {
+__device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t first, uint32_t stride,
+                            const uint64_t* act, bool any_live, int32_t* F, uint32_t* fctr, uint32_t* clen,
+                            unsigned long long* arcs) {
+    using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     unsigned long long my_arcs = 0;
     for (uint32_t rb = first; rb < len; rb += stride) {
         const uint32_t i = rb + tid;
-        uint64_t nb[WW];
-#pragma unroll
-        for (int j = 0; j < WW; ++j) nb[j] = 0;
-        uint32_t deg = 0;
-        bool fresh = false;
+        bool keep = false, fresh = false;
         int32_t w = 0;
         if (i < len) {
             w = N[i];
-            uint64_t old_any = 0;
+            uint64_t* rec = &P.ns[(size_t)w * Lo::SW];
+            if (!any_live) {
 #pragma unroll
-            for (int j = 0; j < WW; ++j) {
-                const size_t o = (size_t)w * WW + j;
-                nb[j] = atomicExch((unsigned long long*)&P.nxt[o], 0ull);
-                const uint64_t old = P.seen[o];
-                old_any |= old;
-                P.seen[o] = old | nb[j];
-                P.cur[o] = nb[j];
+                for (int j = 0; j < WW; ++j) rec[Lo::NXT + j] = 0;
+            } else {
+                uint64_t nb[WW];
+                uint64_t any = 0;
+#pragma unroll
+                for (int j = 0; j < WW; ++j) {
+                    nb[j] = atomicExch((unsigned long long*)&rec[Lo::NXT + j], 0ull) & act[j];
+                    any |= nb[j];
+                }
+                if (any) {
+                    uint64_t old_any = 0;
+#pragma unroll
+                    for (int j = 0; j < WW; ++j) {
+                        const uint64_t old = rec[j];
+                        old_any |= old;
+                        rec[j] = old | nb[j];
+                        rec[Lo::CUR + j] = nb[j];
+                    }
+                    keep = true;
+                    fresh = old_any == 0ull;
+                    my_arcs += (uint32_t)(rec[Lo::META] >> 32);
+                }
             }
-            fresh = old_any == 0;
-            deg = G.deg[w];
-            my_arcs += deg;
         }
-        append_if(fresh, w, P.clr, clen);
-        count_bits<WW>(nb, deg, L, cg, ct);
+        if (any_live) {
+            append_if(keep, w, F, fctr);
+            append_if(fresh, w, P.clr, clen);
+        }
     }
     if (my_arcs) atomicAdd(arcs, my_arcs);
 }
 
 // The per-level decision for the W sources of a batch (first W threads of one
 // workgroup).  With apply = true, first fold the counters of the level just
-// built (gamma == 0 completes a source).  Then insert completions into the
-// top-k, read the threshold, and cut.  Writes the active masks and returns
-// the live count (to every thread).
+// reached (gamma == 0 completes a source).  Then insert completions into the
+// top-k, read the threshold, and cut (or defer).  Writes the active masks
+// and returns the live count (to every thread).
 struct CutLds {
     uint32_t flags[kBlk];
     ThRec th;
@@ -537,11 +548,12 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
     return nlive;
 }
 
-// Initialise the W sources of batch b: the frontier list (qa) and the reset
+// Initialise the W sources of batch b: the frontier list F and the reset
 // list hold the sources themselves, each with its one-hot mask.
 template <int WW>
 __device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, uint32_t b, int W, const SlotPtrs& P,
                            SrcState* S, uint32_t* flen_lds, unsigned long long* arcs_lds) {
+    using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     if (tid == 0) {
         *flen_lds = 0;
@@ -563,12 +575,12 @@ __device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, u
             s.status = s.x0 <= 1 ? S_TRIVIAL : S_LIVE;
             if (s.status == S_LIVE) {
                 const uint64_t bit = 1ull << (tid & 63);
+                uint64_t* rec = &P.ns[(size_t)v * Lo::SW];
 #pragma unroll
                 for (int j = 0; j < WW; ++j) {
-                    const size_t o = (size_t)v * WW + j;
                     const uint64_t x = (j == (tid >> 6)) ? bit : 0ull;
-                    P.seen[o] = x;
-                    P.cur[o] = x;
+                    rec[j] = x;
+                    rec[Lo::CUR + j] = x;
                 }
                 const uint32_t pos = atomicAdd(flen_lds, 1u);
                 P.qa[pos] = v;
@@ -586,10 +598,20 @@ __device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, u
     __syncthreads();
 }
 
+// Write the out-degree into the meta word of every node record of `slots`
+// consecutive slots (the rest of a record is zero at rest).
+template <int WW>
+__global__ void k_slot_init(const uint32_t* __restrict__ deg, int32_t n, uint64_t* ns, int slots) {
+    using Lo = Layout<WW>;
+    const size_t total = (size_t)n * slots;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        ns[i * Lo::SW + Lo::META] = (uint64_t)deg[i % (size_t)n] << 32;
+}
+
 // ------------------------------------------------------- plain kernels
 //
 // One batch at a time; per level the host launches
-//   push (or pull) -> clearcur -> finish
+//   expand (or pull; its last workgroup runs the cut step) -> clearcur -> build
 // and reads the control block to see whether any source is still live.
 
 template <int WW>
@@ -607,7 +629,6 @@ __global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* 
         C->flen = s_flen;
         C->nlen = 0;
         C->clen = s_flen;
-        C->parity = 0;
         C->live = live;
         C->pull = 0;
         C->chunk = 0;
@@ -619,64 +640,120 @@ __global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* 
     }
 }
 
+// Shared epilogue of the plain expand/pull kernels: flush the workgroup's bit
+// counters; the last workgroup to finish runs the cut step for the level.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_push(DevGraph G, SlotPtrs P, Ctl* C, QStats* st) {
+__device__ void plain_level_epilogue(Ctl* C, SrcState* S, TopKDev T, QStats* st, int W, const uint32_t* cg,
+                                     const unsigned long long* ct, CutLds& CL, uint64_t* s_act, uint32_t* s_last) {
+    const int tid = threadIdx.x;
+    if (tid < W && cg[tid]) {
+        atomicAdd(&C->cnt_g[tid], cg[tid]);
+        atomicAdd(&C->cnt_t[tid], ct[tid]);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) *s_last = (atomicAdd(&C->done_blocks, 1u) == gridDim.x - 1) ? 1u : 0u;
+    __syncthreads();
+    if (!*s_last) return;
+    __threadfence();
+    const uint32_t d = C->d;
+    const uint32_t live = cut_step<WW>(T, S, W, d + 1, true, C->cnt_g, C->cnt_t, true, false, st, s_act, CL);
+    if (tid < W) {
+        C->cnt_g[tid] = 0;
+        C->cnt_t[tid] = 0;
+    }
+    if (tid == 0) {
+        if (C->pull) atomicAdd(&st->pull_levels, 1ull);
+        C->d = d + 1;
+        C->live = live;
+        C->chunk = 0;
+        for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
+        atomicAdd(&st->levels, 1ull);
+        atomicAdd(&st->discovered, (unsigned long long)C->nlen);
+        __threadfence();
+        C->done_blocks = 0;
+    }
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
+                                                      QStats* st, int W) {
     __shared__ LdsExpand<WW> L;
-    __shared__ uint64_t s_act[WW];
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_last;
+    __shared__ uint64_t s_act[4];
     __shared__ unsigned long long s_arcs, s_ent;
     const uint32_t flen = C->flen, stamp = C->stamp;
-    const int32_t* F = C->parity ? P.qb : P.qa;
-    int32_t* N = C->parity ? P.qa : P.qb;
-    if (threadIdx.x < WW) s_act[threadIdx.x] = C->active[threadIdx.x];
-    if (threadIdx.x == 0) {
+    const int tid = threadIdx.x;
+    if (tid < WW) s_act[tid] = C->active[tid];
+    cg[tid] = 0;
+    ct[tid] = 0;
+    if (tid == 0) {
         s_arcs = 0;
         s_ent = 0;
     }
     __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) L.chunk = atomicAdd(&C->chunk, 1u);
+        if (tid == 0) L.chunk = atomicAdd(&C->chunk, 1u);
         __syncthreads();
         const uint32_t e0 = L.chunk * kBlk;
         __syncthreads();
         if (e0 >= flen) break;
-        expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &C->nlen, stamp, L, &s_arcs, &s_ent);
+        expand_entries<WW>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &C->nlen, stamp, L, cg, ct, &s_arcs,
+                           &s_ent);
     }
-    if (threadIdx.x == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
-    if (threadIdx.x == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
+    if (tid == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
+    if (tid == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
+    __syncthreads();
+    plain_level_epilogue<WW>(C, S, T, st, W, cg, ct, CL, s_act, &s_last);
 }
 
 // Bottom-up step: every node not yet seen by some live source looks for an
 // in-neighbour in the frontier of that source (early exit once all of its
-// unseen live bits are found).
+// unseen live bits are found).  One thread owns a node, so all bits it finds
+// are new and counted here.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Ctl* C, QStats* st) {
+__global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
+                                                    QStats* st, int W) {
+    using Lo = Layout<WW>;
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_last;
+    __shared__ uint64_t s_act[4];
+    const int tid = threadIdx.x;
     uint64_t act[WW];
 #pragma unroll
     for (int j = 0; j < WW; ++j) act[j] = C->active[j];
-    int32_t* N = C->parity ? P.qa : P.qb;
+    cg[tid] = 0;
+    ct[tid] = 0;
+    __syncthreads();
     unsigned long long scanned = 0;
     const uint32_t stride = gridDim.x * kBlk;
     for (uint32_t base = blockIdx.x * kBlk; base < (uint32_t)G.n; base += stride) {
-        const int32_t w = (int32_t)(base + threadIdx.x);
+        const int32_t w = (int32_t)(base + tid);
         bool app = false;
         if (w < G.n) {
+            uint64_t* rec = &P.ns[(size_t)w * Lo::SW];
             uint64_t unv[WW], acc[WW];
             uint64_t any = 0;
 #pragma unroll
             for (int j = 0; j < WW; ++j) {
-                unv[j] = act[j] & ~P.seen[(size_t)w * WW + j];
+                unv[j] = act[j] & ~rec[j];
                 acc[j] = 0;
                 any |= unv[j];
             }
             if (any) {
                 const int32_t e1 = G.irp[w + 1];
                 for (int32_t e = G.irp[w]; e < e1; ++e) {
-                    const int32_t u = G.icol[e];
+                    const uint64_t* ur = &P.ns[(size_t)G.icol[e] * Lo::SW];
                     ++scanned;
                     bool full = true;
 #pragma unroll
                     for (int j = 0; j < WW; ++j) {
-                        acc[j] |= P.cur[(size_t)u * WW + j] & unv[j];
+                        acc[j] |= ur[Lo::CUR + j] & unv[j];
                         full = full && (acc[j] == unv[j]);
                     }
                     if (full) break;
@@ -685,94 +762,86 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Ctl
 #pragma unroll
                 for (int j = 0; j < WW; ++j) got |= acc[j];
                 if (got) {
+                    const uint32_t deg = (uint32_t)(rec[Lo::META] >> 32);
 #pragma unroll
-                    for (int j = 0; j < WW; ++j) P.nxt[(size_t)w * WW + j] = acc[j];
+                    for (int j = 0; j < WW; ++j) {
+                        rec[Lo::NXT + j] = acc[j];
+                        count_new(acc[j], j, deg, cg, ct);
+                    }
                     app = true;
                 }
             }
         }
-        append_if(app, w, N, &C->nlen);
+        append_if(app, w, P.qb, &C->nlen);
     }
     if (scanned) atomicAdd(&st->node_arcs, scanned);
+    __syncthreads();
+    plain_level_epilogue<WW>(C, S, T, st, W, cg, ct, CL, s_act, &s_last);
 }
 
 template <int WW>
 __global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C) {
-    const int32_t* F = C->parity ? P.qb : P.qa;
-    clear_cur<WW>(P, F, C->flen, blockIdx.x * kBlk, gridDim.x * kBlk);
+    clear_cur<WW>(P, P.qa, C->flen, blockIdx.x * kBlk, gridDim.x * kBlk);
 }
 
+// Materialise the level (or only reset nxt when nothing is live); the last
+// workgroup closes the level: frontier length, next direction.  The chunk
+// counter is idle between levels and counts finished workgroups here; the
+// done_blocks word counts the new frontier entries.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_finish(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
-                                                      QStats* st, int W, LevelParams lp) {
-    __shared__ LdsFinish<WW> L;
-    __shared__ uint32_t cg[kBlk];
-    __shared__ unsigned long long ct[kBlk];
-    __shared__ CutLds CL;
+__global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ctl* C, LevelParams lp) {
     __shared__ uint32_t s_last;
-    __shared__ uint64_t s_act[4];
     __shared__ unsigned long long s_arcs;
     const int tid = threadIdx.x;
-    const uint32_t nlen = C->nlen, d = C->d;
-    const int32_t* N = C->parity ? P.qa : P.qb;
-    cg[tid] = 0;
-    ct[tid] = 0;
+    uint64_t act[WW];
+#pragma unroll
+    for (int j = 0; j < WW; ++j) act[j] = C->active[j];
+    const bool any_live = C->live != 0;
+    const uint32_t nlen = C->nlen;
     if (tid == 0) s_arcs = 0;
     __syncthreads();
-    finish_entries<WW>(G, P, N, nlen, blockIdx.x * kBlk, gridDim.x * kBlk, &C->clen, L, cg, ct, &s_arcs);
+    build_level<WW>(P, P.qb, nlen, blockIdx.x * kBlk, gridDim.x * kBlk, act, any_live, P.qa, &C->done_blocks,
+                    &C->clen, &s_arcs);
     __syncthreads();
-    if (tid < W && cg[tid]) {
-        atomicAdd(&C->cnt_g[tid], cg[tid]);
-        atomicAdd(&C->cnt_t[tid], ct[tid]);
-    }
     if (tid == 0 && s_arcs) atomicAdd(&C->acc_arcs, s_arcs);
     __threadfence();
     __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&C->done_blocks, 1u) == gridDim.x - 1) ? 1u : 0u;
+    if (tid == 0) s_last = (atomicAdd(&C->chunk, 1u) == gridDim.x - 1) ? 1u : 0u;
     __syncthreads();
-    if (!s_last) return;
+    if (!s_last || tid != 0) return;
     __threadfence();
-    const uint32_t live = cut_step<WW>(T, S, W, d + 1, true, C->cnt_g, C->cnt_t, true, false, st, s_act, CL);
-    if (tid < W) {
-        C->cnt_g[tid] = 0;
-        C->cnt_t[tid] = 0;
+    const uint32_t flen =
+        any_live ? __hip_atomic_load(&C->done_blocks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    const unsigned long long fa = __hip_atomic_load(&C->acc_arcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t pull = C->pull;
+    if (lp.can_pull) {
+        if (!pull && lp.pull_alpha > 0.f && (double)fa > (double)G.m / lp.pull_alpha) pull = 1;
+        else if (pull && (double)flen < (double)G.n / lp.pull_beta) pull = 0;
     }
-    if (tid == 0) {
-        const unsigned long long fa = __hip_atomic_load(&C->acc_arcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t pull = C->pull;
-        if (pull) atomicAdd(&st->pull_levels, 1ull);
-        if (lp.can_pull) {
-            if (!pull && lp.pull_alpha > 0.f && (double)fa > (double)G.m / lp.pull_alpha) pull = 1;
-            else if (pull && (double)nlen < (double)G.n / lp.pull_beta) pull = 0;
-        }
-        C->pull = pull;
-        C->d = d + 1;
-        C->flen = nlen;
-        C->nlen = 0;
-        C->parity ^= 1u;
-        C->live = live;
-        C->chunk = 0;
-        C->front_arcs = fa;
-        C->acc_arcs = 0;
-        C->stamp = C->stamp + 1;
-        for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
-        atomicAdd(&st->levels, 1ull);
-        atomicAdd(&st->discovered, (unsigned long long)nlen);
-        __threadfence();
-        C->done_blocks = 0;
-    }
+    C->pull = pull;
+    C->flen = flen;
+    C->nlen = 0;
+    C->front_arcs = fa;
+    C->acc_arcs = 0;
+    C->stamp = C->stamp + 1;
+    C->chunk = 0;
+    __threadfence();
+    C->done_blocks = 0;
 }
 
-// End of a batch: reset seen and cur of every node the batch reached.
+// End of a batch: reset seen and cur of every node the batch reached (nxt
+// is already zero; cur is non-zero only for sources of a batch that ended
+// at level 0).
 template <int WW>
 __global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
+    using Lo = Layout<WW>;
     const uint32_t nc = C->clen;
     for (uint32_t i = blockIdx.x * kBlk + threadIdx.x; i < nc; i += gridDim.x * kBlk) {
-        const int32_t w = P.clr[i];
+        uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
 #pragma unroll
         for (int j = 0; j < WW; ++j) {
-            P.seen[(size_t)w * WW + j] = 0;
-            P.cur[(size_t)w * WW + j] = 0;
+            rec[j] = 0;
+            rec[Lo::CUR + j] = 0;
         }
     }
 }
@@ -785,8 +854,8 @@ template <int WW>
 __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* order, int W, uint32_t nbatches,
                                                  uint32_t* next_batch, SlotPtrs base, uint32_t* slot_stamp,
                                                  TopKDev T, QStats* st, DeferList D) {
+    using Lo = Layout<WW>;
     __shared__ LdsExpand<WW> LE;
-    __shared__ LdsFinish<WW> LF;
     __shared__ SrcState S[kBlk];
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
@@ -796,16 +865,12 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
     __shared__ unsigned long long s_arcs, s_narcs, s_ent;
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
-    const size_t words = (size_t)G.n * WW;
     SlotPtrs P;
-    P.seen = base.seen + slot * words;
-    P.nxt = base.nxt + slot * words;
-    P.cur = base.cur + slot * words;
-    P.touched = WW > 1 ? base.touched + slot * (size_t)G.n : nullptr;
+    P.ns = base.ns + slot * (size_t)G.n * Lo::SW;
     P.qa = base.qa + slot * (size_t)G.n;
     P.qb = base.qb + slot * (size_t)G.n;
     P.clr = base.clr + slot * (size_t)G.n;
-    // first-touch stamps keep growing across queries (the touched array is never cleared)
+    // first-touch stamps keep growing across queries (stamps are never cleared)
     uint32_t stamp = slot_stamp[slot];
     unsigned long long levels = 0, batches = 0, disc = 0;
     unsigned long long ticks[5] = {0, 0, 0, 0, 0};
@@ -824,51 +889,48 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
         init_batch<WW>(G, order, G.n, b, W, P, S, &s_flen, &s_arcs);
         if (tid == 0) s_clen = s_flen;
         uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D);
-        uint32_t flen = s_flen, d = 0, parity = 0;
+        uint32_t flen = s_flen, d = 0;
         uint64_t tp = __builtin_amdgcn_s_memrealtime();
         ticks[0] += tp - tb;
         while (live) {
             ++stamp;
-            const int32_t* F = parity ? P.qb : P.qa;
-            int32_t* N = parity ? P.qa : P.qb;
+            cg[tid] = 0;
+            ct[tid] = 0;
             if (tid == 0) s_nlen = 0;
             __syncthreads();
             for (uint32_t e0 = 0; e0 < flen; e0 += kBlk)
-                expand_entries<WW>(G, P, F, e0, min(flen, e0 + kBlk), s_act, N, &s_nlen, stamp, LE, &s_narcs,
-                                   &s_ent);
+                expand_entries<WW>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &s_nlen, stamp, LE, cg, ct,
+                                   &s_narcs, &s_ent);
             __syncthreads();
-            uint64_t tq = __builtin_amdgcn_s_memrealtime();
-            ticks[1] += tq - tp;
-            tp = tq;
-            clear_cur<WW>(P, F, flen, 0, kBlk);
             const uint32_t nlen = s_nlen;
             disc += nlen;
-            cg[tid] = 0;
-            ct[tid] = 0;
-            if (tid == 0) s_arcs = 0;
-            __syncthreads();
-            finish_entries<WW>(G, P, N, nlen, 0, kBlk, &s_clen, LF, cg, ct, &s_arcs);
-            __syncthreads();
-            tq = __builtin_amdgcn_s_memrealtime();
-            ticks[2] += tq - tp;
+            uint64_t tq = __builtin_amdgcn_s_memrealtime();
+            ticks[1] += tq - tp;
             tp = tq;
             ++d;
             ++levels;
             live = cut_step<WW>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
-            flen = nlen;
-            parity ^= 1u;
+            tq = __builtin_amdgcn_s_memrealtime();
+            ticks[2] += tq - tp;
+            tp = tq;
+            clear_cur<WW>(P, P.qa, flen, 0, kBlk);
+            if (tid == 0) s_flen = 0;
+            __syncthreads();
+            build_level<WW>(P, P.qb, nlen, 0, kBlk, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs);
+            __syncthreads();
+            flen = s_flen;
             tq = __builtin_amdgcn_s_memrealtime();
             ticks[3] += tq - tp;
             tp = tq;
         }
-        // reset the marks of every node this batch reached
+        // reset seen and cur of every node this batch reached
         const uint32_t nc = s_clen;
         for (uint32_t i = tid; i < nc; i += kBlk) {
-            const int32_t w = P.clr[i];
+            uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
 #pragma unroll
             for (int j = 0; j < WW; ++j) {
-                P.seen[(size_t)w * WW + j] = 0;
-                P.cur[(size_t)w * WW + j] = 0;
+                rec[j] = 0;
+                rec[Lo::CUR + j] = 0;
             }
         }
         __syncthreads();
@@ -932,59 +994,53 @@ struct EventPair {
 };
 
 // Level-synchronous slot of the workspace (sized for WW words per node).
-bc_status ensure_plain(Workspace& W_, int32_t n, int ww, hipStream_t s) {
-    if (W_.plain_ready && W_.ww == ww) return BC_OK;
-    const size_t N = (size_t)n, words = N * ww;
+template <int WW>
+bc_status ensure_plain(Workspace& W_, const DevGraph& G, hipStream_t s) {
+    if (W_.plain_ready && W_.ww == WW) return BC_OK;
+    const size_t N = (size_t)G.n, words = N * Layout<WW>::SW;
     BC_TRY(W_.seen.alloc(sizeof(uint64_t) * words));
-    BC_TRY(W_.nxt.alloc(sizeof(uint64_t) * words));
-    BC_TRY(W_.cur.alloc(sizeof(uint64_t) * words));
     BC_TRY(W_.qa.alloc(sizeof(int32_t) * N));
     BC_TRY(W_.qb.alloc(sizeof(int32_t) * N));
     BC_TRY(W_.clr.alloc(sizeof(int32_t) * N));
-    BC_TRY(W_.touched.alloc(sizeof(uint32_t) * N));
     BC_TRY(W_.srcs.alloc(sizeof(SrcState) * kBlk));
     BC_TRY(W_.ctl.alloc(sizeof(Ctl)));
     BC_HIP(hipMemsetAsync(W_.seen.p, 0, sizeof(uint64_t) * words, s));
-    BC_HIP(hipMemsetAsync(W_.nxt.p, 0, sizeof(uint64_t) * words, s));
-    BC_HIP(hipMemsetAsync(W_.cur.p, 0, sizeof(uint64_t) * words, s));
-    BC_HIP(hipMemsetAsync(W_.touched.p, 0, sizeof(uint32_t) * N, s));
     BC_HIP(hipMemsetAsync(W_.ctl.p, 0, sizeof(Ctl), s));
+    if (N > 0) k_slot_init<WW><<<clamp_grid((int64_t)N, 4096), kBlk, 0, s>>>(G.deg, G.n, W_.seen.as<uint64_t>(), 1);
     W_.plain_ready = true;
     return BC_OK;
 }
 
-// Persistent slots of the workspace; returns the slot count in *slots.
-bc_status ensure_batched(Workspace& W_, int32_t n, int ww, int want, hipStream_t s, int* slots) {
-    const size_t N = (size_t)n, words = N * ww;
-    if (W_.slots >= want && W_.ww == ww) {
-        *slots = want;
-        return BC_OK;
-    }
+// Persistent slots of the workspace.
+template <int WW>
+bc_status ensure_batched(Workspace& W_, const DevGraph& G, int want, hipStream_t s) {
+    if (W_.slots >= want && W_.ww == WW) return BC_OK;
+    const size_t N = (size_t)G.n, words = N * Layout<WW>::SW;
     const size_t S_ = (size_t)want;
-    W_.bseen.release(); W_.bnxt.release(); W_.bcur.release(); W_.btouched.release();
-    W_.bqa.release(); W_.bqb.release(); W_.bclr.release(); W_.slot_stamp.release();
+    W_.bseen.release();
+    W_.bqa.release();
+    W_.bqb.release();
+    W_.bclr.release();
+    W_.slot_stamp.release();
     W_.slots = 0;
     BC_TRY(W_.bseen.alloc(sizeof(uint64_t) * words * S_));
-    BC_TRY(W_.bnxt.alloc(sizeof(uint64_t) * words * S_));
-    BC_TRY(W_.bcur.alloc(sizeof(uint64_t) * words * S_));
     BC_TRY(W_.bqa.alloc(sizeof(int32_t) * N * S_));
     BC_TRY(W_.bqb.alloc(sizeof(int32_t) * N * S_));
     BC_TRY(W_.bclr.alloc(sizeof(int32_t) * N * S_));
-    BC_TRY(W_.btouched.alloc(sizeof(uint32_t) * N * S_));
     BC_TRY(W_.slot_stamp.alloc(sizeof(uint32_t) * S_));
     BC_HIP(hipMemsetAsync(W_.bseen.p, 0, sizeof(uint64_t) * words * S_, s));
-    BC_HIP(hipMemsetAsync(W_.bnxt.p, 0, sizeof(uint64_t) * words * S_, s));
-    BC_HIP(hipMemsetAsync(W_.bcur.p, 0, sizeof(uint64_t) * words * S_, s));
-    BC_HIP(hipMemsetAsync(W_.btouched.p, 0, sizeof(uint32_t) * N * S_, s));
     BC_HIP(hipMemsetAsync(W_.slot_stamp.p, 0, sizeof(uint32_t) * S_, s));
+    if (N > 0)
+        k_slot_init<WW><<<clamp_grid((int64_t)(N * S_), 16384), kBlk, 0, s>>>(G.deg, G.n, W_.bseen.as<uint64_t>(),
+                                                                               want);
     W_.slots = want;
-    *slots = want;
     return BC_OK;
 }
 
 template <int WW>
 bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_order, TopKDev T, QStats* d_st,
                  Workspace& Wk, int W, Timing& tm) {
+    using Lo = Layout<WW>;
     const DevGraph& G = g->dg;
     hipStream_t s = g->stream;
     const int32_t n = G.n;
@@ -1002,14 +1058,13 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         // a different width: drop buffers sized for the old one
         Wk.plain_ready = false;
         Wk.slots = 0;
+        Wk.ww = WW;
     }
 
     // level-synchronous batches over order[0, count), batches [0, nb)
     auto run_plain = [&](const int32_t* ord, int32_t count, uint32_t nb, double* ms) -> bc_status {
-        BC_TRY(ensure_plain(Wk, n, WW, s));
-        Wk.ww = WW;
-        SlotPtrs P{Wk.seen.as<uint64_t>(), Wk.nxt.as<uint64_t>(), Wk.cur.as<uint64_t>(), Wk.touched.as<uint32_t>(),
-                   Wk.qa.as<int32_t>(), Wk.qb.as<int32_t>(), Wk.clr.as<int32_t>()};
+        BC_TRY(ensure_plain<WW>(Wk, G, s));
+        SlotPtrs P{Wk.seen.as<uint64_t>(), Wk.qa.as<int32_t>(), Wk.qb.as<int32_t>(), Wk.clr.as<int32_t>()};
         SrcState* S = Wk.srcs.as<SrcState>();
         Ctl* C = Wk.ctl.as<Ctl>();
         uint32_t* hctl = nullptr;
@@ -1026,17 +1081,18 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
             for (;;) {
                 BC_HIP(hipMemcpyAsync(hctl, C, 64, hipMemcpyDeviceToHost, s));
                 BC_HIP(hipStreamSynchronize(s));
-                // control block words: d, flen, nlen, clen, live, pull, chunk, done, stamp, parity, front_arcs
+                // control block words: d, flen, nlen, clen, live, pull, chunk, done, stamp, pad, front_arcs
                 const uint32_t flen = hctl[1], live = hctl[4], pull = hctl[5];
                 unsigned long long fa;
                 std::memcpy(&fa, hctl + 10, sizeof(fa));
                 if (!live) break;
-                if (pull) k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st);
-                else k_plain_push<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st);
+                if (pull) k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W);
+                else k_plain_expand<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W);
                 k_plain_clearcur<WW><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C);
-                // new entries <= arcs out of the frontier (push) or n (pull)
-                const int64_t bound = pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
-                k_plain_finish<WW><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, lp);
+                // reached nodes <= arcs out of the frontier (push) or n (pull)
+                const int64_t bound =
+                    pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
+                k_plain_build<WW><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, C, lp);
             }
             k_plain_clear<WW><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
         }
@@ -1055,31 +1111,28 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
     }
 
     if (batched && seed < nbatches) {
-        int slots = o.slots > 0 ? o.slots : 4 * cus;
-        // per-slot bytes: seen, nxt, cur (8 B x WW each per node), qa, qb, clr, touched (4 B each)
-        const size_t per_slot = N * (24 * WW + 16);
+        int slots = o.slots > 0 ? o.slots : cus;
+        // per-slot bytes: node records (SW words) and three int32 lists per node
+        const size_t per_slot = N * (8 * Lo::SW + 12);
         size_t freeb = 0, totalb = 0;
         if (Wk.slots < slots && hipMemGetInfo(&freeb, &totalb) == hipSuccess && per_slot > 0) {
-            const size_t have = (Wk.ww == WW) ? (size_t)Wk.slots * per_slot : 0;
+            const size_t have = (size_t)Wk.slots * per_slot;
             const size_t cap = ((size_t)(0.45 * (double)freeb) + have) / per_slot;
             if ((size_t)slots > cap) slots = (int)std::max<size_t>(cap, 1);
         }
         if ((uint32_t)slots > nbatches - seed) slots = (int)(nbatches - seed);
-        if (Wk.ww != WW) Wk.slots = 0;
-        BC_TRY(ensure_batched(Wk, n, WW, slots, s, &slots));
-        Wk.ww = WW;
+        BC_TRY(ensure_batched<WW>(Wk, G, slots, s));
         BC_TRY(Wk.nextb.alloc(sizeof(uint32_t)));
         BC_HIP(hipMemcpyAsync(Wk.nextb.p, &seed, sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        SlotPtrs base{Wk.bseen.as<uint64_t>(), Wk.bnxt.as<uint64_t>(), Wk.bcur.as<uint64_t>(),
-                      Wk.btouched.as<uint32_t>(), Wk.bqa.as<int32_t>(), Wk.bqb.as<int32_t>(), Wk.bclr.as<int32_t>()};
-        EventPair ev;
-        BC_TRY(ev.create());
-        BC_HIP(hipEventRecord(ev.a, s));
+        SlotPtrs base{Wk.bseen.as<uint64_t>(), Wk.bqa.as<int32_t>(), Wk.bqb.as<int32_t>(), Wk.bclr.as<int32_t>()};
         BC_TRY(Wk.defer.alloc(sizeof(int32_t) * N + 64));
         uint32_t* dcnt = (uint32_t*)(Wk.defer.as<char>() + sizeof(int32_t) * N);
         BC_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t), s));
-        DeferList D{Wk.defer.as<int32_t>(), dcnt, o.defer_arcs < 0 ? 0ull
-                    : (uint64_t)(o.defer_arcs > 0 ? o.defer_arcs : 65536)};
+        DeferList D{Wk.defer.as<int32_t>(), dcnt,
+                    o.defer_arcs < 0 ? 0ull : (uint64_t)(o.defer_arcs > 0 ? o.defer_arcs : 65536)};
+        EventPair ev;
+        BC_TRY(ev.create());
+        BC_HIP(hipEventRecord(ev.a, s));
         k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
                                               Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
         BC_HIP(hipEventRecord(ev.b, s));
@@ -1122,12 +1175,16 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
         QueryBufs B;
         BC_TRY(B.order.alloc(sizeof(int32_t) * (size_t)n));
         int32_t* d_order = B.order.as<int32_t>();
-        if (o.order == BC_ORDER_DEGREE) {
+        const int32_t ord = o.order == BC_ORDER_AUTO ? (o.mode == BC_MODE_BATCHED ? BC_ORDER_GROUPED : BC_ORDER_DEGREE)
+                                                      : o.order;
+        if (ord == BC_ORDER_DEGREE) {
             BC_TRY(order_by_degree(g, d_order));
-        } else if (o.order == BC_ORDER_GIVEN) {
+        } else if (ord == BC_ORDER_GROUPED) {
+            BC_TRY(order_grouped(g, d_order));
+        } else if (ord == BC_ORDER_GIVEN) {
             if (!o.perm) { set_error("BC_ORDER_GIVEN needs opts.perm"); return BC_EINVAL; }
             BC_TRY(order_given(g, o.perm, d_order));
-        } else if (o.order == BC_ORDER_SCORES) {
+        } else if (ord == BC_ORDER_SCORES) {
             if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
             BC_TRY(order_by_scores(g, o.scores, d_order));
         } else {

@@ -41,7 +41,7 @@ def test_opts_defaults_and_version():
     o = bc.Opts()
     lib.bc_opts_default(ctypes.byref(o))
     assert o.size == ctypes.sizeof(bc.Opts)
-    assert o.width == 64 and o.mode == bc.MODE_PLAIN and o.order == bc.ORDER_DEGREE
+    assert o.width == 64 and o.mode == bc.MODE_PLAIN and o.order == bc.ORDER_AUTO
     assert lib.bc_version().decode().startswith("bfscut")
 
 

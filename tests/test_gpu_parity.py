@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 VARIANTS = [
     dict(mode="plain", width=64),
+    dict(mode="plain", width=64, pull_alpha=0.0),
     dict(mode="plain", width=128),
     dict(mode="plain", width=256),
     dict(mode="plain", width=64, pull_alpha=1e9, pull_beta=1e-9),  # bottom-up from level 1 on
@@ -78,6 +79,8 @@ def test_orders_do_not_change_the_answer():
             assert_same(G.topk(10, order=rng.permutation(g.n), **v), ref, v)
             assert_same(G.topk(10, scores=rng.random(g.n), **v), ref, v)
             assert_same(G.topk(10, order=np.arange(g.n)[::-1], **v), ref, v)
+            assert_same(G.topk(10, order="grouped", **v), ref, v)
+            assert_same(G.topk(10, order="degree", **v), ref, v)
 
 
 @pytest.mark.parametrize("k", [1, 10])

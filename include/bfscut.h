@@ -76,10 +76,14 @@ typedef struct bc_opts {
     float pull_beta;        /* pull -> push when frontier nodes < n / pull_beta          */
     int32_t slots;          /* BC_MODE_BATCHED: concurrent workgroup batches (0 = auto)  */
     int32_t seed_batches;   /* BC_MODE_BATCHED: level-synchronous batches first (-1 = auto) */
-    int32_t block;          /* reserved, 0                                               */
+    int32_t chunk;          /* BC_MODE_BATCHED: consecutive batches a workgroup claims at
+                               a time (0 = 1)                                            */
     int32_t defer_arcs;     /* BC_MODE_BATCHED: a source whose next level scans more arcs
                                than this leaves its workgroup batch and is re-run by the
                                level-synchronous kernels afterwards (0 = 65536, -1 = never) */
+    int32_t lds_tables;     /* BC_MODE_BATCHED, W = 64: keep small batch states in LDS
+                               hash tables (0 = yes, -1 = always use the node records)   */
+    int32_t reserved;
 } bc_opts;
 
 typedef struct bc_stats {

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                 ("width", ctypes.c_int32), ("perm", ctypes.c_void_p), ("scores", ctypes.c_void_p),
                 ("pull_alpha", ctypes.c_float), ("pull_beta", ctypes.c_float),
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("defer_arcs", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("defer_arcs", ctypes.c_int32),
+                ("lds_tables", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -198,7 +199,8 @@ class Graph:
 
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
              pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
-             seed_batches: int = -1, defer_arcs: int = 0) -> TopK:
+             seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
+             lds_tables: bool = True) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
         order: None (automatic), "degree", "grouped", or a permutation of
@@ -215,6 +217,8 @@ class Graph:
         o.slots = int(slots)
         o.seed_batches = int(seed_batches)
         o.defer_arcs = int(defer_arcs)
+        o.chunk = int(chunk)
+        o.lds_tables = 0 if lds_tables else -1
         keep = []
         if isinstance(order, str):
             o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "auto": ORDER_AUTO}[order]

@@ -53,7 +53,7 @@ void bc_opts_default(bc_opts* o) {
     o->pull_beta = 24.f;
     o->slots = 0;
     o->seed_batches = -1;
-    o->block = 0;
+    o->chunk = 0;
     o->defer_arcs = 0;
 }
 

@@ -246,14 +246,42 @@ __device__ inline void count_new(uint64_t bits, int j, uint32_t deg, uint32_t* c
     }
 }
 
-// Arc u->w for the live source bits m of u: OR the unseen ones into nxt[w],
-// count the bits this thread sets first, report whether w is new this level.
+// Wave-aggregated form of count_new: every lane holds the bits it set first
+// (word j) and the degree of its target; lane b adds the column sums of bit b
+// with one atomic, so lanes sharing a source never contend.  Wave-uniform call.
+__device__ inline void wave_count(uint64_t bits, uint32_t deg, int j, uint32_t* cg, unsigned long long* ct) {
+    unsigned long long lanes = __ballot(bits != 0ull);
+    if (!lanes) return;
+    const uint32_t lane = lane_id();
+    const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
+    uint32_t g = 0;
+    unsigned long long t = 0;
+    while (lanes) {
+        const int i = __ffsll((long long)lanes) - 1;
+        lanes &= lanes - 1ull;
+        const uint32_t xl = __builtin_amdgcn_readlane(lo, i);
+        const uint32_t xh = __builtin_amdgcn_readlane(hi, i);
+        const uint32_t dv = __builtin_amdgcn_readlane(deg, i);
+        const uint32_t mine = lane < 32 ? (xl >> lane) & 1u : (xh >> (lane - 32)) & 1u;
+        g += mine;
+        t += mine ? dv : 0u;
+    }
+    if (g) {
+        atomicAdd(&cg[j * 64 + lane], g);
+        atomicAdd(&ct[j * 64 + lane], t);
+    }
+}
+
+// Arc u->w for the live source bits m of u: OR the unseen ones into nxt[w];
+// nb_first[j] receives the bits this thread set first and *deg the degree
+// of w (for counting).  Returns whether w is new this level.
 template <int WW>
-__device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp, uint32_t* cg,
-                             unsigned long long* ct) {
+__device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp, uint64_t* nb_first, uint32_t* degw) {
     using Lo = Layout<WW>;
     uint64_t nb[WW];
     uint64_t any = 0;
+#pragma unroll
+    for (int j = 0; j < WW; ++j) nb_first[j] = 0;
     if constexpr (WW == 1) {
         // seen and nxt share one 16-byte load; a stale nxt only costs an extra atomic
         const ulonglong2 sn = *reinterpret_cast<const ulonglong2*>(rec);
@@ -267,24 +295,25 @@ __device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp, u
         }
     }
     if (!any) return false;
-    const uint32_t deg = (uint32_t)(rec[Lo::META] >> 32);
+    *degw = (uint32_t)(rec[Lo::META] >> 32);
     if constexpr (WW == 1) {
         const uint64_t old = atomicOr((unsigned long long*)&rec[Lo::NXT], (unsigned long long)nb[0]);
-        count_new(nb[0] & ~old, 0, deg, cg, ct);
+        nb_first[0] = nb[0] & ~old;
         return old == 0ull;
     } else {
 #pragma unroll
         for (int j = 0; j < WW; ++j) {
             if (!nb[j]) continue;
             const uint64_t old = atomicOr((unsigned long long*)&rec[Lo::NXT + j], (unsigned long long)nb[j]);
-            count_new(nb[j] & ~old, j, deg, cg, ct);
+            nb_first[j] = nb[j] & ~old;
         }
         return atomicMax(reinterpret_cast<uint32_t*>(&rec[Lo::META]), stamp) < stamp;
     }
 }
 
-// Block-wide exclusive scan of one uint32 per thread (kBlk threads).
-__device__ inline uint32_t block_exscan(uint32_t v, uint32_t* tmp /* kBlk/64 + 1 */, uint32_t* total) {
+// Block-wide exclusive scan of one uint32 per thread (B threads).
+template <int B = kBlk>
+__device__ inline uint32_t block_exscan(uint32_t v, uint32_t* tmp /* B/64 + 1 */, uint32_t* total) {
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / 64;
     uint32_t x = v;
@@ -297,35 +326,35 @@ __device__ inline uint32_t block_exscan(uint32_t v, uint32_t* tmp /* kBlk/64 + 1
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
-        for (int i = 0; i < kBlk / 64; ++i) {
+        for (int i = 0; i < B / 64; ++i) {
             uint32_t t = tmp[i];
             tmp[i] = acc;
             acc += t;
         }
-        tmp[kBlk / 64] = acc;
+        tmp[B / 64] = acc;
     }
     __syncthreads();
     uint32_t r = tmp[wave] + x - v;
-    *total = tmp[kBlk / 64];
+    *total = tmp[B / 64];
     __syncthreads();
     return r;
 }
 
-template <int WW>
+template <int WW, int B = kBlk>
 struct LdsExpand {
-    int32_t beg[kBlk];
-    uint32_t off[kBlk + 1];
-    uint64_t m[kBlk * WW];
-    uint32_t scan[kBlk / 64 + 1];
+    int32_t beg[B];
+    uint32_t off[B + 1];
+    uint64_t m[B * WW];
+    uint32_t scan[B / 64 + 1];
     uint32_t chunk;
 };
 
 // Expand entries [e0, e1) (at most kBlk) of the frontier list F: every arc of
 // every entry with a live bit, balanced over the workgroup by a scan of the
 // degrees.  Nodes reached for the first time this level go to N once.
-template <int WW>
+template <int WW, int B = kBlk>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
-                               const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW>& L,
+                               const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW, B>& L,
                                uint32_t* cg, unsigned long long* ct, unsigned long long* arcs,
                                unsigned long long* entries) {
     using Lo = Layout<WW>;
@@ -356,19 +385,32 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
 #pragma unroll
     for (int j = 0; j < WW; ++j) L.m[tid * WW + j] = m[j];
     uint32_t total;
-    const uint32_t off = block_exscan(deg, L.scan, &total);
+    const uint32_t off = block_exscan<B>(deg, L.scan, &total);
     L.off[tid] = off;
     __syncthreads();
-    for (uint32_t a = tid; a < total; a += kBlk) {
-        // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
-        uint32_t lo = 0, hi = kBlk;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (L.off[mid] <= a) lo = mid + 1; else hi = mid;
+    for (uint32_t a0 = 0; a0 < total; a0 += B) {
+        const uint32_t a = a0 + tid;
+        bool app = false;
+        int32_t w = 0;
+        uint64_t nbf[WW];
+        uint32_t dw = 0;
+#pragma unroll
+        for (int j = 0; j < WW; ++j) nbf[j] = 0;
+        if (a < total) {
+            // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
+            uint32_t lo = 0, hi = B;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (L.off[mid] <= a) lo = mid + 1; else hi = mid;
+            }
+            const uint32_t i = lo - 1;
+            w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
+            app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp, nbf, &dw);
         }
-        const uint32_t i = lo - 1;
-        const int32_t w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
-        const bool app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp, cg, ct);
+        if (cg) {
+#pragma unroll
+            for (int j = 0; j < WW; ++j) wave_count(nbf[j], dw, j, cg, ct);
+        }
         append_if(app, w, N, nctr);
     }
     if (tid == 0) *arcs += total;
@@ -735,6 +777,10 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Src
     for (uint32_t base = blockIdx.x * kBlk; base < (uint32_t)G.n; base += stride) {
         const int32_t w = (int32_t)(base + tid);
         bool app = false;
+        uint64_t pbits[WW];
+        uint32_t pdeg = 0;
+#pragma unroll
+        for (int j = 0; j < WW; ++j) pbits[j] = 0;
         if (w < G.n) {
             uint64_t* rec = &P.ns[(size_t)w * Lo::SW];
             uint64_t unv[WW], acc[WW];
@@ -762,16 +808,18 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Src
 #pragma unroll
                 for (int j = 0; j < WW; ++j) got |= acc[j];
                 if (got) {
-                    const uint32_t deg = (uint32_t)(rec[Lo::META] >> 32);
+                    pdeg = (uint32_t)(rec[Lo::META] >> 32);
 #pragma unroll
                     for (int j = 0; j < WW; ++j) {
                         rec[Lo::NXT + j] = acc[j];
-                        count_new(acc[j], j, deg, cg, ct);
+                        pbits[j] = acc[j];
                     }
                     app = true;
                 }
             }
         }
+#pragma unroll
+        for (int j = 0; j < WW; ++j) wave_count(pbits[j], pdeg, j, cg, ct);
         append_if(app, w, P.qb, &C->nlen);
     }
     if (scanned) atomicAdd(&st->node_arcs, scanned);
@@ -852,15 +900,15 @@ __global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
 // batch indices from a device counter, with every level inside the workgroup.
 template <int WW>
 __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* order, int W, uint32_t nbatches,
-                                                 uint32_t* next_batch, SlotPtrs base, uint32_t* slot_stamp,
-                                                 TopKDev T, QStats* st, DeferList D) {
+                                                 uint32_t* next_batch, uint32_t chunk, SlotPtrs base,
+                                                 uint32_t* slot_stamp, TopKDev T, QStats* st, DeferList D) {
     using Lo = Layout<WW>;
     __shared__ LdsExpand<WW> LE;
     __shared__ SrcState S[kBlk];
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
     __shared__ CutLds CL;
-    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b;
+    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b, s_next, s_end;
     __shared__ uint64_t s_act[4];
     __shared__ unsigned long long s_arcs, s_narcs, s_ent;
     const int tid = threadIdx.x;
@@ -877,9 +925,18 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
     if (tid == 0) {
         s_narcs = 0;
         s_ent = 0;
+        s_next = s_end = 0;
     }
     for (;;) {
-        if (tid == 0) s_b = atomicAdd(next_batch, 1u);
+        // claim `chunk` consecutive batches at a time: neighbouring batches of
+        // the grouped order share neighbourhoods, whose records then stay cached
+        if (tid == 0) {
+            if (s_next >= s_end) {
+                s_next = atomicAdd(next_batch, chunk);
+                s_end = s_next + chunk;
+            }
+            s_b = s_next++;
+        }
         __syncthreads();
         const uint32_t b = s_b;
         __syncthreads();
@@ -944,6 +1001,515 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
         if (s_ent) atomicAdd(&st->frontier_entries, s_ent);
         for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], ticks[i]);
         slot_stamp[slot] = stamp;
+    }
+}
+
+// ------------------------------------------- LDS-resident batched kernel
+//
+// For W = 64 most batches end after two levels, and the state of such a
+// search is small: the nodes of the levels built so far (a few hundred) and
+// the distinct nodes of the level being counted (~10^4).  This kernel keeps
+// both in LDS hash tables, so that the only global traffic of a level is the
+// adjacency lists it scans:
+//   H_seen  node -> seen, cur, next-cur masks of the levels built so far
+//   H_next  node -> mask of the level being counted (dedup of arc targets)
+// A level whose arc count T exceeds the H_next capacity is counted in P
+// passes, pass p taking the targets w with part(w) = p.  After the cut step
+// the live bits of the level are built into H_seen by the same passes.  When
+// the state would outgrow LDS (P too large, or H_seen too small for the new
+// level) the batch moves to the global node records at a level boundary and
+// continues with the global level step.
+
+constexpr int kCapN = 8192;       // H_next entries
+constexpr int kCapNLog = 13;
+constexpr int kCapS = 1024;       // H_seen entries
+constexpr int kCapSLog = 10;
+constexpr uint32_t kPassCap = 4900;   // arcs per counting pass (H_next load <= 0.6)
+constexpr uint32_t kSeenCap = 700;    // H_seen entries allowed after a build (load <= 0.68)
+constexpr uint32_t kPassMax = 8;
+
+struct LdsTab {
+    int32_t nkey[kCapN];
+    uint64_t nmask[kCapN];
+    int32_t skey[kCapS];
+    uint64_t sseen[kCapS], scur[kCapS], sncur[kCapS];
+    int32_t fl[2][kCapS];   // frontier lists: slots of H_seen
+    uint32_t nins, sfill, flen2, over;
+    unsigned long long tsum;
+};
+
+__device__ inline uint32_t hmix(int32_t w) { return (uint32_t)w * 2654435761u; }
+__device__ inline uint32_t hpart(int32_t w, uint32_t P) { return (((uint32_t)w * 0x85EBCA77u) >> 8) % P; }
+
+__device__ inline int32_t lds_ld(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// seen mask of w (0 when absent); H_seen is read-only while this runs
+__device__ inline uint64_t tab_seen(const LdsTab& L, int32_t w) {
+    uint32_t i = hmix(w) >> (32 - kCapSLog);
+    for (int probe = 0; probe < kCapS; ++probe) {
+        const int32_t k = L.skey[i];
+        if (k == w) return L.sseen[i];
+        if (k < 0) return 0;
+        i = (i + 1) & (kCapS - 1);
+    }
+    return 0;
+}
+
+// slot of w in H_seen, inserting it if absent (-1 when full)
+__device__ inline int tab_seen_claim(LdsTab& L, int32_t w) {
+    uint32_t i = hmix(w) >> (32 - kCapSLog);
+    for (int probe = 0; probe < kCapS; ++probe) {
+        const int32_t k = lds_ld(&L.skey[i]);
+        if (k == w) return (int)i;
+        if (k < 0) {
+            const int32_t prev = atomicCAS(&L.skey[i], -1, w);
+            if (prev < 0) {
+                atomicAdd(&L.sfill, 1u);
+                return (int)i;
+            }
+            if (prev == w) return (int)i;
+        }
+        i = (i + 1) & (kCapS - 1);
+    }
+    return -1;
+}
+
+// slot of w in H_next, inserting it if absent (-1 when full)
+__device__ inline int tab_next_claim(LdsTab& L, int32_t w) {
+    uint32_t i = hmix(w) >> (32 - kCapNLog);
+    for (int probe = 0; probe < kCapN; ++probe) {
+        const int32_t k = lds_ld(&L.nkey[i]);
+        if (k == w) return (int)i;
+        if (k < 0) {
+            const int32_t prev = atomicCAS(&L.nkey[i], -1, w);
+            if (prev < 0) {
+                atomicAdd(&L.nins, 1u);
+                return (int)i;
+            }
+            if (prev == w) return (int)i;
+        }
+        i = (i + 1) & (kCapN - 1);
+    }
+    return -1;
+}
+
+// Block-wide inclusive max-scan of one int32 per thread (B threads).
+template <int B>
+__device__ inline int32_t block_incl_max(int32_t v, int32_t* tmp /* B/64 */) {
+    const int lane = (int)lane_id();
+    const int wave = threadIdx.x / 64;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o);
+        if (lane >= o) x = max(x, y);
+    }
+    if (lane == 63) tmp[wave] = x;
+    __syncthreads();
+    int32_t pre = -1;
+    for (int i = 0; i < wave; ++i) pre = max(pre, tmp[i]);
+    __syncthreads();
+    return max(x, pre);
+}
+
+constexpr int kLdsBlk = 1024;  // one workgroup per CU holds the tables; 16 waves share them
+
+// Scratch of one pass: per frontier entry its first arc position, row start
+// and live mask, and the owner marks of one window of arc positions.
+struct PassScratch {
+    uint32_t eoff[kLdsBlk];
+    int32_t ebeg[kLdsBlk];
+    uint64_t em[kLdsBlk];
+    int32_t own[kLdsBlk];
+    int32_t scan[kLdsBlk / 64];
+    uint32_t uscan[kLdsBlk / 64 + 1];
+};
+
+// Target w of an arc from a frontier entry with live bits m (one pass):
+// returns the bits this thread set first in H_next (0 if none).
+__device__ inline uint64_t tab_visit(LdsTab& L, int32_t w, uint64_t m, uint32_t P, uint32_t p) {
+    if (P > 1 && hpart(w, P) != p) return 0;
+    const uint64_t nb = m & ~tab_seen(L, w);
+    if (!nb) return 0;
+    const int slot = tab_next_claim(L, w);
+    if (slot < 0) {
+        L.over = 1u;
+        return 0;
+    }
+    const uint64_t old = atomicOr((unsigned long long*)&L.nmask[slot], (unsigned long long)nb);
+    return nb & ~old;
+}
+
+// One pass over the arcs of frontier F (slots of H_seen): targets of part p
+// whose live bits are not yet seen are ORed into H_next; with counting, the
+// bits a thread sets first add to gamma / tgamma.  Thread i holds frontier
+// entry i (flen <= kCapS <= B); the arcs are dealt out B at a time, the owner
+// entry of each arc position being the max-scan of the entries' first
+// positions within the window.
+template <bool kCount>
+__device__ void tab_pass(const DevGraph& G, LdsTab& L, const int32_t* F, uint32_t flen, uint64_t act, uint32_t P,
+                         uint32_t p, PassScratch& X, uint32_t* cg, unsigned long long* ct,
+                         unsigned long long* arcs, unsigned long long* entries) {
+    constexpr int B = kLdsBlk;
+    static_assert(kCapS <= B, "one thread per frontier entry");
+    const int tid = threadIdx.x;
+    uint32_t deg = 0;
+    int32_t beg = 0;
+    uint64_t m = 0;
+    if ((uint32_t)tid < flen) {
+        const int32_t slot = F[tid];
+        m = L.scur[slot] & act;
+        if (m) {
+            const int32_t u = L.skey[slot];
+            beg = G.rp[u];
+            deg = (uint32_t)(G.rp[u + 1] - beg);
+        }
+    }
+    if (kCount && p == 0) {
+        const unsigned long long nlive = __ballot(deg != 0);
+        if ((tid & 63) == 0 && nlive) atomicAdd(entries, (unsigned long long)__popcll(nlive));
+    }
+    uint32_t total;
+    const uint32_t off = block_exscan<B>(deg, X.uscan, &total);
+    X.eoff[tid] = off;
+    X.ebeg[tid] = beg;
+    X.em[tid] = m;
+    if (kCount && p == 0 && tid == 0) *arcs += total;
+    for (uint32_t a0 = 0; a0 < total; a0 += B) {
+        X.own[tid] = -1;
+        __syncthreads();
+        if (deg) {
+            if (off >= a0 && off < a0 + B) X.own[off - a0] = tid;
+            else if (off < a0 && off + deg > a0) X.own[0] = tid;
+        }
+        __syncthreads();
+        const int32_t i = block_incl_max<B>(X.own[tid], X.scan);
+        const uint32_t a = a0 + tid;
+        uint64_t first = 0;
+        uint32_t dw = 0;
+        if (a < total) {
+            const int32_t w = G.col[X.ebeg[i] + (int32_t)(a - X.eoff[i])];
+            first = tab_visit(L, w, X.em[i], P, p);
+            if (kCount && first) dw = G.deg[w];
+        }
+        if (kCount) wave_count(first, dw, 0, cg, ct);
+    }
+    __syncthreads();
+}
+
+// Clear H_next after a counting pass.
+template <int B>
+__device__ inline void tab_next_reset(LdsTab& L) {
+    for (int i = threadIdx.x; i < kCapN; i += B) {
+        L.nkey[i] = -1;
+        L.nmask[i] = 0;
+    }
+}
+
+// After a build pass: every H_next entry becomes (or updates) an H_seen entry
+// and joins the next frontier; H_next is cleared.
+template <int B>
+__device__ inline void tab_build_pass(LdsTab& L, int32_t* Fn) {
+    for (int i = threadIdx.x; i < kCapN; i += B) {
+        const int32_t w = L.nkey[i];
+        if (w < 0) continue;
+        const uint64_t bits = L.nmask[i];
+        L.nkey[i] = -1;
+        L.nmask[i] = 0;
+        const int s = tab_seen_claim(L, w);
+        if (s < 0) {
+            L.over = 1u;
+            continue;
+        }
+        L.sseen[s] |= bits;
+        L.sncur[s] = bits;
+        Fn[atomicAdd(&L.flen2, 1u)] = s;
+    }
+}
+
+template <int WW>
+__global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32_t* order, int W,
+                                                        uint32_t nbatches, uint32_t* next_batch, SlotPtrs base,
+                                                        TopKDev T, QStats* st, DeferList D) {
+    static_assert(WW == 1, "LDS-resident batches hold 64 sources");
+    using Lo = Layout<1>;
+    constexpr int B = kLdsBlk;
+    __shared__ LdsTab L;
+    __shared__ union {
+        LdsExpand<1, B> e;   // global-record levels
+        PassScratch x;       // LDS levels
+    } U;
+    LdsExpand<1, B>& LE = U.e;
+    PassScratch& PX = U.x;
+    __shared__ SrcState S[64];
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b, s_mode;
+    __shared__ uint64_t s_act[4];
+    __shared__ unsigned long long s_arcs, s_narcs, s_ent;
+    const int tid = threadIdx.x;
+    const size_t slot = blockIdx.x;
+    SlotPtrs P;
+    P.ns = base.ns + slot * (size_t)G.n * Lo::SW;
+    P.qa = base.qa + slot * (size_t)G.n;
+    P.qb = base.qb + slot * (size_t)G.n;
+    P.clr = base.clr + slot * (size_t)G.n;
+    unsigned long long levels = 0, batches = 0, disc = 0;
+    unsigned long long ticks[5] = {0, 0, 0, 0, 0};
+    tab_next_reset<B>(L);
+    for (int i = tid; i < kCapS; i += B) {
+        L.skey[i] = -1;
+        L.sseen[i] = L.scur[i] = L.sncur[i] = 0;
+    }
+    if (tid == 0) {
+        s_narcs = 0;
+        s_ent = 0;
+        L.nins = L.sfill = L.flen2 = L.over = 0;
+    }
+    __syncthreads();
+
+    // move the LDS state of the batch into the global node records (level
+    // boundary): seen/cur of every H_seen node, the frontier as node ids
+    auto to_global = [&](const int32_t* F, uint32_t flen) {
+        if (tid == 0) s_clen = 0;
+        __syncthreads();
+        for (int i = tid; i < kCapS; i += B) {
+            const int32_t w = L.skey[i];
+            if (w >= 0) {
+                uint64_t* rec = &P.ns[(size_t)w * Lo::SW];
+                rec[0] = L.sseen[i];
+                rec[Lo::CUR] = L.scur[i];
+            }
+            append_if(w >= 0, w, P.clr, &s_clen);
+        }
+        for (uint32_t e = tid; e < flen; e += B) P.qa[e] = L.skey[F[e]];
+        __syncthreads();
+        for (int i = tid; i < kCapS; i += B) {
+            L.skey[i] = -1;
+            L.sseen[i] = L.scur[i] = L.sncur[i] = 0;
+        }
+        if (tid == 0) {
+            L.sfill = 0;
+            s_mode = 1;
+        }
+        __syncthreads();
+    };
+
+    for (;;) {
+        if (tid == 0) s_b = atomicAdd(next_batch, 1u);
+        __syncthreads();
+        const uint32_t b = s_b;
+        __syncthreads();
+        if (b >= nbatches) break;
+        ++batches;
+        const uint64_t tb = __builtin_amdgcn_s_memrealtime();
+        // sources: level 0 in H_seen
+        if (tid == 0) {
+            s_flen = 0;
+            s_mode = 0;
+        }
+        __syncthreads();
+        if (tid < W) {
+            const int64_t i = (int64_t)b * W + tid;
+            SrcState sv;
+            sv.nd = 1;
+            sv.fd = 0;
+            sv.mvis = 0;
+            if (i < G.n) {
+                const int32_t v = order[i];
+                sv.id = v;
+                sv.x0 = G.x0[v];
+                sv.x1 = G.x1[v];
+                sv.tg = G.deg[v];
+                sv.status = sv.x0 <= 1 ? S_TRIVIAL : S_LIVE;
+                if (sv.status == S_LIVE) {
+                    const int sl = tab_seen_claim(L, v);  // <= 64 distinct sources: always fits
+                    const uint64_t bit = 1ull << tid;
+                    L.sseen[sl] = bit;
+                    L.scur[sl] = bit;
+                    L.fl[0][atomicAdd(&s_flen, 1u)] = sl;
+                }
+            } else {
+                sv.id = -1;
+                sv.x0 = sv.x1 = 0;
+                sv.tg = 0;
+                sv.status = S_EMPTY;
+            }
+            S[tid] = sv;
+        }
+        __syncthreads();
+        uint32_t live = cut_step<1>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D);
+        uint32_t flen = s_flen, d = 0, cur = 0, stamp = 0;
+        uint64_t tp = __builtin_amdgcn_s_memrealtime();
+        ticks[0] += tp - tb;
+        while (live) {
+            if (s_mode == 0) {
+                // ---------------- LDS level
+                const int32_t* F = L.fl[cur];
+                const uint64_t act = s_act[0];
+                if (tid == 0) L.tsum = 0;
+                __syncthreads();
+                unsigned long long tl = 0;
+                for (uint32_t e = tid; e < flen; e += B) {
+                    const int32_t sl = F[e];
+                    if (L.scur[sl] & act) tl += G.deg[L.skey[sl]];
+                }
+                if (tl) atomicAdd(&L.tsum, tl);
+                __syncthreads();
+                const unsigned long long Tarcs = L.tsum;
+                const uint32_t npass = (uint32_t)((Tarcs + kPassCap - 1) / kPassCap);
+                if (npass > kPassMax) {
+                    to_global(F, flen);
+                    continue;
+                }
+                const uint32_t np = npass > 0 ? npass : 1;
+                if (tid < kBlk) {
+                    cg[tid] = 0;
+                    ct[tid] = 0;
+                }
+                if (tid == 0) {
+                    L.nins = 0;
+                    L.over = 0;
+                }
+                __syncthreads();
+                uint32_t distinct = 0;
+                for (uint32_t p = 0; p < np; ++p) {
+                    tab_pass<true>(G, L, F, flen, act, np, p, PX, cg, ct, &s_narcs, &s_ent);
+                    __syncthreads();
+                    tab_next_reset<B>(L);
+                    __syncthreads();
+                }
+                distinct = L.nins;
+                if (L.over) {
+                    // a pass overflowed H_next: count this level on the global records
+                    if (tid < kBlk) {
+                        cg[tid] = 0;
+                        ct[tid] = 0;
+                    }
+                    __syncthreads();
+                    to_global(F, flen);
+                    continue;
+                }
+                disc += distinct;
+                uint64_t tq = __builtin_amdgcn_s_memrealtime();
+                ticks[1] += tq - tp;
+                tp = tq;
+                ++d;
+                ++levels;
+                live = cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
+                tq = __builtin_amdgcn_s_memrealtime();
+                ticks[2] += tq - tp;
+                tp = tq;
+                if (!live) break;
+                const uint64_t lact = s_act[0];
+                if (L.sfill + distinct > kSeenCap) {
+                    // the new level does not fit H_seen: build it on the global records
+                    to_global(F, flen);
+                    if (tid == 0) s_nlen = 0;
+                    __syncthreads();
+                    ++stamp;
+                    for (uint32_t e0 = 0; e0 < flen; e0 += B)
+                        expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
+                                          nullptr, nullptr, &s_arcs, &s_arcs);
+                    __syncthreads();
+                    const uint32_t nlen = s_nlen;
+                    clear_cur<1>(P, P.qa, flen, 0, B);
+                    if (tid == 0) s_flen = 0;
+                    __syncthreads();
+                    build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs);
+                    __syncthreads();
+                    flen = s_flen;
+                    tq = __builtin_amdgcn_s_memrealtime();
+                    ticks[3] += tq - tp;
+                    tp = tq;
+                    continue;
+                }
+                // build the live bits of the level into H_seen
+                int32_t* Fn = L.fl[cur ^ 1];
+                if (tid == 0) L.flen2 = 0;
+                __syncthreads();
+                for (uint32_t p = 0; p < np; ++p) {
+                    tab_pass<false>(G, L, F, flen, lact, np, p, PX, nullptr, nullptr, nullptr, nullptr);
+                    __syncthreads();
+                    tab_build_pass<B>(L, Fn);
+                    __syncthreads();
+                }
+                for (uint32_t e = tid; e < flen; e += B) L.scur[F[e]] = 0;
+                __syncthreads();
+                const uint32_t fl2 = L.flen2;
+                for (uint32_t e = tid; e < fl2; e += B) {
+                    const int32_t sl = Fn[e];
+                    L.scur[sl] = L.sncur[sl];
+                    L.sncur[sl] = 0;
+                }
+                __syncthreads();
+                flen = fl2;
+                cur ^= 1;
+                tq = __builtin_amdgcn_s_memrealtime();
+                ticks[3] += tq - tp;
+                tp = tq;
+            } else {
+                // ---------------- global level (state on the node records)
+                ++stamp;
+                if (tid < kBlk) {
+                    cg[tid] = 0;
+                    ct[tid] = 0;
+                }
+                if (tid == 0) s_nlen = 0;
+                __syncthreads();
+                for (uint32_t e0 = 0; e0 < flen; e0 += B)
+                    expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, cg, ct,
+                                      &s_narcs, &s_ent);
+                __syncthreads();
+                const uint32_t nlen = s_nlen;
+                disc += nlen;
+                uint64_t tq = __builtin_amdgcn_s_memrealtime();
+                ticks[1] += tq - tp;
+                tp = tq;
+                ++d;
+                ++levels;
+                live = cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
+                tq = __builtin_amdgcn_s_memrealtime();
+                ticks[2] += tq - tp;
+                tp = tq;
+                clear_cur<1>(P, P.qa, flen, 0, B);
+                if (tid == 0) s_flen = 0;
+                __syncthreads();
+                build_level<1>(P, P.qb, nlen, 0, B, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs);
+                __syncthreads();
+                flen = s_flen;
+                tq = __builtin_amdgcn_s_memrealtime();
+                ticks[3] += tq - tp;
+                tp = tq;
+            }
+        }
+        // reset the batch state: global records (when used) and the LDS tables
+        if (s_mode == 1) {
+            const uint32_t nc = s_clen;
+            for (uint32_t i = tid; i < nc; i += B) {
+                uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
+                rec[0] = 0;
+                rec[Lo::CUR] = 0;
+            }
+        }
+        for (int i = tid; i < kCapS; i += B) {
+            L.skey[i] = -1;
+            L.sseen[i] = L.scur[i] = L.sncur[i] = 0;
+        }
+        if (tid == 0) L.sfill = 0;
+        __syncthreads();
+        ticks[4] += __builtin_amdgcn_s_memrealtime() - tp;
+    }
+    if (tid == 0) {
+        atomicAdd(&st->levels, levels);
+        atomicAdd(&st->batches, batches);
+        atomicAdd(&st->discovered, disc);
+        if (s_narcs) atomicAdd(&st->node_arcs, s_narcs);
+        if (s_ent) atomicAdd(&st->frontier_entries, s_ent);
+        for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], ticks[i]);
     }
 }
 
@@ -1133,8 +1699,18 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         EventPair ev;
         BC_TRY(ev.create());
         BC_HIP(hipEventRecord(ev.a, s));
-        k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
-                                              Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
+        const uint32_t chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 1);
+        if constexpr (WW == 1) {
+            if (o.lds_tables >= 0)
+                k_batched_lds<1><<<slots, kLdsBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
+                                                           T, d_st, D);
+            else
+                k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), chunk, base,
+                                                      Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
+        } else {
+            k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), chunk, base,
+                                                  Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
+        }
         BC_HIP(hipEventRecord(ev.b, s));
         BC_HIP(hipGetLastError());
         BC_TRY(ev.ms(&tm.persistent_ms));

@@ -23,6 +23,8 @@ VARIANTS = [
     dict(mode="plain", width=64, pull_alpha=1e9, pull_beta=1e-9),  # bottom-up from level 1 on
     dict(mode="plain", width=256, pull_alpha=14.0),
     dict(mode="batched", width=64),
+    dict(mode="batched", width=64, lds_tables=False),
+    dict(mode="batched", width=64, seed_batches=0, slots=7),
     dict(mode="batched", width=128, seed_batches=0),
     dict(mode="batched", width=256, slots=3),
     dict(mode="batched", width=64, defer_arcs=1),    # nearly every source re-run level-synchronously
@@ -107,7 +109,7 @@ def test_medium_graphs(kind):
     for k in (1, 10, 100):
         ref = oracle.topk(g, k, nthreads=8)
         with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
-            for v in (VARIANTS[0], VARIANTS[4], VARIANTS[5], VARIANTS[7]):
+            for v in VARIANTS:
                 assert_same(G.topk(k, **v), ref, (kind, k, v))
 
 

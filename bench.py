@@ -42,6 +42,26 @@ def algorithmic_bytes(arcs: int, entries: int, discovered: int, W: int) -> int:
     return arcs * (4 + wb) + entries * (12 + wb) + discovered * (8 + 5 * wb)
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when there is none or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    info = json.loads(m.group(1))
+    src = os.path.join(ROOT, "paper_1507_01490_amd", "csrc", "topk.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != info.get("source_sha256_16"):
+        return None
+    return info.get("traffic_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,14 +183,16 @@ def main():
         log(f"[bench] plain: {pms:.1f} ms/step, batched speed-up {pms / ms_per_step:.2f}x")
 
     roofline = None
+    kernel = "k_batched_lds<1>" if args.width == 64 else f"k_batched<{args.width // 64}>"
     if args.mode == "batched" and agg["persistent_ms"] > 0:
         nlaunch = args.steps * len(ks)
         bytes_per_launch = algorithmic_bytes(agg["arcs"], agg["entries"], agg["disc"], args.width) / nlaunch
         avg_ms = agg["persistent_ms"] / nlaunch
         achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                        kernel="k_batched<1>", avg_launch_ms=round(avg_ms, 4),
+                        frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=measured_traffic(kernel, args.workload),
+                        kernel=kernel, avg_launch_ms=round(avg_ms, 4),
                         bytes_per_launch=int(bytes_per_launch),
                         arcs_per_launch=int(agg["arcs"] / nlaunch))
 

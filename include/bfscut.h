@@ -108,7 +108,10 @@ typedef struct bc_stats {
     double defer_ms;        /* level-synchronous re-run of deferred sources, HIP events  */
     uint64_t n_deferred;    /* sources deferred out of the persistent kernel             */
     double phase_ms[5];     /* persistent kernel, summed over its workgroups: batch set-up,
-                               level expansion, level build, cut step, mark reset        */
+                               level counting, cut step, level build, mark reset         */
+    uint64_t lds_levels;    /* persistent W = 64 levels run on the LDS tables            */
+    uint64_t record_levels; /* persistent levels run on the global node records          */
+    uint64_t spills;        /* batches moved from the LDS tables to the node records     */
 } bc_stats;
 
 /* Fill *opts with the defaults (plain mode, automatic order, W = 64, bottom-up

@@ -74,6 +74,7 @@ struct QStats {
     unsigned long long m_vis, node_arcs, levels, pull_levels, n_cut, n_done, n_trivial, batches;
     unsigned long long frontier_entries, discovered, n_deferred;
     unsigned long long phase_ticks[5];  // persistent kernel: set-up, expand, cut, build, reset (100 MHz)
+    unsigned long long lds_levels, record_levels, spills;  // LDS-table levels, node-record levels, moves
 };
 
 // Sources handed from the persistent kernel to the level-synchronous kernels
@@ -1095,35 +1096,14 @@ __device__ inline int tab_next_claim(LdsTab& L, int32_t w) {
     return -1;
 }
 
-// Block-wide inclusive max-scan of one int32 per thread (B threads).
-template <int B>
-__device__ inline int32_t block_incl_max(int32_t v, int32_t* tmp /* B/64 */) {
-    const int lane = (int)lane_id();
-    const int wave = threadIdx.x / 64;
-    int32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(x, o);
-        if (lane >= o) x = max(x, y);
-    }
-    if (lane == 63) tmp[wave] = x;
-    __syncthreads();
-    int32_t pre = -1;
-    for (int i = 0; i < wave; ++i) pre = max(pre, tmp[i]);
-    __syncthreads();
-    return max(x, pre);
-}
-
 constexpr int kLdsBlk = 1024;  // one workgroup per CU holds the tables; 16 waves share them
 
 // Scratch of one pass: per frontier entry its first arc position, row start
-// and live mask, and the owner marks of one window of arc positions.
+// and live mask.
 struct PassScratch {
     uint32_t eoff[kLdsBlk];
     int32_t ebeg[kLdsBlk];
     uint64_t em[kLdsBlk];
-    int32_t own[kLdsBlk];
-    int32_t scan[kLdsBlk / 64];
     uint32_t uscan[kLdsBlk / 64 + 1];
 };
 
@@ -1145,9 +1125,9 @@ __device__ inline uint64_t tab_visit(LdsTab& L, int32_t w, uint64_t m, uint32_t 
 // One pass over the arcs of frontier F (slots of H_seen): targets of part p
 // whose live bits are not yet seen are ORed into H_next; with counting, the
 // bits a thread sets first add to gamma / tgamma.  Thread i holds frontier
-// entry i (flen <= kCapS <= B); the arcs are dealt out B at a time, the owner
-// entry of each arc position being the max-scan of the entries' first
-// positions within the window.
+// entry i (flen <= kCapS <= B); the arcs are dealt out over the workgroup by
+// a scan of the degrees, each thread finding the owner of its arc by binary
+// search over the entries' first positions.
 template <bool kCount>
 __device__ void tab_pass(const DevGraph& G, LdsTab& L, const int32_t* F, uint32_t flen, uint64_t act, uint32_t P,
                          uint32_t p, PassScratch& X, uint32_t* cg, unsigned long long* ct,
@@ -1177,24 +1157,17 @@ __device__ void tab_pass(const DevGraph& G, LdsTab& L, const int32_t* F, uint32_
     X.ebeg[tid] = beg;
     X.em[tid] = m;
     if (kCount && p == 0 && tid == 0) *arcs += total;
-    for (uint32_t a0 = 0; a0 < total; a0 += B) {
-        X.own[tid] = -1;
-        __syncthreads();
-        if (deg) {
-            if (off >= a0 && off < a0 + B) X.own[off - a0] = tid;
-            else if (off < a0 && off + deg > a0) X.own[0] = tid;
-        }
-        __syncthreads();
-        const int32_t i = block_incl_max<B>(X.own[tid], X.scan);
-        const uint32_t a = a0 + tid;
-        uint64_t first = 0;
-        uint32_t dw = 0;
-        if (a < total) {
-            const int32_t w = G.col[X.ebeg[i] + (int32_t)(a - X.eoff[i])];
-            first = tab_visit(L, w, X.em[i], P, p);
-            if (kCount && first) dw = G.deg[w];
-        }
-        if (kCount) wave_count(first, dw, 0, cg, ct);
+    __syncthreads();
+    for (uint32_t a = tid; a < total; a += B) {
+            uint32_t lo = 0, hi = B;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (X.eoff[mid] <= a) lo = mid + 1; else hi = mid;
+            }
+            const uint32_t i = lo - 1;
+        const int32_t w = G.col[X.ebeg[i] + (int32_t)(a - X.eoff[i])];
+        const uint64_t first = tab_visit(L, w, X.em[i], P, p);
+        if (kCount && first) count_new(first, 0, G.deg[w], cg, ct);
     }
     __syncthreads();
 }
@@ -1257,7 +1230,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     P.qa = base.qa + slot * (size_t)G.n;
     P.qb = base.qb + slot * (size_t)G.n;
     P.clr = base.clr + slot * (size_t)G.n;
-    unsigned long long levels = 0, batches = 0, disc = 0;
+    unsigned long long levels = 0, batches = 0, disc = 0, lds_lv = 0, rec_lv = 0, spills = 0;
     unsigned long long ticks[5] = {0, 0, 0, 0, 0};
     tab_next_reset<B>(L);
     for (int i = tid; i < kCapS; i += B) {
@@ -1274,6 +1247,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     // move the LDS state of the batch into the global node records (level
     // boundary): seen/cur of every H_seen node, the frontier as node ids
     auto to_global = [&](const int32_t* F, uint32_t flen) {
+        ++spills;
         if (tid == 0) s_clen = 0;
         __syncthreads();
         for (int i = tid; i < kCapS; i += B) {
@@ -1394,6 +1368,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     continue;
                 }
                 disc += distinct;
+                ++lds_lv;
                 uint64_t tq = __builtin_amdgcn_s_memrealtime();
                 ticks[1] += tq - tp;
                 tp = tq;
@@ -1405,7 +1380,13 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 tp = tq;
                 if (!live) break;
                 const uint64_t lact = s_act[0];
-                if (L.sfill + distinct > kSeenCap) {
+                // nodes to build <= sum of gamma over the live sources
+                if (tid == 0) L.tsum = 0;
+                __syncthreads();
+                if (tid < 64 && ((lact >> tid) & 1ull)) atomicAdd(&L.tsum, (unsigned long long)cg[tid]);
+                __syncthreads();
+                const unsigned long long live_nodes = L.tsum;
+                if (L.sfill + live_nodes > kSeenCap) {
                     // the new level does not fit H_seen: build it on the global records
                     to_global(F, flen);
                     if (tid == 0) s_nlen = 0;
@@ -1466,6 +1447,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 __syncthreads();
                 const uint32_t nlen = s_nlen;
                 disc += nlen;
+                ++rec_lv;
                 uint64_t tq = __builtin_amdgcn_s_memrealtime();
                 ticks[1] += tq - tp;
                 tp = tq;
@@ -1510,6 +1492,9 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
         if (s_narcs) atomicAdd(&st->node_arcs, s_narcs);
         if (s_ent) atomicAdd(&st->frontier_entries, s_ent);
         for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], ticks[i]);
+        atomicAdd(&st->lds_levels, lds_lv);
+        atomicAdd(&st->record_levels, rec_lv);
+        atomicAdd(&st->spills, spills);
     }
 }
 
@@ -1862,6 +1847,9 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
         o2.defer_ms = tm.defer_ms;
         o2.n_deferred = hst.n_deferred;
         for (int i = 0; i < 5; ++i) o2.phase_ms[i] = (double)hst.phase_ticks[i] / 1e5;
+        o2.lds_levels = hst.lds_levels;
+        o2.record_levels = hst.record_levels;
+        o2.spills = hst.spills;
         std::memcpy(st_out, &o2, std::min<size_t>(sz ? sz : sizeof(bc_stats), sizeof(bc_stats)));
     }
     return BC_OK;

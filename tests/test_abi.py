@@ -48,7 +48,7 @@ def test_opts_defaults_and_version():
 def test_struct_sizes_match_header():
     # bc_opts: 4 x int32, 2 pointers, 2 floats, 4 x int32 ; bc_stats: see header
     assert ctypes.sizeof(bc.Opts) == 4 * 4 + 2 * 8 + 2 * 4 + 6 * 4
-    assert ctypes.sizeof(bc.Stats) == 8 + 7 * 8 + 4 * 8 + 5 * 8 + 2 * 8 + 5 * 8
+    assert ctypes.sizeof(bc.Stats) == 8 + 7 * 8 + 4 * 8 + 5 * 8 + 2 * 8 + 5 * 8 + 3 * 8
 
 
 def test_null_arguments_rejected_without_gpu_work():

@@ -57,7 +57,13 @@ typedef struct bc_graph bc_graph;
 #define BC_ORDER_SCORES 2    /* opts.scores: decreasing score, ties by out-degree then id        */
 #define BC_ORDER_GROUPED 3   /* decreasing out-degree; equal degrees grouped by their highest-degree
                                 neighbour (then id), so that a batch shares neighbourhoods       */
+#define BC_ORDER_LEARNED 4   /* opts.mlp: decreasing score of the order perceptron over the features
+                                of bc_graph_features (ties by out-degree, then id)               */
 #define BC_ORDER_AUTO   -1   /* BC_ORDER_GROUPED in batched mode, BC_ORDER_DEGREE in plain mode   */
+
+/* Parameters of the order perceptron 3 -> 64 -> 64 -> 1 (ReLU, fp32), one flat vector:
+ * W1[64][3] @0, b1[64] @192, W2[64][64] @256, b2[64] @4352, w3[64] @4416, b3 @4480. */
+#define BC_MLP_PARAMS 4481
 
 /* Execution mode.  Neither changes the result, only the speed. */
 #define BC_MODE_PLAIN   0    /* one batch of W sources at a time, level-synchronous
@@ -84,6 +90,7 @@ typedef struct bc_opts {
     int32_t lds_tables;     /* BC_MODE_BATCHED, W = 64: keep small batch states in LDS
                                hash tables (0 = yes, -1 = always use the node records)   */
     int32_t reserved;
+    const float* mlp;       /* BC_ORDER_LEARNED: host, BC_MLP_PARAMS floats              */
 } bc_opts;
 
 typedef struct bc_stats {
@@ -187,6 +194,80 @@ bc_status bc_graph_csr(const bc_graph* g, int32_t* row_ptr, int32_t* col);
  */
 bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uint64_t* farness,
                   uint32_t* reach, int32_t* count, bc_stats* stats);
+
+/*
+ * bc_farness_all -- exact farness and reach of every node (the textbook
+ * computation of Section 1: one breadth-first search per node, here in
+ * bit-parallel batches, with no bound and no cut).
+ *
+ *   opts     NULL for the defaults; mode, width, order and batching knobs
+ *            apply as in bc_topk (they change the speed only)
+ *   farness  host, n entries: f(v) of node v
+ *   reach    host, n entries: r(v) of node v
+ *   stats    host, optional
+ *
+ * Blocking.  Used to label training data of the order perceptron and as the
+ * baseline the pruned search is compared with.  Errors as bc_topk.
+ */
+bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, uint32_t* reach, bc_stats* stats);
+
+/*
+ * Learned source order.  Algorithm 1 returns the same top-k whatever order
+ * the sources are processed in; the order only decides how soon the k-th
+ * best value is known (Section 2.1).  The paper processes by decreasing
+ * degree; BC_ORDER_LEARNED processes by decreasing score of a perceptron
+ * trained to predict log closeness from three per-node features.  These
+ * calls expose the features and the perceptron so that it can be trained
+ * on the device.
+ */
+
+/*
+ * bc_graph_features -- per-node features of the order perceptron.
+ *
+ *   x     device, n * 3 floats, row v = (x0, x1, x2) of node v, each column
+ *         standardised over the nodes ((x - mean) / population std; 0 when
+ *         the column's integers are all equal):
+ *           x0 = log(1 + outdeg(v))
+ *           x1 = log(1 + sum of outdeg(u) over the out-arcs v -> u)
+ *           x2 = log(1 + core(v))
+ *   core  device, n uint32 (may be NULL): core(v), the largest c such that v
+ *         lies in a subgraph in which every node has >= c out-neighbours
+ *         (the k-core number of an undirected graph)
+ *
+ * Computed once per graph and cached; the call copies into the caller's
+ * arrays and returns when they are written.  Errors: BC_EINVAL, BC_EDEVICE.
+ */
+bc_status bc_graph_features(bc_graph* g, float* x, uint32_t* core);
+
+/* y[i] = perceptron(x[3i .. 3i+2]) for i < count (device pointers; params
+ * holds BC_MLP_PARAMS floats).  Asynchronous on `stream`. */
+bc_status bc_mlp_forward(const float* params, const float* x, int64_t count, float* y, void* stream);
+
+/*
+ * bc_mlp_loss_grad -- loss and gradient of the order perceptron.
+ *
+ *   loss = sum_i w[v_i] (y(x[v_i]) - t[v_i])^2 / sum_i w[v_i],  v_i = idx[i]
+ *   (or i when idx is NULL), i < count
+ *
+ *   params  device, BC_MLP_PARAMS floats
+ *   x, t, w device, rows * 3, rows, rows floats (w may be NULL: all 1)
+ *   idx     device, count int32 in [0, rows), or NULL (then count <= rows)
+ *   grad    device, BC_MLP_PARAMS floats, written
+ *   loss    host, may be NULL
+ *
+ * Blocking (synchronises `stream`).  Deterministic: tiles of 128 samples
+ * summed in a fixed order.  Errors: BC_EINVAL (an idx entry outside
+ * [0, rows), count > rows without idx), BC_ENOMEM, BC_EDEVICE.
+ */
+bc_status bc_mlp_loss_grad(const float* params, const float* x, const float* t, const float* w, int64_t rows,
+                           const int32_t* idx, int64_t count, float* grad, double* loss, void* stream);
+
+/* One Adam step (Kingma and Ba, 2015) on BC_MLP_PARAMS floats (device):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * params -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps); step >= 1.
+ * Asynchronous on `stream`. */
+bc_status bc_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                      float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -24,12 +24,16 @@ import numpy as np
 
 __all__ = ["Graph", "TopK", "Opts", "Stats", "BcError", "load_library", "closeness",
            "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES", "ORDER_GROUPED",
-           "LIB_PATH"]
+           "ORDER_LEARNED", "MLP_PARAMS", "LIB_PATH", "MLP_PATH", "default_mlp", "mlp_forward", "mlp_loss_grad",
+           "mlp_adam"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.so")
+# trained parameters of the order perceptron (written by train_order.py)
+MLP_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "order_mlp.npy")
 
 BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS = 0x1, 0x2, 0x4
-ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_AUTO = 0, 1, 2, 3, -1
+ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_AUTO = 0, 1, 2, 3, 4, -1
+MLP_PARAMS = 4481
 MODE_PLAIN, MODE_BATCHED = 0, 1
 _STATUS = {0: "BC_OK", -1: "BC_EINVAL", -2: "BC_EGRAPH", -3: "BC_ENOMEM", -4: "BC_EDEVICE",
            -5: "BC_EAGAIN", -6: "BC_ECANCELED"}
@@ -47,7 +51,7 @@ class Opts(ctypes.Structure):
                 ("pull_alpha", ctypes.c_float), ("pull_beta", ctypes.c_float),
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("defer_arcs", ctypes.c_int32),
-                ("lds_tables", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_tables", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -92,8 +96,15 @@ def load_library(path: str = LIB_PATH):
     lib.bc_graph_reach.argtypes = [P, P, P]
     lib.bc_graph_csr.argtypes = [P, P, P]
     lib.bc_topk.argtypes = [P, i32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(Stats)]
+    f32 = ctypes.c_float
+    lib.bc_farness_all.argtypes = [P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Stats)]
+    lib.bc_graph_features.argtypes = [P, P, P]
+    lib.bc_mlp_forward.argtypes = [P, P, i64, P, P]
+    lib.bc_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, i64, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.bc_mlp_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
     for name in ("bc_graph_create", "bc_graph_destroy", "bc_graph_info", "bc_graph_reach",
-                 "bc_graph_csr", "bc_topk"):
+                 "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_graph_features", "bc_mlp_forward", "bc_mlp_loss_grad",
+                 "bc_mlp_adam"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -110,6 +121,66 @@ def _ptr(a):
 
 def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
+
+
+def _dptr(t, dtype, numel=None):
+    """Device pointer of a contiguous torch CUDA tensor of `dtype` (None -> NULL)."""
+    if t is None:
+        return None
+    if not (_is_torch(t) and t.is_cuda and t.is_contiguous() and t.dtype == dtype):
+        raise TypeError(f"expected a contiguous CUDA tensor of {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_mlp() -> np.ndarray:
+    """The trained order perceptron shipped with the package (float32, MLP_PARAMS)."""
+    if not os.path.exists(MLP_PATH):
+        raise FileNotFoundError(f"{MLP_PATH} is missing: train it with `python -m paper_1507_01490_amd.train_order`")
+    p = np.load(MLP_PATH, allow_pickle=False).astype(np.float32)
+    if p.shape != (MLP_PARAMS,):
+        raise ValueError(f"{MLP_PATH} holds {p.shape}, expected ({MLP_PARAMS},)")
+    return p
+
+
+def mlp_forward(params, x):
+    """Scores y (float32 CUDA tensor, rows of x) of the order perceptron."""
+    import torch
+    n = x.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(load_library().bc_mlp_forward(_dptr(params, torch.float32, MLP_PARAMS), _dptr(x, torch.float32, 3 * n),
+                                         n, _dptr(y, torch.float32), _stream()))
+    return y
+
+
+def mlp_loss_grad(params, x, t, w=None, idx=None):
+    """(gradient tensor, loss) of sum w (y - t)^2 / sum w over rows idx (or all)."""
+    import torch
+    rows = x.shape[0]
+    count = rows if idx is None else idx.numel()
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = ctypes.c_double()
+    _check(load_library().bc_mlp_loss_grad(
+        _dptr(params, torch.float32, MLP_PARAMS), _dptr(x, torch.float32, 3 * rows), _dptr(t, torch.float32, rows),
+        _dptr(w, torch.float32, rows), rows, _dptr(idx, torch.int32), count, _dptr(grad, torch.float32),
+        ctypes.byref(loss), _stream()))
+    return grad, loss.value
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8):
+    """One Adam step on params (in place; m, v are the moment tensors)."""
+    import torch
+    f = torch.float32
+    _check(load_library().bc_mlp_adam(_dptr(params, f, MLP_PARAMS), _dptr(grad, f, MLP_PARAMS),
+                                      _dptr(m, f, MLP_PARAMS), _dptr(v, f, MLP_PARAMS), int(step), float(lr),
+                                      float(beta1), float(beta2), float(eps), _stream()))
 
 
 def closeness(r, f, n: int) -> np.ndarray:
@@ -199,20 +270,24 @@ class Graph:
         _check(load_library().bc_graph_csr(self._h, _ptr(rp), _ptr(col)))
         return rp, col[:self.m]
 
-    def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
-             pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
-             seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
-             lds_tables: bool = True) -> TopK:
-        """The k nodes of largest closeness: ids, exact farness, exact reach.
+    def features(self):
+        """(x, core): standardised order features (float32 CUDA tensor n x 3)
+        and core numbers (int32 CUDA tensor, values of the uint32 array)."""
+        import torch
+        x = torch.empty((max(self.n, 1), 3), dtype=torch.float32, device="cuda")
+        core = torch.empty(max(self.n, 1), dtype=torch.int32, device="cuda")
+        _check(load_library().bc_graph_features(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                ctypes.c_void_p(core.data_ptr())))
+        return x[:self.n], core[:self.n]
 
-        order: None (automatic), "degree", "grouped", or a permutation of
-        range(n); scores: per-node floats (decreasing score first)."""
+    def _opts(self, mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
+              lds_tables, mlp, keep):
         lib = load_library()
         o = Opts()
         lib.bc_opts_default(ctypes.byref(o))
-        o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}.get(mode, mode) if isinstance(mode, str) else int(mode)
         if isinstance(mode, str) and mode not in ("plain", "batched"):
             raise ValueError(f"unknown mode {mode!r}")
+        o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}[mode] if isinstance(mode, str) else int(mode)
         o.width = int(width)
         o.pull_alpha = float(pull_alpha)
         o.pull_beta = float(pull_beta)
@@ -221,8 +296,14 @@ class Graph:
         o.defer_arcs = int(defer_arcs)
         o.chunk = int(chunk)
         o.lds_tables = 0 if lds_tables else -1
-        keep = []
-        if isinstance(order, str):
+        if isinstance(order, str) and order == "learned":
+            prm = np.ascontiguousarray(default_mlp() if mlp is None else mlp, dtype=np.float32)
+            if prm.shape != (MLP_PARAMS,):
+                raise ValueError(f"mlp must hold {MLP_PARAMS} floats")
+            o.order = ORDER_LEARNED
+            o.mlp = prm.ctypes.data
+            keep.append(prm)
+        elif isinstance(order, str):
             o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "auto": ORDER_AUTO}[order]
         elif order is not None:
             perm = np.ascontiguousarray(order, dtype=np.int32)
@@ -238,6 +319,20 @@ class Graph:
             o.order = ORDER_SCORES
             o.scores = sc.ctypes.data
             keep.append(sc)
+        return o
+
+    def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
+             pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
+             seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
+             lds_tables: bool = True, mlp=None) -> TopK:
+        """The k nodes of largest closeness: ids, exact farness, exact reach.
+
+        order: None (automatic), "degree", "grouped", "learned" (the order
+        perceptron `mlp`, default the trained one), or a permutation of
+        range(n); scores: per-node floats (decreasing score first)."""
+        keep = []
+        o = self._opts(mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
+                       lds_tables, mlp, keep)
         kk = max(1, int(k))
         ids = np.zeros(kk, np.int32)
         far = np.zeros(kk, np.uint64)
@@ -245,7 +340,20 @@ class Graph:
         cnt = ctypes.c_int32()
         st = Stats()
         st.size = ctypes.sizeof(Stats)
-        _check(lib.bc_topk(self._h, int(k), ctypes.byref(o), _ptr(ids), _ptr(far), _ptr(rea),
-                           ctypes.byref(cnt), ctypes.byref(st)))
+        _check(load_library().bc_topk(self._h, int(k), ctypes.byref(o), _ptr(ids), _ptr(far), _ptr(rea),
+                                      ctypes.byref(cnt), ctypes.byref(st)))
         c = cnt.value
         return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
+
+    def farness_all(self, mode: str | int = "batched", width: int = 64, order=None, slots: int = 0,
+                    seed_batches: int = -1, defer_arcs: int = 0, lds_tables: bool = True):
+        """(farness, reach, stats) of every node, exactly (no cut)."""
+        keep = []
+        o = self._opts(mode, width, order, None, 14.0, 24.0, slots, seed_batches, defer_arcs, 0, lds_tables,
+                       None, keep)
+        far = np.zeros(max(self.n, 1), np.uint64)
+        rea = np.zeros(max(self.n, 1), np.uint32)
+        st = Stats()
+        st.size = ctypes.sizeof(Stats)
+        _check(load_library().bc_farness_all(self._h, ctypes.byref(o), _ptr(far), _ptr(rea), ctypes.byref(st)))
+        return far[:self.n], rea[:self.n], st.as_dict()

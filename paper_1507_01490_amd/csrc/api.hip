@@ -55,6 +55,7 @@ void bc_opts_default(bc_opts* o) {
     o->seed_batches = -1;
     o->chunk = 0;
     o->defer_arcs = 0;
+    o->mlp = nullptr;
 }
 
 bc_status bc_graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
@@ -119,6 +120,19 @@ bc_status bc_graph_csr(const bc_graph* g, int32_t* row_ptr, int32_t* col) {
     return BC_OK;
 }
 
+static bc_status copy_opts(const bc_opts* opts, bc_opts* o) {
+    bc_opts_default(o);
+    if (opts) {
+        if (opts->size < sizeof(uint32_t) || opts->size > sizeof(bc_opts)) {
+            set_error("opts.size %u not supported", opts->size);
+            return BC_EINVAL;
+        }
+        std::memcpy(o, opts, opts->size);
+        o->size = sizeof(bc_opts);
+    }
+    return BC_OK;
+}
+
 bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uint64_t* farness, uint32_t* reach,
                   int32_t* count, bc_stats* stats) {
     BC_GUARD_BEGIN
@@ -127,16 +141,64 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
     if (k <= 0) { set_error("k must be positive (got %d)", k); return BC_EINVAL; }
     if (!ids || !farness || !reach || !count) { set_error("NULL output array"); return BC_EINVAL; }
     bc_opts o;
-    bc_opts_default(&o);
-    if (opts) {
-        if (opts->size < sizeof(uint32_t) || opts->size > sizeof(bc_opts)) {
-            set_error("opts.size %u not supported", opts->size);
-            return BC_EINVAL;
-        }
-        std::memcpy(&o, opts, opts->size);
-        o.size = sizeof(bc_opts);
-    }
+    BC_TRY(copy_opts(opts, &o));
     return bc::run_topk(g, k, o, ids, farness, reach, count, stats);
+    BC_GUARD_END
+}
+
+bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, uint32_t* reach, bc_stats* stats) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (g->dg.n > 0 && (!farness || !reach)) { set_error("NULL output array"); return BC_EINVAL; }
+    bc_opts o;
+    BC_TRY(copy_opts(opts, &o));
+    return bc::run_farness_all(g, o, farness, reach, stats);
+    BC_GUARD_END
+}
+
+bc_status bc_graph_features(bc_graph* g, float* x, uint32_t* core) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (!x) { set_error("x is NULL"); return BC_EINVAL; }
+    BC_TRY(bc::graph_features(g));
+    const size_t n = (size_t)g->dg.n;
+    if (n == 0) return BC_OK;
+    BC_HIP(hipMemcpyAsync(x, g->feat.p, sizeof(float) * 3 * n, hipMemcpyDefault, g->stream));
+    if (core) BC_HIP(hipMemcpyAsync(core, g->core.p, sizeof(uint32_t) * n, hipMemcpyDefault, g->stream));
+    BC_HIP(hipStreamSynchronize(g->stream));
+    return BC_OK;
+    BC_GUARD_END
+}
+
+bc_status bc_mlp_forward(const float* params, const float* x, int64_t count, float* y, void* stream) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (count < 0) { set_error("negative count"); return BC_EINVAL; }
+    if (count > 0 && (!params || !x || !y)) { set_error("NULL pointer"); return BC_EINVAL; }
+    return bc::mlp_forward(params, x, count, y, (hipStream_t)stream);
+    BC_GUARD_END
+}
+
+bc_status bc_mlp_loss_grad(const float* params, const float* x, const float* t, const float* w, int64_t rows,
+                           const int32_t* idx, int64_t count, float* grad, double* loss, void* stream) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (count < 0 || rows < 0) { set_error("negative size"); return BC_EINVAL; }
+    if (!params || !grad || (count > 0 && (!x || !t))) { set_error("NULL pointer"); return BC_EINVAL; }
+    return bc::mlp_loss_grad(params, x, t, w, rows, idx, count, grad, loss, (hipStream_t)stream);
+    BC_GUARD_END
+}
+
+bc_status bc_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                      float beta2, float eps, void* stream) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!params || !grad || !m || !v) { set_error("NULL pointer"); return BC_EINVAL; }
+    if (step < 1) { set_error("step must be >= 1"); return BC_EINVAL; }
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f)) { set_error("betas outside [0, 1)"); return BC_EINVAL; }
+    return bc::mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
     BC_GUARD_END
 }
 

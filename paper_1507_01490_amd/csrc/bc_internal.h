@@ -105,6 +105,9 @@ struct bc_graph {
     bool have_order_deg = false;
     bc::DevBuf order_grp;  // cached grouped degree order
     bool have_order_grp = false;
+    bc::DevBuf feat, core;  // learned-order features (n x 3 float) and core numbers, built on first use
+    bool have_feat = false;
+    int core_sweeps = 0;
     hipStream_t stream = nullptr;
     double preprocess_ms = 0.0;
     int device = 0;
@@ -124,11 +127,21 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp, cons
 // given permutation, or decreasing score (ties by degree, then id).
 bc_status order_by_degree(bc_graph* g, int32_t* d_order);
 bc_status order_grouped(bc_graph* g, int32_t* d_order);
-bc_status order_by_scores(bc_graph* g, const float* h_scores, int32_t* d_order);
+bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order);
 bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order);
+
+// Learned order (learned.hip): features cached in g->feat / g->core; the
+// perceptron's forward pass, loss gradient and Adam step.
+bc_status graph_features(bc_graph* g);
+bc_status mlp_forward(const float* params, const float* x, int64_t count, float* y, hipStream_t s);
+bc_status mlp_loss_grad(const float* params, const float* x, const float* t, const float* w, int64_t rows,
+                        const int32_t* idx, int64_t count, float* grad, double* loss, hipStream_t s);
+bc_status mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                   float beta2, float eps, hipStream_t s);
 
 // Top-k drivers (topk.hip).
 bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness,
                    uint32_t* reach, int32_t* count, bc_stats* st);
+bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st);
 
 }  // namespace bc

@@ -221,6 +221,7 @@ __global__ void k_score_keys(int32_t n, const float* __restrict__ s, const int32
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         uint32_t b = __float_as_uint(s[order[i]]);
+        if (b == 0x80000000u) b = 0u;  // -0 ranks with +0
         uint32_t asc = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // monotone in the float
         key[i] = ~asc;
     }
@@ -407,7 +408,7 @@ bc_status order_grouped(bc_graph* g, int32_t* d_order) {
     return BC_OK;
 }
 
-bc_status order_by_scores(bc_graph* g, const float* h_scores, int32_t* d_order) {
+bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
     hipStream_t s = g->stream;
@@ -417,7 +418,8 @@ bc_status order_by_scores(bc_graph* g, const float* h_scores, int32_t* d_order) 
     BC_TRY(key0.alloc(sizeof(uint32_t) * (size_t)n));
     BC_TRY(key1.alloc(sizeof(uint32_t) * (size_t)n));
     BC_TRY(val1.alloc(sizeof(int32_t) * (size_t)n));
-    BC_HIP(hipMemcpyAsync(sc.p, h_scores, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(sc.p, scores, sizeof(float) * (size_t)n,
+                          scores_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     k_score_keys<<<grid_for(n), kBlk, 0, s>>>(n, sc.as<float>(), d_order, key0.as<uint32_t>());
     // radix sort is stable: equal scores keep the degree order
     BC_TRY(cub_call([&](void* t, size_t& b) {

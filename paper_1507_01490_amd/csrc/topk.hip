@@ -92,6 +92,10 @@ struct TopKDev {
     uint32_t* seq;
     Rec* list;
     ThRec* ring;
+    // every-node mode (no top-k list, no threshold): completed sources write
+    // their exact farness and reach here, indexed by node id
+    uint64_t* all_f;
+    uint32_t* all_r;
 };
 
 // Level-synchronous control block (device memory) of the plain slot.
@@ -531,7 +535,23 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
     if (tid == 0) {
         uint32_t nd = 0, nt = 0;
         unsigned long long mv = 0;
-        if (any) {
+        if (any && T.all_f) {
+            for (int j = 0; j < W; ++j) {
+                if (!s_flags[j]) continue;
+                const SrcState& s = S[j];
+                const bool triv = s.status == S_TRIVIAL;
+                T.all_f[s.id] = triv ? 0 : s.fd;
+                T.all_r[s.id] = triv ? 1u : (uint32_t)s.nd;
+                if (triv) ++nt;
+                else {
+                    ++nd;
+                    mv += s.mvis;
+                }
+            }
+            if (nd) atomicAdd(&st->n_done, (unsigned long long)nd);
+            if (nt) atomicAdd(&st->n_trivial, (unsigned long long)nt);
+            if (mv) atomicAdd(&st->m_vis, mv);
+        } else if (any) {
             if (locked) lock_acquire(T.lock);
             for (int j = 0; j < W; ++j) {
                 if (!s_flags[j]) continue;
@@ -1714,9 +1734,18 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
 
 }  // namespace
 
-bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness, uint32_t* reach,
-                   int32_t* count, bc_stats* st_out) {
+namespace {
+
+// Top-k query, or (all_f != nullptr) the exact farness and reach of every
+// node: the same batches with no list and no threshold, so nothing is cut.
+bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* farness, uint32_t* reach,
+                    int32_t* count, bc_stats* st_out, uint64_t* all_f, uint32_t* all_r) {
     auto t0 = std::chrono::steady_clock::now();
+    const bool all = all_f != nullptr;
+    if (all) {
+        k = g->dg.n;
+        if (o.seed_batches < 0) o.seed_batches = 0;  // no threshold to seed
+    }
     const int32_t n = g->dg.n;
     hipStream_t s = g->stream;
     const int W = o.width;
@@ -1747,17 +1776,33 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
             BC_TRY(order_given(g, o.perm, d_order));
         } else if (ord == BC_ORDER_SCORES) {
             if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
-            BC_TRY(order_by_scores(g, o.scores, d_order));
+            BC_TRY(order_by_scores(g, o.scores, false, d_order));
+        } else if (ord == BC_ORDER_LEARNED) {
+            if (!o.mlp) { set_error("BC_ORDER_LEARNED needs opts.mlp"); return BC_EINVAL; }
+            BC_TRY(graph_features(g));
+            DevBuf prm, sc;
+            BC_TRY(prm.alloc(sizeof(float) * BC_MLP_PARAMS));
+            BC_TRY(sc.alloc(sizeof(float) * (size_t)n));
+            BC_HIP(hipMemcpyAsync(prm.p, o.mlp, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
+            BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
+            BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order));
         } else {
             set_error("unknown order %d", o.order);
             return BC_EINVAL;
         }
-        // top-k list: cnt, lock, seq (16 B header) + k records; ring of n + 1 records
+        // top-k list: cnt, lock, seq (16 B header) + k records; ring of n + 1
+        // records (every-node mode: only the header, and the per-node outputs)
         const size_t hdr = 64;
-        BC_TRY(B.topk.alloc(hdr + sizeof(Rec) * (size_t)kk));
-        BC_TRY(B.ring.alloc(sizeof(ThRec) * ((size_t)n + 1)));
+        const size_t nrec = all ? 0 : (size_t)kk;
+        BC_TRY(B.topk.alloc(hdr + sizeof(Rec) * nrec));
+        BC_TRY(B.ring.alloc(sizeof(ThRec) * (all ? 1 : (size_t)n + 1)));
         BC_TRY(B.stats.alloc(sizeof(QStats)));
-        BC_HIP(hipMemsetAsync(B.topk.p, 0, hdr + sizeof(Rec) * (size_t)kk, s));
+        DevBuf allf, allr;
+        if (all) {
+            BC_TRY(allf.alloc(sizeof(uint64_t) * (size_t)n));
+            BC_TRY(allr.alloc(sizeof(uint32_t) * (size_t)n));
+        }
+        BC_HIP(hipMemsetAsync(B.topk.p, 0, hdr + sizeof(Rec) * nrec, s));
         BC_HIP(hipMemsetAsync(B.stats.p, 0, sizeof(QStats), s));
         TopKDev T;
         T.k = kk;
@@ -1767,6 +1812,8 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
         T.seq = (uint32_t*)(hb + 8);
         T.list = (Rec*)(hb + hdr);
         T.ring = B.ring.as<ThRec>();
+        T.all_f = all ? allf.as<uint64_t>() : nullptr;
+        T.all_r = all ? allr.as<uint32_t>() : nullptr;
         QStats* d_st = B.stats.as<QStats>();
         // the graph's cached workspace, or a private one when another query holds it
         std::unique_ptr<Workspace> own;
@@ -1803,13 +1850,23 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
             if (own == nullptr) g->ws.reset();
             return rs;
         }
+        if (all) {
+            BC_HIP(hipMemcpyAsync(all_f, allf.p, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+            BC_HIP(hipMemcpyAsync(all_r, allr.p, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+        }
         int32_t cnt = 0;
-        std::vector<Rec> recs((size_t)kk);
+        std::vector<Rec> recs(nrec);
         BC_HIP(hipMemcpyAsync(&cnt, T.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        BC_HIP(hipMemcpyAsync(recs.data(), T.list, sizeof(Rec) * (size_t)kk, hipMemcpyDeviceToHost, s));
+        if (nrec) BC_HIP(hipMemcpyAsync(recs.data(), T.list, sizeof(Rec) * nrec, hipMemcpyDeviceToHost, s));
         BC_HIP(hipMemcpyAsync(&hst, d_st, sizeof(QStats), hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
-        if (cnt != kk) {
+        if (all) {
+            if (hst.n_done + hst.n_trivial != (unsigned long long)n) {
+                set_error("internal: %llu of %d sources completed", hst.n_done + hst.n_trivial, n);
+                return BC_EDEVICE;
+            }
+            cnt = 0;
+        } else if (cnt != kk) {
             set_error("internal: top-k list holds %d of %d entries", cnt, kk);
             return BC_EDEVICE;
         }
@@ -1819,7 +1876,7 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
             farness[i] = recs[i].f;
         }
     }
-    *count = kk > 0 ? kk : 0;
+    if (count) *count = all ? n : (kk > 0 ? kk : 0);
     auto t1 = std::chrono::steady_clock::now();
     if (st_out) {
         const uint32_t sz = st_out->size;
@@ -1853,6 +1910,17 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
         std::memcpy(st_out, &o2, std::min<size_t>(sz ? sz : sizeof(bc_stats), sizeof(bc_stats)));
     }
     return BC_OK;
+}
+
+}  // namespace
+
+bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness, uint32_t* reach,
+                   int32_t* count, bc_stats* st) {
+    return run_query(g, k, o, ids, farness, reach, count, st, nullptr, nullptr);
+}
+
+bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st) {
+    return run_query(g, 0, o, nullptr, nullptr, nullptr, nullptr, st, farness, reach);
 }
 
 }  // namespace bc

@@ -4,6 +4,7 @@ that include/bfscut.h declares (no compute calls: this runs without a GPU)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -41,14 +42,31 @@ def test_opts_defaults_and_version():
     o = bc.Opts()
     lib.bc_opts_default(ctypes.byref(o))
     assert o.size == ctypes.sizeof(bc.Opts)
-    assert o.width == 64 and o.mode == bc.MODE_PLAIN and o.order == bc.ORDER_AUTO
+    assert o.width == 64 and o.mode == bc.MODE_PLAIN and o.order == bc.ORDER_AUTO and not o.mlp
     assert lib.bc_version().decode().startswith("bfscut")
 
 
-def test_struct_sizes_match_header():
-    # bc_opts: 4 x int32, 2 pointers, 2 floats, 4 x int32 ; bc_stats: see header
-    assert ctypes.sizeof(bc.Opts) == 4 * 4 + 2 * 8 + 2 * 4 + 6 * 4
-    assert ctypes.sizeof(bc.Stats) == 8 + 7 * 8 + 4 * 8 + 5 * 8 + 2 * 8 + 5 * 8 + 3 * 8
+def test_struct_layouts_match_header(tmp_path):
+    """Size and every field offset of bc_opts / bc_stats as a C compiler
+    lays them out from the header, against the binding's ctypes structs."""
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bfscut.h"', 'int main(void) {']
+    for cname, py in (("bc_opts", bc.Opts), ("bc_stats", bc.Stats)):
+        lines.append(f'printf("{cname} __sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in (("bc_opts", bc.Opts), ("bc_stats", bc.Stats)):
+        assert got[(cname, "__sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_null_arguments_rejected_without_gpu_work():

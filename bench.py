@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--order", default="auto", choices=["auto", "degree", "grouped", "learned", "learned_grouped"],
+                    help="source order of the timed mode (auto: grouped degree in batched mode)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -122,8 +124,8 @@ def main():
     del rp, col
     log(f"[bench] graph resident on GPU, pre-processing {G.preprocess_ms:.1f} ms")
 
-    def step(mode):
-        return [G.topk(k, mode=mode, width=args.width, slots=args.slots) for k in ks]
+    def step(mode, order=args.order):
+        return [G.topk(k, mode=mode, width=args.width, slots=args.slots, order=order) for k in ks]
 
     def check(results):
         if gold is None:
@@ -169,11 +171,11 @@ def main():
 
     plain = None
     if args.plain_steps > 0 and args.mode != "plain":
-        step("plain")  # plain-mode workspace already sized; one untimed pass
+        step("plain", "degree")  # plain-mode workspace already sized; one untimed pass
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            pout = step("plain")
+            pout = step("plain", "degree")
         torch.cuda.synchronize()
         pms = (time.perf_counter() - tp0) * 1e3 / args.plain_steps
         pc = check(pout)
@@ -213,7 +215,7 @@ def main():
                 warmup=args.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="int64", data="synthetic",
                 config=dict(workload=workloads.DESCRIPTION[args.workload], k=ks, mode=args.mode,
-                            width=args.width, order="degree", parity_vs_oracle=parity,
+                            width=args.width, order=args.order, parity_vs_oracle=parity,
                             work_m_vis=int(work)),
                 breakdown_ms_per_step=dict(seed=round(agg["seed_ms"] / args.steps, 3),
                                            persistent=round(agg["persistent_ms"] / args.steps, 3),

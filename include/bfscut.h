@@ -59,6 +59,9 @@ typedef struct bc_graph bc_graph;
                                 neighbour (then id), so that a batch shares neighbourhoods       */
 #define BC_ORDER_LEARNED 4   /* opts.mlp: decreasing score of the order perceptron over the features
                                 of bc_graph_features (ties by out-degree, then id)               */
+#define BC_ORDER_LEARNED_GROUPED 5 /* opts.mlp: the sources of the seed batches (ceil(k/W) batches
+                                unless opts.seed_batches says otherwise) by decreasing score, then
+                                all others in BC_ORDER_GROUPED order                               */
 #define BC_ORDER_AUTO   -1   /* BC_ORDER_GROUPED in batched mode, BC_ORDER_DEGREE in plain mode   */
 
 /* Parameters of the order perceptron 3 -> 64 -> 64 -> 1 (ReLU, fp32), one flat vector:

@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = ["Graph", "TopK", "Opts", "Stats", "BcError", "load_library", "closeness",
            "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES", "ORDER_GROUPED",
-           "ORDER_LEARNED", "MLP_PARAMS", "LIB_PATH", "MLP_PATH", "default_mlp", "mlp_forward", "mlp_loss_grad",
+           "ORDER_LEARNED", "ORDER_LEARNED_GROUPED", "MLP_PARAMS", "LIB_PATH", "MLP_PATH", "default_mlp", "mlp_forward", "mlp_loss_grad",
            "mlp_adam"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.so")
@@ -32,7 +32,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.s
 MLP_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "order_mlp.npy")
 
 BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS = 0x1, 0x2, 0x4
-ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_AUTO = 0, 1, 2, 3, 4, -1
+ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_LEARNED_GROUPED, ORDER_AUTO = \
+    0, 1, 2, 3, 4, 5, -1
 MLP_PARAMS = 4481
 MODE_PLAIN, MODE_BATCHED = 0, 1
 _STATUS = {0: "BC_OK", -1: "BC_EINVAL", -2: "BC_EGRAPH", -3: "BC_ENOMEM", -4: "BC_EDEVICE",
@@ -296,11 +297,11 @@ class Graph:
         o.defer_arcs = int(defer_arcs)
         o.chunk = int(chunk)
         o.lds_tables = 0 if lds_tables else -1
-        if isinstance(order, str) and order == "learned":
+        if isinstance(order, str) and order in ("learned", "learned_grouped"):
             prm = np.ascontiguousarray(default_mlp() if mlp is None else mlp, dtype=np.float32)
             if prm.shape != (MLP_PARAMS,):
                 raise ValueError(f"mlp must hold {MLP_PARAMS} floats")
-            o.order = ORDER_LEARNED
+            o.order = ORDER_LEARNED if order == "learned" else ORDER_LEARNED_GROUPED
             o.mlp = prm.ctypes.data
             keep.append(prm)
         elif isinstance(order, str):
@@ -328,8 +329,10 @@ class Graph:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
         order: None (automatic), "degree", "grouped", "learned" (the order
-        perceptron `mlp`, default the trained one), or a permutation of
-        range(n); scores: per-node floats (decreasing score first)."""
+        perceptron `mlp`, default the trained one), "learned_grouped" (the
+        seed-batch sources by learned score, then the grouped order), or a
+        permutation of range(n); scores: per-node floats (decreasing score
+        first)."""
         keep = []
         o = self._opts(mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
                        lds_tables, mlp, keep)

@@ -129,6 +129,7 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order);
 bc_status order_grouped(bc_graph* g, int32_t* d_order);
 bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order);
 bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order);
+bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order);
 
 // Learned order (learned.hip): features cached in g->feat / g->core; the
 // perceptron's forward pass, loss gradient and Adam step.

@@ -9,6 +9,7 @@
 //   * source orders for Algorithm 1 (decreasing degree, given, or scored).
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <chrono>
 
 #include "bc_internal.h"
@@ -227,6 +228,19 @@ __global__ void k_score_keys(int32_t n, const float* __restrict__ s, const int32
     }
 }
 
+// mark[v] = 1 for the first `head` sources of `order`
+__global__ void k_mark_head(int32_t head, const int32_t* __restrict__ order, uint8_t* __restrict__ mark) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < head; i += stride) mark[order[i]] = 1;
+}
+
+// keep[i] = the i-th source of `order` is not marked
+__global__ void k_keep_unmarked(int32_t n, const int32_t* __restrict__ order, const uint8_t* __restrict__ mark,
+                                uint8_t* __restrict__ keep) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) keep[i] = !mark[order[i]];
+}
+
 __global__ void k_perm_check(int32_t n, const int32_t* __restrict__ perm, uint32_t* __restrict__ seen,
                              uint32_t* err) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -428,6 +442,41 @@ bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_devic
     }, s, tmp));
     BC_HIP(hipMemcpyAsync(d_order, val1.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     BC_HIP(hipStreamSynchronize(s));
+    return BC_OK;
+}
+
+// The first `head` sources by decreasing device score, then every other
+// source in the grouped degree order (relative order kept).
+bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order) {
+    int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    head = std::min(std::max(head, 0), n);
+    hipStream_t s = g->stream;
+    DevBuf by_score, grp, mark, keep, nsel, tmp;
+    BC_TRY(by_score.alloc(sizeof(int32_t) * (size_t)n));
+    BC_TRY(grp.alloc(sizeof(int32_t) * (size_t)n));
+    BC_TRY(mark.alloc((size_t)n));
+    BC_TRY(keep.alloc((size_t)n));
+    BC_TRY(nsel.alloc(sizeof(int32_t)));
+    BC_TRY(order_by_scores(g, d_scores, true, by_score.as<int32_t>()));
+    BC_TRY(order_grouped(g, grp.as<int32_t>()));
+    BC_HIP(hipMemsetAsync(mark.p, 0, (size_t)n, s));
+    if (head > 0) {
+        k_mark_head<<<grid_for(head), kBlk, 0, s>>>(head, by_score.as<int32_t>(), mark.as<uint8_t>());
+        BC_HIP(hipMemcpyAsync(d_order, by_score.p, sizeof(int32_t) * (size_t)head, hipMemcpyDeviceToDevice, s));
+    }
+    k_keep_unmarked<<<grid_for(n), kBlk, 0, s>>>(n, grp.as<int32_t>(), mark.as<uint8_t>(), keep.as<uint8_t>());
+    BC_TRY(cub_call([&](void* t, size_t& b) {
+        return hipcub::DeviceSelect::Flagged(t, b, grp.as<int32_t>(), keep.as<uint8_t>(), d_order + head,
+                                             nsel.as<int32_t>(), n, s);
+    }, s, tmp));
+    int32_t got = 0;
+    BC_HIP(hipMemcpyAsync(&got, nsel.p, sizeof(got), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (got != n - head) {
+        set_error("internal: head/grouped order holds %d + %d of %d sources", head, got, n);
+        return BC_EDEVICE;
+    }
     return BC_OK;
 }
 

@@ -1777,15 +1777,21 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         } else if (ord == BC_ORDER_SCORES) {
             if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
             BC_TRY(order_by_scores(g, o.scores, false, d_order));
-        } else if (ord == BC_ORDER_LEARNED) {
-            if (!o.mlp) { set_error("BC_ORDER_LEARNED needs opts.mlp"); return BC_EINVAL; }
+        } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED) {
+            if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
             BC_TRY(graph_features(g));
             DevBuf prm, sc;
             BC_TRY(prm.alloc(sizeof(float) * BC_MLP_PARAMS));
             BC_TRY(sc.alloc(sizeof(float) * (size_t)n));
             BC_HIP(hipMemcpyAsync(prm.p, o.mlp, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
             BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
-            BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order));
+            if (ord == BC_ORDER_LEARNED) {
+                BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order));
+            } else {
+                const int64_t sb = o.seed_batches >= 0 ? o.seed_batches : ((int64_t)kk + W - 1) / W;
+                const int64_t head = std::min<int64_t>((int64_t)n, sb * W);
+                BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order));
+            }
         } else {
             set_error("unknown order %d", o.order);
             return BC_EINVAL;

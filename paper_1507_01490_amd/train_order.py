@@ -13,7 +13,7 @@ Features, forward pass, loss gradient and Adam all run in the library's HIP
 kernels (bc_graph_features, bc_mlp_loss_grad, bc_mlp_adam); this script only
 generates graphs and schedules the steps.
 
-    python -m paper_1507_01490_amd.train_order [--graphs 40] [--steps 3000]
+    python -m paper_1507_01490_amd.train_order [--graphs 40] [--steps 20000] [--batch 32768]
 """
 
 from __future__ import annotations
@@ -150,8 +150,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--graphs", type=int, default=40, help="training graphs per family")
     ap.add_argument("--holdout", type=int, default=6, help="held-out graphs per family")
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--batch", type=int, default=32768)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--seed", type=int, default=100)
     ap.add_argument("--out", default=bc.MLP_PATH)

@@ -215,6 +215,86 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
 bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, uint32_t* reach, bc_stats* stats);
 
 /*
+ * Serving: a queue of top-k requests over many graphs on one GPU.
+ *
+ * Graphs are registered once (host arrays, copied) and made resident on
+ * demand; resident graphs that no running request uses are evicted, least
+ * recently used first, when the memory budget needs room.  Requests start
+ * in submission order as soon as their footprint fits the free budget, on
+ * one of `lanes` concurrent HIP streams, so several requests share the GPU;
+ * each batched request's persistent kernel uses at most `slots` workgroups.
+ * A request's result is the same as that of bc_topk on the same graph with
+ * the same k (Algorithm 1 is exact for every order and threshold history).
+ */
+typedef struct bc_server bc_server;
+
+typedef struct bc_server_opts {
+    uint32_t size;          /* sizeof(bc_server_opts)                                    */
+    int32_t lanes;          /* concurrent requests (streams), 1..16 (default 4)          */
+    int32_t slots;          /* workgroups of one batched request's persistent kernel
+                               (default 64); opts.slots of a request overrides it       */
+    int32_t device;         /* HIP device (-1: the current one)                          */
+    uint64_t budget_bytes;  /* device memory for resident graphs and running requests
+                               (0: 45 % of the free memory at creation)                 */
+} bc_server_opts;
+
+typedef struct bc_request_info {
+    uint32_t size;          /* sizeof(bc_request_info)                                   */
+    int32_t lane;           /* lane the request ran on (-1: never started)               */
+    int32_t uploaded;       /* 1 if it had to make its graph resident first              */
+    int32_t reserved;
+    double submit_ms, start_ms, finish_ms;  /* since server creation (host clock)       */
+    uint64_t footprint_bytes;  /* working memory reserved for it                          */
+} bc_request_info;
+
+typedef struct bc_server_stats {
+    uint32_t size;
+    uint32_t graphs, resident_graphs, queued, running, reserved;
+    uint64_t budget_bytes, used_bytes, peak_bytes;
+    uint64_t uploads, evictions, completed, failed, canceled;
+} bc_server_stats;
+
+void bc_server_opts_default(bc_server_opts* opts);
+
+/* Start a server (its lane threads and streams).  Errors: BC_EINVAL, BC_EDEVICE. */
+bc_status bc_server_create(const bc_server_opts* opts, bc_server** out);
+
+/* Cancel queued requests, wait for running ones, free every graph and stream. */
+bc_status bc_server_destroy(bc_server* s);
+
+/* Register a graph (host arrays as for bc_graph_create, copied; not resident
+ * until a request needs it).  graph_id receives its index. */
+bc_status bc_server_add_graph(bc_server* s, int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
+                              uint32_t flags, int32_t* graph_id);
+
+/* Queue a top-k request (opts as for bc_topk; the arrays it points at are
+ * copied).  Returns at once with a ticket. */
+bc_status bc_submit(bc_server* s, int32_t graph_id, int32_t k, const bc_opts* opts, uint64_t* ticket);
+
+/* Block until the request has finished (or timeout_ms passes: BC_EAGAIN;
+ * a negative timeout waits for ever). */
+bc_status bc_wait(bc_server* s, uint64_t ticket, int32_t timeout_ms);
+
+/* BC_EAGAIN while queued or running.  Once finished: writes the results
+ * (host arrays of capacity k, as bc_topk), stats and info (both may be
+ * NULL), releases the ticket and returns BC_OK, the request's error (e.g.
+ * BC_ENOMEM when its footprint exceeds the whole budget), or BC_ECANCELED. */
+bc_status bc_poll(bc_server* s, uint64_t ticket, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count,
+                  bc_stats* stats, bc_request_info* info);
+
+/* Cancel: a queued request is dropped at once; a running one completes and
+ * its result is discarded.  BC_EINVAL if it has already finished. */
+bc_status bc_cancel(bc_server* s, uint64_t ticket);
+
+bc_status bc_server_info(bc_server* s, bc_server_stats* out);
+
+/* The admission estimate for a graph of n nodes and m arcs and one request
+ * (pure arithmetic, no device call): bytes the graph holds while resident,
+ * transient bytes of its upload, working memory of the request. */
+bc_status bc_footprint(int32_t n, int64_t m, uint32_t flags, int32_t k, const bc_opts* opts, int32_t slots,
+                       uint64_t* graph_bytes, uint64_t* upload_bytes, uint64_t* query_bytes);
+
+/*
  * Learned source order.  Algorithm 1 returns the same top-k whatever order
  * the sources are processed in; the order only decides how soon the k-th
  * best value is known (Section 2.1).  The paper processes by decreasing

@@ -24,7 +24,8 @@ import numpy as np
 
 __all__ = ["Graph", "TopK", "Opts", "Stats", "BcError", "load_library", "closeness",
            "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES", "ORDER_GROUPED",
-           "ORDER_LEARNED", "ORDER_LEARNED_GROUPED", "MLP_PARAMS", "LIB_PATH", "MLP_PATH", "default_mlp", "mlp_forward", "mlp_loss_grad",
+           "ORDER_LEARNED", "ORDER_LEARNED_GROUPED", "MLP_PARAMS", "Server", "ServerOpts", "RequestInfo",
+           "ServerStats", "footprint", "LIB_PATH", "MLP_PATH", "default_mlp", "mlp_forward", "mlp_loss_grad",
            "mlp_adam"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.so")
@@ -75,6 +76,31 @@ class Stats(ctypes.Structure):
         return d
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("lanes", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("lane", ctypes.c_int32), ("uploaded", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("finish_ms", ctypes.c_double), ("footprint_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("size", "reserved")}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("graphs", ctypes.c_uint32), ("resident_graphs", ctypes.c_uint32),
+                ("queued", ctypes.c_uint32), ("running", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("uploads", ctypes.c_uint64), ("evictions", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("canceled", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("size", "reserved")}
+
+
 _lib = None
 
 
@@ -99,12 +125,26 @@ def load_library(path: str = LIB_PATH):
     lib.bc_topk.argtypes = [P, i32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(Stats)]
     f32 = ctypes.c_float
     lib.bc_farness_all.argtypes = [P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Stats)]
+    u64 = ctypes.c_uint64
+    lib.bc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+    lib.bc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
+    lib.bc_server_destroy.argtypes = [P]
+    lib.bc_server_add_graph.argtypes = [P, i32, i64, P, P, u32, ctypes.POINTER(i32)]
+    lib.bc_submit.argtypes = [P, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(u64)]
+    lib.bc_wait.argtypes = [P, u64, i32]
+    lib.bc_poll.argtypes = [P, u64, P, P, P, P, ctypes.POINTER(Stats), ctypes.POINTER(RequestInfo)]
+    lib.bc_cancel.argtypes = [P, u64]
+    lib.bc_server_info.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.bc_footprint.argtypes = [i32, i64, u32, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(u64),
+                                 ctypes.POINTER(u64), ctypes.POINTER(u64)]
     lib.bc_graph_features.argtypes = [P, P, P]
     lib.bc_mlp_forward.argtypes = [P, P, i64, P, P]
     lib.bc_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, i64, P, ctypes.POINTER(ctypes.c_double), P]
     lib.bc_mlp_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
     for name in ("bc_graph_create", "bc_graph_destroy", "bc_graph_info", "bc_graph_reach",
-                 "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_graph_features", "bc_mlp_forward", "bc_mlp_loss_grad",
+                 "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_graph_features", "bc_server_create",
+                 "bc_server_destroy", "bc_server_add_graph", "bc_submit", "bc_wait", "bc_poll", "bc_cancel",
+                 "bc_server_info", "bc_footprint", "bc_mlp_forward", "bc_mlp_loss_grad",
                  "bc_mlp_adam"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -182,6 +222,60 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
     _check(load_library().bc_mlp_adam(_dptr(params, f, MLP_PARAMS), _dptr(grad, f, MLP_PARAMS),
                                       _dptr(m, f, MLP_PARAMS), _dptr(v, f, MLP_PARAMS), int(step), float(lr),
                                       float(beta1), float(beta2), float(eps), _stream()))
+
+
+def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=14.0, pull_beta=24.0,
+              slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None) -> Opts:
+    """bc_opts for a graph of n nodes; host arrays the options point at are
+    appended to `keep` (they must outlive the call that reads them)."""
+    lib = load_library()
+    o = Opts()
+    lib.bc_opts_default(ctypes.byref(o))
+    if isinstance(mode, str) and mode not in ("plain", "batched"):
+        raise ValueError(f"unknown mode {mode!r}")
+    o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}[mode] if isinstance(mode, str) else int(mode)
+    o.width = int(width)
+    o.pull_alpha = float(pull_alpha)
+    o.pull_beta = float(pull_beta)
+    o.slots = int(slots)
+    o.seed_batches = int(seed_batches)
+    o.defer_arcs = int(defer_arcs)
+    o.chunk = int(chunk)
+    o.lds_tables = 0 if lds_tables else -1
+    if isinstance(order, str) and order in ("learned", "learned_grouped"):
+        prm = np.ascontiguousarray(default_mlp() if mlp is None else mlp, dtype=np.float32)
+        if prm.shape != (MLP_PARAMS,):
+            raise ValueError(f"mlp must hold {MLP_PARAMS} floats")
+        o.order = ORDER_LEARNED if order == "learned" else ORDER_LEARNED_GROUPED
+        o.mlp = prm.ctypes.data
+        keep.append(prm)
+    elif isinstance(order, str):
+        o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "auto": ORDER_AUTO}[order]
+    elif order is not None:
+        perm = np.ascontiguousarray(order, dtype=np.int32)
+        if perm.shape[0] != n:
+            raise ValueError("order must hold n entries")
+        o.order = ORDER_GIVEN
+        o.perm = perm.ctypes.data
+        keep.append(perm)
+    elif scores is not None:
+        sc = np.ascontiguousarray(scores, dtype=np.float32)
+        if sc.shape[0] != n:
+            raise ValueError("scores must hold n entries")
+        o.order = ORDER_SCORES
+        o.scores = sc.ctypes.data
+        keep.append(sc)
+    return o
+
+
+def footprint(n: int, m: int, directed: bool = False, k: int = 10, slots: int = 64, **kw):
+    """(graph_bytes, upload_bytes, query_bytes): the serving admission estimate."""
+    keep = []
+    o = make_opts(n, keep, **kw)
+    g, u, q = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().bc_footprint(int(n), int(m), BC_DIRECTED if directed else 0, int(k), ctypes.byref(o),
+                                       int(slots), ctypes.byref(g), ctypes.byref(u), ctypes.byref(q)))
+    return g.value, u.value, q.value
 
 
 def closeness(r, f, n: int) -> np.ndarray:
@@ -283,44 +377,9 @@ class Graph:
 
     def _opts(self, mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
               lds_tables, mlp, keep):
-        lib = load_library()
-        o = Opts()
-        lib.bc_opts_default(ctypes.byref(o))
-        if isinstance(mode, str) and mode not in ("plain", "batched"):
-            raise ValueError(f"unknown mode {mode!r}")
-        o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}[mode] if isinstance(mode, str) else int(mode)
-        o.width = int(width)
-        o.pull_alpha = float(pull_alpha)
-        o.pull_beta = float(pull_beta)
-        o.slots = int(slots)
-        o.seed_batches = int(seed_batches)
-        o.defer_arcs = int(defer_arcs)
-        o.chunk = int(chunk)
-        o.lds_tables = 0 if lds_tables else -1
-        if isinstance(order, str) and order in ("learned", "learned_grouped"):
-            prm = np.ascontiguousarray(default_mlp() if mlp is None else mlp, dtype=np.float32)
-            if prm.shape != (MLP_PARAMS,):
-                raise ValueError(f"mlp must hold {MLP_PARAMS} floats")
-            o.order = ORDER_LEARNED if order == "learned" else ORDER_LEARNED_GROUPED
-            o.mlp = prm.ctypes.data
-            keep.append(prm)
-        elif isinstance(order, str):
-            o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "auto": ORDER_AUTO}[order]
-        elif order is not None:
-            perm = np.ascontiguousarray(order, dtype=np.int32)
-            if perm.shape[0] != self.n:
-                raise ValueError("order must hold n entries")
-            o.order = ORDER_GIVEN
-            o.perm = perm.ctypes.data
-            keep.append(perm)
-        elif scores is not None:
-            sc = np.ascontiguousarray(scores, dtype=np.float32)
-            if sc.shape[0] != self.n:
-                raise ValueError("scores must hold n entries")
-            o.order = ORDER_SCORES
-            o.scores = sc.ctypes.data
-            keep.append(sc)
-        return o
+        return make_opts(self.n, keep, mode=mode, width=width, order=order, scores=scores, pull_alpha=pull_alpha,
+                         pull_beta=pull_beta, slots=slots, seed_batches=seed_batches, defer_arcs=defer_arcs,
+                         chunk=chunk, lds_tables=lds_tables, mlp=mlp)
 
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
              pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
@@ -360,3 +419,91 @@ class Graph:
         st.size = ctypes.sizeof(Stats)
         _check(load_library().bc_farness_all(self._h, ctypes.byref(o), _ptr(far), _ptr(rea), ctypes.byref(st)))
         return far[:self.n], rea[:self.n], st.as_dict()
+
+
+class Server:
+    """Serving queue over registered graphs (bc_server_*): submit returns a
+    ticket at once; poll returns None until the result is ready."""
+
+    def __init__(self, lanes: int = 4, slots: int = 64, budget_bytes: int = 0, device: int = -1):
+        lib = load_library()
+        o = ServerOpts()
+        lib.bc_server_opts_default(ctypes.byref(o))
+        o.lanes, o.slots, o.budget_bytes, o.device = int(lanes), int(slots), int(budget_bytes), int(device)
+        h = ctypes.c_void_p()
+        _check(lib.bc_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._n = {}
+        self._k = {}
+
+    def add_graph(self, row_ptr, col, directed: bool = False, validate: bool = False) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        gid = ctypes.c_int32()
+        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0)
+        _check(load_library().bc_server_add_graph(self._h, int(rp.shape[0]) - 1, int(cl.shape[0]), _ptr(rp),
+                                                  _ptr(cl) if cl.shape[0] else None, flags, ctypes.byref(gid)))
+        self._n[gid.value] = int(rp.shape[0]) - 1
+        return gid.value
+
+    def submit(self, graph_id: int, k: int, **kw) -> int:
+        keep = []
+        o = make_opts(self._n.get(graph_id, 0), keep, **kw)
+        t = ctypes.c_uint64()
+        _check(load_library().bc_submit(self._h, int(graph_id), int(k), ctypes.byref(o), ctypes.byref(t)))
+        self._k[t.value] = max(1, int(k))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
+        st = load_library().bc_wait(self._h, ctypes.c_uint64(ticket), int(timeout_ms))
+        if st == -5:
+            return False
+        _check(st)
+        return True
+
+    def poll(self, ticket: int):
+        kk = self._k.get(ticket, 1)
+        ids = np.zeros(kk, np.int32)
+        far = np.zeros(kk, np.uint64)
+        rea = np.zeros(kk, np.uint32)
+        cnt = ctypes.c_int32()
+        st = Stats()
+        st.size = ctypes.sizeof(Stats)
+        info = RequestInfo()
+        info.size = ctypes.sizeof(RequestInfo)
+        rc = load_library().bc_poll(self._h, ctypes.c_uint64(ticket), _ptr(ids), _ptr(far), _ptr(rea),
+                                    ctypes.byref(cnt), ctypes.byref(st), ctypes.byref(info))
+        if rc == -5:
+            return None
+        self._k.pop(ticket, None)
+        _check(rc)
+        c = cnt.value
+        res = TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
+        res.info = info.as_dict()
+        return res
+
+    def cancel(self, ticket: int):
+        _check(load_library().bc_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def info(self) -> dict:
+        st = ServerStats()
+        st.size = ctypes.sizeof(ServerStats)
+        _check(load_library().bc_server_info(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().bc_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

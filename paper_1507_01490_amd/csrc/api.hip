@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "bc_internal.h"
@@ -10,6 +11,22 @@
 namespace bc {
 
 static thread_local char g_err[512];
+
+void prepare_pool() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done[dev]) return;
+    done[dev] = true;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = ~0ull;  // freed blocks stay in the pool for the next query
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+}
 
 void set_error(const char* fmt, ...) {
     va_list ap;
@@ -142,7 +159,7 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
     if (!ids || !farness || !reach || !count) { set_error("NULL output array"); return BC_EINVAL; }
     bc_opts o;
     BC_TRY(copy_opts(opts, &o));
-    return bc::run_topk(g, k, o, ids, farness, reach, count, stats);
+    return bc::run_topk(g, k, o, ids, farness, reach, count, stats, g->stream);
     BC_GUARD_END
 }
 
@@ -153,7 +170,7 @@ bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, ui
     if (g->dg.n > 0 && (!farness || !reach)) { set_error("NULL output array"); return BC_EINVAL; }
     bc_opts o;
     BC_TRY(copy_opts(opts, &o));
-    return bc::run_farness_all(g, o, farness, reach, stats);
+    return bc::run_farness_all(g, o, farness, reach, stats, g->stream);
     BC_GUARD_END
 }
 
@@ -162,7 +179,7 @@ bc_status bc_graph_features(bc_graph* g, float* x, uint32_t* core) {
     bc::g_err[0] = 0;
     if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
     if (!x) { set_error("x is NULL"); return BC_EINVAL; }
-    BC_TRY(bc::graph_features(g));
+    BC_TRY(bc::graph_features(g, g->stream));
     const size_t n = (size_t)g->dg.n;
     if (n == 0) return BC_OK;
     BC_HIP(hipMemcpyAsync(x, g->feat.p, sizeof(float) * 3 * n, hipMemcpyDefault, g->stream));

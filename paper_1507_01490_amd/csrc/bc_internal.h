@@ -51,18 +51,32 @@ struct DevGraph {
     const uint32_t* x1;
 };
 
+// Raise the release threshold of the device's default memory pool once per
+// device, so that stream-ordered frees keep their memory in the pool.
+void prepare_pool();
+
 // Device allocation owned by a graph or a query; freed in the destructor.
+// alloc() is a plain hipMalloc (graph lifetime); alloc_on(stream) is
+// stream-ordered (hipMallocAsync / hipFreeAsync on that stream), so that
+// query-lifetime buffers never wait for the whole device when released
+// while other streams are running.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool ordered = false;
+    hipStream_t stream = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (ordered) (void)hipFreeAsync(p, stream);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        ordered = false;
     }
     bc_status alloc(size_t nbytes) {
         release();
@@ -74,6 +88,21 @@ struct DevBuf {
             return BC_ENOMEM;
         }
         bytes = nbytes;
+        return BC_OK;
+    }
+    bc_status alloc_on(size_t nbytes, hipStream_t s) {
+        release();
+        prepare_pool();
+        if (nbytes == 0) nbytes = 8;
+        if (hipMallocAsync(&p, nbytes, s) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            set_error("hipMallocAsync of %zu bytes failed", nbytes);
+            return BC_ENOMEM;
+        }
+        bytes = nbytes;
+        ordered = true;
+        stream = s;
         return BC_OK;
     }
     template <class T>
@@ -94,6 +123,15 @@ struct Workspace {
     DevBuf bseen, bqa, bqb, bclr;  // persistent slots
     DevBuf srcs, ctl, nextb, slot_stamp, defer;
     bool plain_ready = false;
+    hipStream_t stream = nullptr;  // stream its buffers are ordered on
+    uint32_t* hctl = nullptr;      // pinned copy of the level-synchronous control block
+    Workspace() = default;
+    explicit Workspace(hipStream_t s) : stream(s) {}
+    Workspace(const Workspace&) = delete;
+    Workspace& operator=(const Workspace&) = delete;
+    ~Workspace() {
+        if (hctl) (void)hipHostFree(hctl);
+    }
 };
 
 }  // namespace bc
@@ -114,6 +152,7 @@ struct bc_graph {
     std::mutex ws_mu;                       // guards ws_busy
     bool ws_busy = false;
     std::unique_ptr<bc::Workspace> ws;      // cached workspace (one query at a time)
+    std::mutex cache_mu;                    // guards building the cached orders and features
 };
 
 namespace bc {
@@ -125,24 +164,33 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp, cons
 
 // Source orders (preprocess.hip): decreasing out-degree (ties by id), or a
 // given permutation, or decreasing score (ties by degree, then id).
-bc_status order_by_degree(bc_graph* g, int32_t* d_order);
-bc_status order_grouped(bc_graph* g, int32_t* d_order);
-bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order);
-bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order);
-bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order);
+// Every order call runs on stream s and returns with d_order written.
+bc_status order_by_degree(bc_graph* g, int32_t* d_order, hipStream_t s);
+bc_status order_grouped(bc_graph* g, int32_t* d_order, hipStream_t s);
+bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order, hipStream_t s);
+bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipStream_t s);
+bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order, hipStream_t s);
 
 // Learned order (learned.hip): features cached in g->feat / g->core; the
 // perceptron's forward pass, loss gradient and Adam step.
-bc_status graph_features(bc_graph* g);
+bc_status graph_features(bc_graph* g, hipStream_t s);
 bc_status mlp_forward(const float* params, const float* x, int64_t count, float* y, hipStream_t s);
 bc_status mlp_loss_grad(const float* params, const float* x, const float* t, const float* w, int64_t rows,
                         const int32_t* idx, int64_t count, float* grad, double* loss, hipStream_t s);
 bc_status mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
                    float beta2, float eps, hipStream_t s);
 
+// Admission estimate of the server (serve.hip).
+void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o, int32_t slots, uint64_t* graph_bytes,
+               uint64_t* upload_bytes, uint64_t* query_bytes);
+
 // Top-k drivers (topk.hip).
+// Queries run on stream s (the graph's stream for the blocking API, a lane
+// stream of the server); with private_ws the query never uses the graph's
+// cached workspace (its working memory is allocated and released with it).
 bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness,
-                   uint32_t* reach, int32_t* count, bc_stats* st);
-bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st);
+                   uint32_t* reach, int32_t* count, bc_stats* st, hipStream_t s, bool private_ws = false);
+bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st,
+                          hipStream_t s);
 
 }  // namespace bc

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "bc_internal.h"
 
@@ -410,10 +411,10 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 // Features of the graph into g->feat (n x 3 float) and g->core (u32), built
 // once per graph.
-bc_status graph_features(bc_graph* g) {
+bc_status graph_features(bc_graph* g, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g->cache_mu);
     if (g->have_feat) return BC_OK;
     const int32_t n = g->dg.n;
-    hipStream_t s = g->stream;
     BC_TRY(g->feat.alloc(sizeof(float) * 3 * (size_t)std::max(n, 1)));
     BC_TRY(g->core.alloc(sizeof(uint32_t) * (size_t)std::max(n, 1)));
     if (n == 0) {
@@ -421,13 +422,13 @@ bc_status graph_features(bc_graph* g) {
         return BC_OK;
     }
     DevBuf s2, mm, flag, part, stat, heavy, nheavy;
-    BC_TRY(s2.alloc(sizeof(uint64_t) * (size_t)n));
-    BC_TRY(heavy.alloc(sizeof(int32_t) * (size_t)n));
-    BC_TRY(nheavy.alloc(sizeof(uint32_t)));
-    BC_TRY(mm.alloc(sizeof(unsigned long long) * 6));
-    BC_TRY(flag.alloc(sizeof(uint32_t)));
-    BC_TRY(part.alloc(sizeof(double) * 3 * kRedBlocks));
-    BC_TRY(stat.alloc(sizeof(double) * 6));
+    BC_TRY(s2.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+    BC_TRY(heavy.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(nheavy.alloc_on(sizeof(uint32_t), s));
+    BC_TRY(mm.alloc_on(sizeof(unsigned long long) * 6, s));
+    BC_TRY(flag.alloc_on(sizeof(uint32_t), s));
+    BC_TRY(part.alloc_on(sizeof(double) * 3 * kRedBlocks, s));
+    BC_TRY(stat.alloc_on(sizeof(double) * 6, s));
     uint32_t* h = g->core.as<uint32_t>();
     k_minmax_init<<<1, 64, 0, s>>>(mm.as<unsigned long long>());
     k_feat_init<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, g->dg.deg, s2.as<uint64_t>(), h,
@@ -482,8 +483,8 @@ bc_status mlp_loss_grad(const float* params, const float* x, const float* t, con
         return BC_EINVAL;
     }
     DevBuf part, dres;
-    BC_TRY(part.alloc(sizeof(float) * (kNP + 2) * (size_t)ntiles));
-    BC_TRY(dres.alloc(sizeof(double) * 2));
+    BC_TRY(part.alloc_on(sizeof(float) * (kNP + 2) * (size_t)ntiles, s));
+    BC_TRY(dres.alloc_on(sizeof(double) * 2, s));
     BC_HIP(hipMemsetAsync(dres.p, 0, sizeof(double) * 2, s));
     uint32_t* d_bad = reinterpret_cast<uint32_t*>(dres.as<double>() + 1);
     k_mlp_grad<<<(unsigned)ntiles, kBlk, 0, s>>>(params, x, t, w, rows, idx, count, part.as<float>(), d_bad);

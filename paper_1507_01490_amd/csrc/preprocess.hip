@@ -255,7 +255,7 @@ template <class F>
 bc_status cub_call(F&& f, hipStream_t s, DevBuf& tmp) {
     size_t bytes = 0;
     BC_HIP(f((void*)nullptr, bytes));
-    if (tmp.bytes < bytes) BC_TRY(tmp.alloc(bytes));
+    if (tmp.bytes < bytes) BC_TRY(tmp.alloc_on(bytes, s));
     BC_HIP(f(tmp.p, bytes));
     (void)s;
     return BC_OK;
@@ -368,14 +368,14 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
     return BC_OK;
 }
 
-bc_status order_by_degree(bc_graph* g, int32_t* d_order) {
+bc_status order_by_degree(bc_graph* g, int32_t* d_order, hipStream_t s) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
-    hipStream_t s = g->stream;
+    std::unique_lock<std::mutex> lk(g->cache_mu);
     if (!g->have_order_deg) {
         DevBuf k0, k1, tmp;
-        BC_TRY(k0.alloc(sizeof(uint64_t) * (size_t)n));
-        BC_TRY(k1.alloc(sizeof(uint64_t) * (size_t)n));
+        BC_TRY(k0.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+        BC_TRY(k1.alloc_on(sizeof(uint64_t) * (size_t)n, s));
         BC_TRY(g->order_deg.alloc(sizeof(int32_t) * (size_t)n));
         k_degree_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.deg, k0.as<uint64_t>());
         BC_TRY(cub_call([&](void* t, size_t& b) {
@@ -385,6 +385,7 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order) {
         BC_HIP(hipStreamSynchronize(s));
         g->have_order_deg = true;
     }
+    lk.unlock();
     BC_HIP(hipMemcpyAsync(d_order, g->order_deg.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     return BC_OK;
 }
@@ -392,17 +393,17 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order) {
 // Decreasing out-degree; among equal degrees, sources sharing their
 // highest-degree neighbour are adjacent (then by id), so a batch of
 // consecutive sources expands common neighbourhoods once.
-bc_status order_grouped(bc_graph* g, int32_t* d_order) {
+bc_status order_grouped(bc_graph* g, int32_t* d_order, hipStream_t s) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
-    hipStream_t s = g->stream;
+    std::unique_lock<std::mutex> lk(g->cache_mu);
     if (!g->have_order_grp) {
         DevBuf k0, k1, perm, dk0, dk1, tmp;
-        BC_TRY(k0.alloc(sizeof(uint64_t) * (size_t)n));
-        BC_TRY(k1.alloc(sizeof(uint64_t) * (size_t)n));
-        BC_TRY(perm.alloc(sizeof(int32_t) * (size_t)n));
-        BC_TRY(dk0.alloc(sizeof(uint32_t) * (size_t)n));
-        BC_TRY(dk1.alloc(sizeof(uint32_t) * (size_t)n));
+        BC_TRY(k0.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+        BC_TRY(k1.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+        BC_TRY(perm.alloc_on(sizeof(int32_t) * (size_t)n, s));
+        BC_TRY(dk0.alloc_on(sizeof(uint32_t) * (size_t)n, s));
+        BC_TRY(dk1.alloc_on(sizeof(uint32_t) * (size_t)n, s));
         BC_TRY(g->order_grp.alloc(sizeof(int32_t) * (size_t)n));
         k_hub_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, g->dg.deg, k0.as<uint64_t>());
         BC_TRY(cub_call([&](void* t, size_t& b) {
@@ -418,20 +419,21 @@ bc_status order_grouped(bc_graph* g, int32_t* d_order) {
         BC_HIP(hipStreamSynchronize(s));
         g->have_order_grp = true;
     }
+    lk.unlock();
     BC_HIP(hipMemcpyAsync(d_order, g->order_grp.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     return BC_OK;
 }
 
-bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order) {
+bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order,
+                          hipStream_t s) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
-    hipStream_t s = g->stream;
-    BC_TRY(order_by_degree(g, d_order));
+    BC_TRY(order_by_degree(g, d_order, s));
     DevBuf sc, key0, key1, val1, tmp;
-    BC_TRY(sc.alloc(sizeof(float) * (size_t)n));
-    BC_TRY(key0.alloc(sizeof(uint32_t) * (size_t)n));
-    BC_TRY(key1.alloc(sizeof(uint32_t) * (size_t)n));
-    BC_TRY(val1.alloc(sizeof(int32_t) * (size_t)n));
+    BC_TRY(sc.alloc_on(sizeof(float) * (size_t)n, s));
+    BC_TRY(key0.alloc_on(sizeof(uint32_t) * (size_t)n, s));
+    BC_TRY(key1.alloc_on(sizeof(uint32_t) * (size_t)n, s));
+    BC_TRY(val1.alloc_on(sizeof(int32_t) * (size_t)n, s));
     BC_HIP(hipMemcpyAsync(sc.p, scores, sizeof(float) * (size_t)n,
                           scores_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     k_score_keys<<<grid_for(n), kBlk, 0, s>>>(n, sc.as<float>(), d_order, key0.as<uint32_t>());
@@ -447,19 +449,19 @@ bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_devic
 
 // The first `head` sources by decreasing device score, then every other
 // source in the grouped degree order (relative order kept).
-bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order) {
+bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order,
+                             hipStream_t s) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
     head = std::min(std::max(head, 0), n);
-    hipStream_t s = g->stream;
     DevBuf by_score, grp, mark, keep, nsel, tmp;
-    BC_TRY(by_score.alloc(sizeof(int32_t) * (size_t)n));
-    BC_TRY(grp.alloc(sizeof(int32_t) * (size_t)n));
-    BC_TRY(mark.alloc((size_t)n));
-    BC_TRY(keep.alloc((size_t)n));
-    BC_TRY(nsel.alloc(sizeof(int32_t)));
-    BC_TRY(order_by_scores(g, d_scores, true, by_score.as<int32_t>()));
-    BC_TRY(order_grouped(g, grp.as<int32_t>()));
+    BC_TRY(by_score.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(grp.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(mark.alloc_on((size_t)n, s));
+    BC_TRY(keep.alloc_on((size_t)n, s));
+    BC_TRY(nsel.alloc_on(sizeof(int32_t), s));
+    BC_TRY(order_by_scores(g, d_scores, true, by_score.as<int32_t>(), s));
+    BC_TRY(order_grouped(g, grp.as<int32_t>(), s));
     BC_HIP(hipMemsetAsync(mark.p, 0, (size_t)n, s));
     if (head > 0) {
         k_mark_head<<<grid_for(head), kBlk, 0, s>>>(head, by_score.as<int32_t>(), mark.as<uint8_t>());
@@ -480,13 +482,12 @@ bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, i
     return BC_OK;
 }
 
-bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order) {
+bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipStream_t s) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
-    hipStream_t s = g->stream;
     DevBuf seen, errb;
-    BC_TRY(seen.alloc(sizeof(uint32_t) * (size_t)n));
-    BC_TRY(errb.alloc(sizeof(uint32_t)));
+    BC_TRY(seen.alloc_on(sizeof(uint32_t) * (size_t)n, s));
+    BC_TRY(errb.alloc_on(sizeof(uint32_t), s));
     BC_HIP(hipMemcpyAsync(d_order, h_perm, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     BC_HIP(hipMemsetAsync(seen.p, 0, sizeof(uint32_t) * (size_t)n, s));
     BC_HIP(hipMemsetAsync(errb.p, 0, sizeof(uint32_t), s));

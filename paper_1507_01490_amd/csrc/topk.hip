@@ -1569,12 +1569,13 @@ template <int WW>
 bc_status ensure_plain(Workspace& W_, const DevGraph& G, hipStream_t s) {
     if (W_.plain_ready && W_.ww == WW) return BC_OK;
     const size_t N = (size_t)G.n, words = N * Layout<WW>::SW;
-    BC_TRY(W_.seen.alloc(sizeof(uint64_t) * words));
-    BC_TRY(W_.qa.alloc(sizeof(int32_t) * N));
-    BC_TRY(W_.qb.alloc(sizeof(int32_t) * N));
-    BC_TRY(W_.clr.alloc(sizeof(int32_t) * N));
-    BC_TRY(W_.srcs.alloc(sizeof(SrcState) * kBlk));
-    BC_TRY(W_.ctl.alloc(sizeof(Ctl)));
+    BC_TRY(W_.seen.alloc_on(sizeof(uint64_t) * words, s));
+    BC_TRY(W_.qa.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(W_.qb.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(W_.clr.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(W_.srcs.alloc_on(sizeof(SrcState) * kBlk, s));
+    BC_TRY(W_.ctl.alloc_on(sizeof(Ctl), s));
+    if (!W_.hctl) BC_HIP(hipHostMalloc((void**)&W_.hctl, 64, hipHostMallocDefault));
     BC_HIP(hipMemsetAsync(W_.seen.p, 0, sizeof(uint64_t) * words, s));
     BC_HIP(hipMemsetAsync(W_.ctl.p, 0, sizeof(Ctl), s));
     if (N > 0) k_slot_init<WW><<<clamp_grid((int64_t)N, 4096), kBlk, 0, s>>>(G.deg, G.n, W_.seen.as<uint64_t>(), 1);
@@ -1594,11 +1595,11 @@ bc_status ensure_batched(Workspace& W_, const DevGraph& G, int want, hipStream_t
     W_.bclr.release();
     W_.slot_stamp.release();
     W_.slots = 0;
-    BC_TRY(W_.bseen.alloc(sizeof(uint64_t) * words * S_));
-    BC_TRY(W_.bqa.alloc(sizeof(int32_t) * N * S_));
-    BC_TRY(W_.bqb.alloc(sizeof(int32_t) * N * S_));
-    BC_TRY(W_.bclr.alloc(sizeof(int32_t) * N * S_));
-    BC_TRY(W_.slot_stamp.alloc(sizeof(uint32_t) * S_));
+    BC_TRY(W_.bseen.alloc_on(sizeof(uint64_t) * words * S_, s));
+    BC_TRY(W_.bqa.alloc_on(sizeof(int32_t) * N * S_, s));
+    BC_TRY(W_.bqb.alloc_on(sizeof(int32_t) * N * S_, s));
+    BC_TRY(W_.bclr.alloc_on(sizeof(int32_t) * N * S_, s));
+    BC_TRY(W_.slot_stamp.alloc_on(sizeof(uint32_t) * S_, s));
     BC_HIP(hipMemsetAsync(W_.bseen.p, 0, sizeof(uint64_t) * words * S_, s));
     BC_HIP(hipMemsetAsync(W_.slot_stamp.p, 0, sizeof(uint32_t) * S_, s));
     if (N > 0)
@@ -1610,10 +1611,9 @@ bc_status ensure_batched(Workspace& W_, const DevGraph& G, int want, hipStream_t
 
 template <int WW>
 bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_order, TopKDev T, QStats* d_st,
-                 Workspace& Wk, int W, Timing& tm) {
+                 Workspace& Wk, int W, Timing& tm, hipStream_t s) {
     using Lo = Layout<WW>;
     const DevGraph& G = g->dg;
-    hipStream_t s = g->stream;
     const int32_t n = G.n;
     const size_t N = (size_t)n;
     const uint32_t nbatches = (uint32_t)((n + W - 1) / W);
@@ -1638,12 +1638,7 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         SlotPtrs P{Wk.seen.as<uint64_t>(), Wk.qa.as<int32_t>(), Wk.qb.as<int32_t>(), Wk.clr.as<int32_t>()};
         SrcState* S = Wk.srcs.as<SrcState>();
         Ctl* C = Wk.ctl.as<Ctl>();
-        uint32_t* hctl = nullptr;
-        BC_HIP(hipHostMalloc((void**)&hctl, 64, hipHostMallocDefault));
-        struct HostFree {
-            uint32_t* p;
-            ~HostFree() { if (p) (void)hipHostFree(p); }
-        } hf{hctl};
+        uint32_t* hctl = Wk.hctl;
         EventPair ev;
         BC_TRY(ev.create());
         BC_HIP(hipEventRecord(ev.a, s));
@@ -1693,10 +1688,10 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         }
         if ((uint32_t)slots > nbatches - seed) slots = (int)(nbatches - seed);
         BC_TRY(ensure_batched<WW>(Wk, G, slots, s));
-        BC_TRY(Wk.nextb.alloc(sizeof(uint32_t)));
+        BC_TRY(Wk.nextb.alloc_on(sizeof(uint32_t), s));
         BC_HIP(hipMemcpyAsync(Wk.nextb.p, &seed, sizeof(uint32_t), hipMemcpyHostToDevice, s));
         SlotPtrs base{Wk.bseen.as<uint64_t>(), Wk.bqa.as<int32_t>(), Wk.bqb.as<int32_t>(), Wk.bclr.as<int32_t>()};
-        BC_TRY(Wk.defer.alloc(sizeof(int32_t) * N + 64));
+        BC_TRY(Wk.defer.alloc_on(sizeof(int32_t) * N + 64, s));
         uint32_t* dcnt = (uint32_t*)(Wk.defer.as<char>() + sizeof(int32_t) * N);
         BC_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t), s));
         DeferList D{Wk.defer.as<int32_t>(), dcnt,
@@ -1739,7 +1734,8 @@ namespace {
 // Top-k query, or (all_f != nullptr) the exact farness and reach of every
 // node: the same batches with no list and no threshold, so nothing is cut.
 bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* farness, uint32_t* reach,
-                    int32_t* count, bc_stats* st_out, uint64_t* all_f, uint32_t* all_r) {
+                    int32_t* count, bc_stats* st_out, uint64_t* all_f, uint32_t* all_r, hipStream_t s,
+                    bool private_ws) {
     auto t0 = std::chrono::steady_clock::now();
     const bool all = all_f != nullptr;
     if (all) {
@@ -1747,7 +1743,6 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         if (o.seed_batches < 0) o.seed_batches = 0;  // no threshold to seed
     }
     const int32_t n = g->dg.n;
-    hipStream_t s = g->stream;
     const int W = o.width;
     if (W != 64 && W != 128 && W != 256) {
         set_error("width must be 64, 128 or 256 (got %d)", W);
@@ -1763,34 +1758,34 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
     Timing tm;
     if (kk > 0) {
         QueryBufs B;
-        BC_TRY(B.order.alloc(sizeof(int32_t) * (size_t)n));
+        BC_TRY(B.order.alloc_on(sizeof(int32_t) * (size_t)n, s));
         int32_t* d_order = B.order.as<int32_t>();
         const int32_t ord = o.order == BC_ORDER_AUTO ? (o.mode == BC_MODE_BATCHED ? BC_ORDER_GROUPED : BC_ORDER_DEGREE)
                                                       : o.order;
         if (ord == BC_ORDER_DEGREE) {
-            BC_TRY(order_by_degree(g, d_order));
+            BC_TRY(order_by_degree(g, d_order, s));
         } else if (ord == BC_ORDER_GROUPED) {
-            BC_TRY(order_grouped(g, d_order));
+            BC_TRY(order_grouped(g, d_order, s));
         } else if (ord == BC_ORDER_GIVEN) {
             if (!o.perm) { set_error("BC_ORDER_GIVEN needs opts.perm"); return BC_EINVAL; }
-            BC_TRY(order_given(g, o.perm, d_order));
+            BC_TRY(order_given(g, o.perm, d_order, s));
         } else if (ord == BC_ORDER_SCORES) {
             if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
-            BC_TRY(order_by_scores(g, o.scores, false, d_order));
+            BC_TRY(order_by_scores(g, o.scores, false, d_order, s));
         } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED) {
             if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
-            BC_TRY(graph_features(g));
+            BC_TRY(graph_features(g, s));
             DevBuf prm, sc;
-            BC_TRY(prm.alloc(sizeof(float) * BC_MLP_PARAMS));
-            BC_TRY(sc.alloc(sizeof(float) * (size_t)n));
+            BC_TRY(prm.alloc_on(sizeof(float) * BC_MLP_PARAMS, s));
+            BC_TRY(sc.alloc_on(sizeof(float) * (size_t)n, s));
             BC_HIP(hipMemcpyAsync(prm.p, o.mlp, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
             BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
             if (ord == BC_ORDER_LEARNED) {
-                BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order));
+                BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
             } else {
                 const int64_t sb = o.seed_batches >= 0 ? o.seed_batches : ((int64_t)kk + W - 1) / W;
                 const int64_t head = std::min<int64_t>((int64_t)n, sb * W);
-                BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order));
+                BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order, s));
             }
         } else {
             set_error("unknown order %d", o.order);
@@ -1800,13 +1795,13 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         // records (every-node mode: only the header, and the per-node outputs)
         const size_t hdr = 64;
         const size_t nrec = all ? 0 : (size_t)kk;
-        BC_TRY(B.topk.alloc(hdr + sizeof(Rec) * nrec));
-        BC_TRY(B.ring.alloc(sizeof(ThRec) * (all ? 1 : (size_t)n + 1)));
-        BC_TRY(B.stats.alloc(sizeof(QStats)));
+        BC_TRY(B.topk.alloc_on(hdr + sizeof(Rec) * nrec, s));
+        BC_TRY(B.ring.alloc_on(sizeof(ThRec) * (all ? 1 : (size_t)n + 1), s));
+        BC_TRY(B.stats.alloc_on(sizeof(QStats), s));
         DevBuf allf, allr;
         if (all) {
-            BC_TRY(allf.alloc(sizeof(uint64_t) * (size_t)n));
-            BC_TRY(allr.alloc(sizeof(uint32_t) * (size_t)n));
+            BC_TRY(allf.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+            BC_TRY(allr.alloc_on(sizeof(uint32_t) * (size_t)n, s));
         }
         BC_HIP(hipMemsetAsync(B.topk.p, 0, hdr + sizeof(Rec) * nrec, s));
         BC_HIP(hipMemsetAsync(B.stats.p, 0, sizeof(QStats), s));
@@ -1824,16 +1819,16 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         // the graph's cached workspace, or a private one when another query holds it
         std::unique_ptr<Workspace> own;
         Workspace* wk = nullptr;
-        {
+        if (!private_ws) {
             std::lock_guard<std::mutex> lk(g->ws_mu);
             if (!g->ws_busy) {
-                if (!g->ws) g->ws.reset(new Workspace());
+                if (!g->ws || g->ws->stream != s) g->ws.reset(new Workspace(s));
                 g->ws_busy = true;
                 wk = g->ws.get();
             }
         }
         if (!wk) {
-            own.reset(new Workspace());
+            own.reset(new Workspace(s));
             wk = own.get();
         }
         struct Release {
@@ -1847,9 +1842,9 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
             }
         } rel{g, own == nullptr};
         bc_status rs;
-        if (W == 64) rs = run_ww<1>(g, kk, o, d_order, T, d_st, *wk, W, tm);
-        else if (W == 128) rs = run_ww<2>(g, kk, o, d_order, T, d_st, *wk, W, tm);
-        else rs = run_ww<4>(g, kk, o, d_order, T, d_st, *wk, W, tm);
+        if (W == 64) rs = run_ww<1>(g, kk, o, d_order, T, d_st, *wk, W, tm, s);
+        else if (W == 128) rs = run_ww<2>(g, kk, o, d_order, T, d_st, *wk, W, tm, s);
+        else rs = run_ww<4>(g, kk, o, d_order, T, d_st, *wk, W, tm, s);
         if (rs != BC_OK) {
             // a failed query may leave marks behind: never reuse its workspace
             std::lock_guard<std::mutex> lk(g->ws_mu);
@@ -1921,12 +1916,13 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
 }  // namespace
 
 bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness, uint32_t* reach,
-                   int32_t* count, bc_stats* st) {
-    return run_query(g, k, o, ids, farness, reach, count, st, nullptr, nullptr);
+                   int32_t* count, bc_stats* st, hipStream_t s, bool private_ws) {
+    return run_query(g, k, o, ids, farness, reach, count, st, nullptr, nullptr, s, private_ws);
 }
 
-bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st) {
-    return run_query(g, 0, o, nullptr, nullptr, nullptr, nullptr, st, farness, reach);
+bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st,
+                          hipStream_t s) {
+    return run_query(g, 0, o, nullptr, nullptr, nullptr, nullptr, st, farness, reach, s, false);
 }
 
 }  // namespace bc

@@ -50,7 +50,9 @@ def test_struct_layouts_match_header(tmp_path):
     """Size and every field offset of bc_opts / bc_stats as a C compiler
     lays them out from the header, against the binding's ctypes structs."""
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bfscut.h"', 'int main(void) {']
-    for cname, py in (("bc_opts", bc.Opts), ("bc_stats", bc.Stats)):
+    structs = (("bc_opts", bc.Opts), ("bc_stats", bc.Stats), ("bc_server_opts", bc.ServerOpts),
+               ("bc_request_info", bc.RequestInfo), ("bc_server_stats", bc.ServerStats))
+    for cname, py in structs:
         lines.append(f'printf("{cname} __sizeof %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
@@ -63,7 +65,7 @@ def test_struct_layouts_match_header(tmp_path):
     for line in subprocess.check_output([str(exe)], text=True).splitlines():
         c, f, v = line.split()
         got[(c, f)] = int(v)
-    for cname, py in (("bc_opts", bc.Opts), ("bc_stats", bc.Stats)):
+    for cname, py in structs:
         assert got[(cname, "__sizeof")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
@@ -74,3 +76,27 @@ def test_null_arguments_rejected_without_gpu_work():
     assert lib.bc_graph_create(0, 0, None, None, 0, None, None) == -1
     assert lib.bc_topk(None, 1, None, None, None, None, None, None) == -1
     assert b"NULL" in lib.bc_last_error()
+
+
+def test_footprint_arithmetic():
+    """The serving admission estimate (pure host arithmetic, no device call)."""
+    n, m = 20000, 160000
+    g, u, q_plain = bc.footprint(n, m, k=10, mode="plain")
+    assert g == 4 * (n + 1) + 4 * m + 36 * n
+    assert u == 12 * m + 40 * n + (1 << 20)
+    per_slot = n * (8 * 4 + 12)
+    _, _, q16 = bc.footprint(n, m, k=10, mode="batched", slots=16)
+    _, _, q32 = bc.footprint(n, m, k=10, mode="batched", slots=32)
+    assert q16 - q_plain == 16 * per_slot + 4 * 16
+    assert q32 - q16 == 16 * per_slot + 4 * 16
+    # W = 256 records are four times wider
+    _, _, q256 = bc.footprint(n, m, k=10, mode="batched", slots=16, width=256)
+    assert q256 - q16 == 17 * n * 8 * 12
+    # slots never exceed the number of batches
+    _, _, qs = bc.footprint(100, 400, k=1, mode="batched", slots=64)
+    _, _, qp = bc.footprint(100, 400, k=1, mode="plain")
+    assert qs - qp == 2 * 100 * 44 + 8
+    gd, _, _ = bc.footprint(n, m, directed=True)
+    assert gd - g == 4 * (n + 1) + 4 * m
+    for big in (bc.footprint(2 * n, m), bc.footprint(n, 2 * m), bc.footprint(n, m, k=100)):
+        assert big[0] + big[2] > g + q_plain

@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ba1m")
+    ap.add_argument("--workload", default="ba1m", help="ba1m (default), ba2k, rmat21, collab, rgg or serve512")
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--slots", type=int, default=0)
@@ -75,6 +75,10 @@ def main():
                     help="source order of the timed mode (auto: grouped degree in batched mode)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--lanes", type=int, default=4, help="serve512: concurrent requests")
+    ap.add_argument("--serve-slots", type=int, default=64, help="serve512: workgroups per persistent kernel")
+    ap.add_argument("--budget-mb", type=int, default=2048, help="serve512: device memory budget")
+    ap.add_argument("--load", type=float, default=0.8, help="serve512: Poisson rate as a fraction of capacity")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -102,6 +106,10 @@ def main():
 
     import paper_1507_01490_amd as bc
     from paper_1507_01490_amd import workloads
+
+    if args.workload == "serve512":
+        serve_bench(args, bc, workloads)
+        return
 
     t0 = time.time()
     g = workloads.build(args.workload)
@@ -226,6 +234,70 @@ def main():
                 roofline=roofline, cpu_baseline=cpu, plain=plain)
     print(json.dumps(line), flush=True)
     G.close()
+
+
+def serve_bench(args, bc, workloads):
+    """Serving mix: capacity from a closed-loop burst of every request, then
+    an open loop with Poisson arrivals at `load` x capacity; latency of a
+    request = finish - submit on the server's clock."""
+    import numpy as np
+    t0 = time.time()
+    mix = workloads.serve_mix()
+    log(f"[serve] generated {len(mix)} graphs (sum n = {sum(g.n for g, _ in mix)}, "
+        f"sum arcs = {sum(g.m for g, _ in mix)}) in {time.time() - t0:.1f}s")
+    S = bc.Server(lanes=args.lanes, slots=args.serve_slots, budget_bytes=args.budget_mb << 20)
+    gids = [S.add_graph(g.row_ptr, g.col, directed=g.directed) for g, _ in mix]
+
+    def run(times):
+        """Submit request i at times[i] seconds from now (None: all at once)."""
+        tickets = []
+        start = time.perf_counter()
+        for i, (gid, (_, k)) in enumerate(zip(gids, mix)):
+            if times is not None:
+                delay = start + times[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(S.submit(gid, k, mode="batched"))
+        out = []
+        for i, t in enumerate(tickets):
+            S.wait(t, -1)
+            out.append(S.poll(t))
+            if (i + 1) % 64 == 0:
+                log(f"[serve] {i + 1}/{len(tickets)} done at {time.perf_counter() - start:.1f}s")
+        return out, time.perf_counter() - start
+
+    for gid, (g, _) in list(zip(gids, mix))[:8]:  # warm-up: library, kernels, pool
+        t = S.submit(gid, 1, mode="batched")
+        S.wait(t, -1)
+        S.poll(t)
+    burst, span = run(None)
+    capacity = len(mix) / span
+    log(f"[serve] burst: {len(mix)} requests in {span:.2f}s -> capacity {capacity:.1f} req/s")
+    rate = args.load * capacity
+    rng = np.random.Generator(np.random.PCG64(3))
+    times = np.cumsum(rng.exponential(1.0 / rate, len(mix)))
+    res, span2 = run(times)
+    same = all(a.ids.tolist() == b.ids.tolist() and a.farness.tolist() == b.farness.tolist()
+               for a, b in zip(burst, res))
+    lat = np.array([r.info["finish_ms"] - r.info["submit_ms"] for r in res])
+    wait = np.array([r.info["start_ms"] - r.info["submit_ms"] for r in res])
+    svc = np.array([r.info["finish_ms"] - r.info["start_ms"] for r in res])
+    info = S.info()
+    S.close()
+    line = dict(metric="serving latency p50/p99 and throughput on 1 MI355X (512-graph top-k mix)",
+                value=round(len(mix) / span2, 3), unit="req/s", n_gpus=1, higher_is_better=True,
+                p50_ms=round(float(np.percentile(lat, 50)), 2), p99_ms=round(float(np.percentile(lat, 99)), 2),
+                mean_ms=round(float(lat.mean()), 2), wait_p50_ms=round(float(np.percentile(wait, 50)), 2),
+                wait_p99_ms=round(float(np.percentile(wait, 99)), 2),
+                service_p50_ms=round(float(np.percentile(svc, 50)), 2),
+                service_p99_ms=round(float(np.percentile(svc, 99)), 2),
+                capacity_rps=round(capacity, 3), offered_rps=round(rate, 3), load=args.load,
+                same_results_burst_vs_poisson=bool(same), dtype="int64", data="synthetic",
+                config=dict(workload=workloads.DESCRIPTION["serve512"], lanes=args.lanes,
+                            slots=args.serve_slots, budget_mb=args.budget_mb, mode="batched"),
+                server=dict(uploads=info["uploads"], evictions=info["evictions"], peak_mb=round(info["peak_bytes"] / 2**20, 1),
+                            completed=info["completed"], failed=info["failed"]))
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -92,8 +92,14 @@ typedef struct bc_opts {
                                level-synchronous kernels afterwards (0 = 65536, -1 = never) */
     int32_t lds_tables;     /* BC_MODE_BATCHED, W = 64: keep small batch states in LDS
                                hash tables (0 = yes, -1 = always use the node records)   */
-    int32_t reserved;
+    int32_t defer_width;    /* BC_MODE_BATCHED: sources per batch of the re-run of deferred
+                               sources, 64, 128 or 256 (0 = 256)                         */
     const float* mlp;       /* BC_ORDER_LEARNED: host, BC_MLP_PARAMS floats              */
+    int32_t graph_levels;   /* level-synchronous batches: capture this many level steps in
+                               a HIP graph and replay it, checking for live sources once
+                               per replay (0, the default: one host round trip per level,
+                               which measures faster on gfx950)                          */
+    int32_t reserved;
 } bc_opts;
 
 typedef struct bc_stats {
@@ -213,6 +219,28 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
  * baseline the pruned search is compared with.  Errors as bc_topk.
  */
 bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, uint32_t* reach, bc_stats* stats);
+
+/*
+ * bc_autotune -- pick the batched-mode execution knobs for one graph and k.
+ *
+ * None of the knobs changes the answer, only the time.  Starting from
+ * `base` (NULL: defaults) in BC_MODE_BATCHED, the tuner runs the query and
+ * tries, one knob at a time around the best setting so far: width (64, 128,
+ * 256), defer_arcs (16384, 65536, 262144), defer_width (64, 256),
+ * pull_alpha (never, 14, 40), slots (128, 256, 512) and order (grouped,
+ * degree).  Each setting is timed as the best of `repeats` runs after one
+ * warm-up.  Every run must return exactly the first run's top-k, else
+ * BC_EDEVICE.  *best receives the fastest setting; report (may be NULL) the
+ * trial count and the times of the base and best settings.
+ */
+typedef struct bc_tune_report {
+    uint32_t size;
+    int32_t trials;
+    double default_ms, best_ms;
+} bc_tune_report;
+
+bc_status bc_autotune(bc_graph* g, int32_t k, const bc_opts* base, int32_t repeats, bc_opts* best,
+                      bc_tune_report* report);
 
 /*
  * Serving: a queue of top-k requests over many graphs on one GPU.

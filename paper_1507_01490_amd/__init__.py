@@ -53,7 +53,8 @@ class Opts(ctypes.Structure):
                 ("pull_alpha", ctypes.c_float), ("pull_beta", ctypes.c_float),
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("defer_arcs", ctypes.c_int32),
-                ("lds_tables", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+                ("lds_tables", ctypes.c_int32), ("defer_width", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("graph_levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -74,6 +75,11 @@ class Stats(ctypes.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
         d["phase_ms"] = list(self.phase_ms)
         return d
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("trials", ctypes.c_int32), ("default_ms", ctypes.c_double),
+                ("best_ms", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -135,6 +141,7 @@ def load_library(path: str = LIB_PATH):
     lib.bc_poll.argtypes = [P, u64, P, P, P, P, ctypes.POINTER(Stats), ctypes.POINTER(RequestInfo)]
     lib.bc_cancel.argtypes = [P, u64]
     lib.bc_server_info.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.bc_autotune.argtypes = [P, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(Opts), ctypes.POINTER(TuneReport)]
     lib.bc_footprint.argtypes = [i32, i64, u32, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(u64),
                                  ctypes.POINTER(u64), ctypes.POINTER(u64)]
     lib.bc_graph_features.argtypes = [P, P, P]
@@ -144,7 +151,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("bc_graph_create", "bc_graph_destroy", "bc_graph_info", "bc_graph_reach",
                  "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_graph_features", "bc_server_create",
                  "bc_server_destroy", "bc_server_add_graph", "bc_submit", "bc_wait", "bc_poll", "bc_cancel",
-                 "bc_server_info", "bc_footprint", "bc_mlp_forward", "bc_mlp_loss_grad",
+                 "bc_server_info", "bc_footprint", "bc_autotune", "bc_mlp_forward", "bc_mlp_loss_grad",
                  "bc_mlp_adam"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -225,7 +232,8 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
 
 
 def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=14.0, pull_beta=24.0,
-              slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None) -> Opts:
+              slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None, defer_width=0,
+              graph_levels=None) -> Opts:
     """bc_opts for a graph of n nodes; host arrays the options point at are
     appended to `keep` (they must outlive the call that reads them)."""
     lib = load_library()
@@ -242,6 +250,9 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
     o.defer_arcs = int(defer_arcs)
     o.chunk = int(chunk)
     o.lds_tables = 0 if lds_tables else -1
+    o.defer_width = int(defer_width)
+    if graph_levels is not None:
+        o.graph_levels = int(graph_levels)
     if isinstance(order, str) and order in ("learned", "learned_grouped"):
         prm = np.ascontiguousarray(default_mlp() if mlp is None else mlp, dtype=np.float32)
         if prm.shape != (MLP_PARAMS,):
@@ -384,7 +395,7 @@ class Graph:
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
              pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
              seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
-             lds_tables: bool = True, mlp=None) -> TopK:
+             lds_tables: bool = True, mlp=None, defer_width: int = 0, graph_levels=None) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
         order: None (automatic), "degree", "grouped", "learned" (the order
@@ -395,6 +406,9 @@ class Graph:
         keep = []
         o = self._opts(mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
                        lds_tables, mlp, keep)
+        o.defer_width = int(defer_width)
+        if graph_levels is not None:
+            o.graph_levels = int(graph_levels)
         kk = max(1, int(k))
         ids = np.zeros(kk, np.int32)
         far = np.zeros(kk, np.uint64)
@@ -406,6 +420,24 @@ class Graph:
                                       ctypes.byref(cnt), ctypes.byref(st)))
         c = cnt.value
         return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
+
+    def autotune(self, k: int, repeats: int = 1, **kw):
+        """(best options as topk keyword arguments, report) for this graph and k."""
+        keep = []
+        o = self._opts(kw.pop("mode", "batched"), kw.pop("width", 64), kw.pop("order", None), None,
+                       kw.pop("pull_alpha", 14.0), kw.pop("pull_beta", 24.0), kw.pop("slots", 0),
+                       kw.pop("seed_batches", -1), kw.pop("defer_arcs", 0), 0, kw.pop("lds_tables", True), None, keep)
+        if kw:
+            raise TypeError(f"unexpected options {sorted(kw)}")
+        best = Opts()
+        rep = TuneReport()
+        rep.size = ctypes.sizeof(TuneReport)
+        _check(load_library().bc_autotune(self._h, int(k), ctypes.byref(o), int(repeats), ctypes.byref(best),
+                                          ctypes.byref(rep)))
+        order = {ORDER_DEGREE: "degree", ORDER_GROUPED: "grouped", ORDER_AUTO: None}.get(best.order, None)
+        tuned = dict(mode="batched", width=best.width, defer_arcs=best.defer_arcs, defer_width=best.defer_width,
+                     pull_alpha=best.pull_alpha, slots=best.slots, order=order)
+        return tuned, dict(trials=rep.trials, default_ms=rep.default_ms, best_ms=rep.best_ms)
 
     def farness_all(self, mode: str | int = "batched", width: int = 64, order=None, slots: int = 0,
                     seed_batches: int = -1, defer_arcs: int = 0, lds_tables: bool = True):

@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 
@@ -33,6 +34,26 @@ void set_error(const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+}
+
+bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
+                       hipStream_t stream, bool ordered, bc_graph** out) {
+    if (!out) { set_error("out is NULL"); return BC_EINVAL; }
+    *out = nullptr;
+    if (n < 0 || m < 0) { set_error("negative size"); return BC_EINVAL; }
+    if (!row_ptr || (m > 0 && !col)) { set_error("row_ptr/col is NULL"); return BC_EINVAL; }
+    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS)) { set_error("unknown flag bits"); return BC_EINVAL; }
+    std::unique_ptr<bc_graph> g(new bc_graph());
+    g->stream = stream;
+    g->ordered = ordered;
+    (void)hipGetDevice(&g->device);
+    bc_status s = graph_build(g.get(), n, m, row_ptr, col, flags);
+    if (s != BC_OK) {
+        (void)hipStreamSynchronize(g->stream);
+        return s;
+    }
+    *out = g.release();
+    return BC_OK;
 }
 
 }  // namespace bc
@@ -73,28 +94,14 @@ void bc_opts_default(bc_opts* o) {
     o->chunk = 0;
     o->defer_arcs = 0;
     o->mlp = nullptr;
+    o->graph_levels = 0;
 }
 
 bc_status bc_graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
                           void* stream, bc_graph** out) {
     BC_GUARD_BEGIN
     bc::g_err[0] = 0;
-    if (!out) { set_error("out is NULL"); return BC_EINVAL; }
-    *out = nullptr;
-    if (n < 0 || m < 0) { set_error("negative size"); return BC_EINVAL; }
-    if (!row_ptr || (m > 0 && !col)) { set_error("row_ptr/col is NULL"); return BC_EINVAL; }
-    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS)) { set_error("unknown flag bits"); return BC_EINVAL; }
-    bc_graph* g = new bc_graph();
-    g->stream = (hipStream_t)stream;
-    (void)hipGetDevice(&g->device);
-    bc_status s = bc::graph_build(g, n, m, row_ptr, col, flags);
-    if (s != BC_OK) {
-        (void)hipStreamSynchronize(g->stream);
-        delete g;
-        return s;
-    }
-    *out = g;
-    return BC_OK;
+    return bc::graph_create(n, m, row_ptr, col, flags, (hipStream_t)stream, false, out);
     BC_GUARD_END
 }
 

@@ -14,6 +14,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "bfscut.h"
@@ -107,6 +108,12 @@ struct DevBuf {
     }
     template <class T>
     T* as() const { return reinterpret_cast<T*>(p); }
+    void swap(DevBuf& o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(ordered, o.ordered);
+        std::swap(stream, o.stream);
+    }
 };
 
 }  // namespace bc
@@ -125,12 +132,14 @@ struct Workspace {
     bool plain_ready = false;
     hipStream_t stream = nullptr;  // stream its buffers are ordered on
     uint32_t* hctl = nullptr;      // pinned copy of the level-synchronous control block
+    hipStream_t cap = nullptr;     // private stream that captures level-step graphs
     Workspace() = default;
     explicit Workspace(hipStream_t s) : stream(s) {}
     Workspace(const Workspace&) = delete;
     Workspace& operator=(const Workspace&) = delete;
     ~Workspace() {
         if (hctl) (void)hipHostFree(hctl);
+        if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
@@ -153,7 +162,16 @@ struct bc_graph {
     bool ws_busy = false;
     std::unique_ptr<bc::Workspace> ws;      // cached workspace (one query at a time)
     std::mutex cache_mu;                    // guards building the cached orders and features
+    bool ordered = false;                   // graph buffers are stream-ordered allocations (server graphs)
 };
+
+namespace bc {
+// A graph-lifetime buffer: stream-ordered on s for server graphs (their
+// lane streams outlive them), a plain allocation otherwise.
+inline bc_status galloc(bc_graph* g, DevBuf& b, size_t bytes, hipStream_t s) {
+    return g->ordered ? b.alloc_on(bytes, s) : b.alloc(bytes);
+}
+}  // namespace bc
 
 namespace bc {
 
@@ -161,6 +179,9 @@ namespace bc {
 // transpose and reach data.  rp/col are host or device pointers per flags.
 bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp, const int32_t* col,
                       uint32_t flags);
+// bc_graph_create on stream s; ordered = stream-ordered graph buffers.
+bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
+                       hipStream_t s, bool ordered, bc_graph** out);
 
 // Source orders (preprocess.hip): decreasing out-degree (ties by id), or a
 // given permutation, or decreasing score (ties by degree, then id).

@@ -415,8 +415,8 @@ bc_status graph_features(bc_graph* g, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g->cache_mu);
     if (g->have_feat) return BC_OK;
     const int32_t n = g->dg.n;
-    BC_TRY(g->feat.alloc(sizeof(float) * 3 * (size_t)std::max(n, 1)));
-    BC_TRY(g->core.alloc(sizeof(uint32_t) * (size_t)std::max(n, 1)));
+    BC_TRY(galloc(g, g->feat, sizeof(float) * 3 * (size_t)std::max(n, 1), s));
+    BC_TRY(galloc(g, g->core, sizeof(uint32_t) * (size_t)std::max(n, 1), s));
     if (n == 0) {
         g->have_feat = true;
         return BC_OK;

@@ -274,9 +274,9 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
         return BC_EGRAPH;
     }
     DevBuf rp0, col0, errb, tmp;
-    BC_TRY(rp0.alloc(sizeof(int32_t) * ((size_t)n + 1)));
-    BC_TRY(col0.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
-    BC_TRY(errb.alloc(sizeof(uint32_t)));
+    BC_TRY(rp0.alloc_on(sizeof(int32_t) * ((size_t)n + 1), s));
+    BC_TRY(col0.alloc_on(sizeof(int32_t) * (size_t)(m > 0 ? m : 1), s));
+    BC_TRY(errb.alloc_on(sizeof(uint32_t), s));
     hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     BC_HIP(hipMemcpyAsync(rp0.p, rp_in, sizeof(int32_t) * ((size_t)n + 1), kind, s));
     if (m > 0) BC_HIP(hipMemcpyAsync(col0.p, col_in, sizeof(int32_t) * (size_t)m, kind, s));
@@ -293,9 +293,9 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
     if (err & 4u) {
         // canonical form: sort every row, then drop self-loops and repeats
         DevBuf sorted, cnt, nrp;
-        BC_TRY(sorted.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
-        BC_TRY(cnt.alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
-        BC_TRY(nrp.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+        BC_TRY(sorted.alloc_on(sizeof(int32_t) * (size_t)(m > 0 ? m : 1), s));
+        BC_TRY(cnt.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+        BC_TRY(nrp.alloc_on(sizeof(int32_t) * ((size_t)n + 1), s));
         const int32_t* rpp = rp0.as<int32_t>();
         BC_TRY(cub_call([&](void* t, size_t& b) {
             return hipcub::DeviceSegmentedRadixSort::SortKeys(t, b, col0.as<int32_t>(), sorted.as<int32_t>(),
@@ -310,17 +310,23 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
         BC_HIP(hipMemcpyAsync(&newm, nrp.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
         mc = newm;
-        BC_TRY(g->rp.alloc(sizeof(int32_t) * ((size_t)n + 1)));
-        BC_TRY(g->col.alloc(sizeof(int32_t) * (size_t)(mc > 0 ? mc : 1)));
+        BC_TRY(galloc(g, g->rp, sizeof(int32_t) * ((size_t)n + 1), s));
+        BC_TRY(galloc(g, g->col, sizeof(int32_t) * (size_t)(mc > 0 ? mc : 1), s));
         BC_HIP(hipMemcpyAsync(g->rp.p, nrp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
         k_compact_rows<<<grid_for(n), kBlk, 0, s>>>(n, rpp, sorted.as<int32_t>(), g->rp.as<int32_t>(),
                                                     g->col.as<int32_t>());
         BC_HIP(hipStreamSynchronize(s));
     } else {
-        std::swap(g->rp.p, rp0.p);
-        std::swap(g->rp.bytes, rp0.bytes);
-        std::swap(g->col.p, col0.p);
-        std::swap(g->col.bytes, col0.bytes);
+        if (g->ordered) {
+            g->rp.swap(rp0);
+            g->col.swap(col0);
+        } else {
+            BC_TRY(g->rp.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+            BC_TRY(g->col.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+            BC_HIP(hipMemcpyAsync(g->rp.p, rp0.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+            if (m > 0)
+                BC_HIP(hipMemcpyAsync(g->col.p, col0.p, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice, s));
+        }
     }
 
     g->dg.n = n;
@@ -328,11 +334,11 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
     g->dg.directed = directed ? 1 : 0;
     g->dg.rp = g->rp.as<int32_t>();
     g->dg.col = g->col.as<int32_t>();
-    BC_TRY(g->deg.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+    BC_TRY(galloc(g, g->deg, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
     k_degree<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->deg.as<uint32_t>());
     g->dg.deg = g->deg.as<uint32_t>();
-    BC_TRY(g->x0.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
-    BC_TRY(g->x1.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+    BC_TRY(galloc(g, g->x0, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
+    BC_TRY(galloc(g, g->x1, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
     g->dg.x0 = g->x0.as<uint32_t>();
     g->dg.x1 = g->x1.as<uint32_t>();
 
@@ -347,9 +353,9 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
         g->dg.irp = g->dg.rp;
         g->dg.icol = g->dg.col;
         DevBuf P, size, label;
-        BC_TRY(P.alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
-        BC_TRY(size.alloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
-        BC_TRY(label.alloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+        BC_TRY(P.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+        BC_TRY(size.alloc_on(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
+        BC_TRY(label.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
         BC_HIP(hipMemsetAsync(size.p, 0, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
         if (n > 0) {
             k_uf_init<<<grid_for(n), kBlk, 0, s>>>(n, P.as<int32_t>());
@@ -376,7 +382,7 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order, hipStream_t s) {
         DevBuf k0, k1, tmp;
         BC_TRY(k0.alloc_on(sizeof(uint64_t) * (size_t)n, s));
         BC_TRY(k1.alloc_on(sizeof(uint64_t) * (size_t)n, s));
-        BC_TRY(g->order_deg.alloc(sizeof(int32_t) * (size_t)n));
+        BC_TRY(galloc(g, g->order_deg, sizeof(int32_t) * (size_t)n, s));
         k_degree_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.deg, k0.as<uint64_t>());
         BC_TRY(cub_call([&](void* t, size_t& b) {
             return hipcub::DeviceRadixSort::SortKeys(t, b, k0.as<uint64_t>(), k1.as<uint64_t>(), n, 0, 64, s);
@@ -404,7 +410,7 @@ bc_status order_grouped(bc_graph* g, int32_t* d_order, hipStream_t s) {
         BC_TRY(perm.alloc_on(sizeof(int32_t) * (size_t)n, s));
         BC_TRY(dk0.alloc_on(sizeof(uint32_t) * (size_t)n, s));
         BC_TRY(dk1.alloc_on(sizeof(uint32_t) * (size_t)n, s));
-        BC_TRY(g->order_grp.alloc(sizeof(int32_t) * (size_t)n));
+        BC_TRY(galloc(g, g->order_grp, sizeof(int32_t) * (size_t)n, s));
         k_hub_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, g->dg.deg, k0.as<uint64_t>());
         BC_TRY(cub_call([&](void* t, size_t& b) {
             return hipcub::DeviceRadixSort::SortKeys(t, b, k0.as<uint64_t>(), k1.as<uint64_t>(), n, 0, 64, s);

@@ -258,10 +258,10 @@ __global__ void k_reach_out(int32_t n, const int32_t* __restrict__ cid, const ui
 }
 
 template <class F>
-bc_status cub_call(F&& f, DevBuf& tmp) {
+bc_status cub_call(F&& f, DevBuf& tmp, hipStream_t s) {
     size_t bytes = 0;
     BC_HIP(f((void*)nullptr, bytes));
-    if (tmp.bytes < bytes) BC_TRY(tmp.alloc(bytes));
+    if (tmp.bytes < bytes) BC_TRY(tmp.alloc_on(bytes, s));
     BC_HIP(f(tmp.p, bytes));
     return BC_OK;
 }
@@ -281,11 +281,11 @@ bc_status directed_reach(bc_graph* g) {
     const size_t N = (size_t)(n > 0 ? n : 1);
     DevBuf tmp, icnt, fill, flag;
     // in-CSR
-    BC_TRY(g->irp.alloc(sizeof(int32_t) * (N + 1)));
-    BC_TRY(g->icol.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
-    BC_TRY(icnt.alloc(sizeof(int32_t) * N));
-    BC_TRY(fill.alloc(sizeof(int32_t) * N));
-    BC_TRY(flag.alloc(sizeof(int32_t) * 4));
+    BC_TRY(galloc(g, g->irp, sizeof(int32_t) * (N + 1), s));
+    BC_TRY(galloc(g, g->icol, sizeof(int32_t) * (size_t)(m > 0 ? m : 1), s));
+    BC_TRY(icnt.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(fill.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(flag.alloc_on(sizeof(int32_t) * 4, s));
     int32_t* fl = flag.as<int32_t>();
     BC_HIP(hipMemsetAsync(icnt.p, 0, sizeof(int32_t) * N, s));
     BC_HIP(hipMemsetAsync(fill.p, 0, sizeof(int32_t) * N, s));
@@ -299,7 +299,7 @@ bc_status directed_reach(bc_graph* g) {
     k_indeg<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, icnt.as<int32_t>());
     BC_TRY(cub_call([&](void* t, size_t& b) {
         return hipcub::DeviceScan::ExclusiveSum(t, b, icnt.as<int32_t>(), g->irp.as<int32_t>(), n, s);
-    }, tmp));
+    }, tmp, s));
     k_close<<<1, 1, 0, s>>>(g->irp.as<int32_t>(), n, icnt.as<int32_t>());
     k_fill_in<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->dg.col, g->irp.as<int32_t>(), fill.as<int32_t>(),
                                            g->icol.as<int32_t>());
@@ -309,13 +309,13 @@ bc_status directed_reach(bc_graph* g) {
 
     // ---- SCCs
     DevBuf comp, comp_next, color, mark, q0, q1, best;
-    BC_TRY(comp.alloc(sizeof(int32_t) * N));
-    BC_TRY(comp_next.alloc(sizeof(int32_t) * N));
-    BC_TRY(color.alloc(sizeof(int32_t) * N));
-    BC_TRY(mark.alloc(sizeof(uint32_t) * N));
-    BC_TRY(q0.alloc(sizeof(int32_t) * N));
-    BC_TRY(q1.alloc(sizeof(int32_t) * N));
-    BC_TRY(best.alloc(sizeof(unsigned long long)));
+    BC_TRY(comp.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(comp_next.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(color.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(mark.alloc_on(sizeof(uint32_t) * N, s));
+    BC_TRY(q0.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(q1.alloc_on(sizeof(int32_t) * N, s));
+    BC_TRY(best.alloc_on(sizeof(unsigned long long), s));
     int32_t* cp = comp.as<int32_t>();
     k_fill_i32<<<grid_for(n), kBlk, 0, s>>>(n, cp, -1);
     auto trim = [&](int passes) -> bc_status {
@@ -398,21 +398,21 @@ bc_status directed_reach(bc_graph* g) {
 
     // ---- condensation DAG and the alpha/omega recurrence
     DevBuf rootpos, cid, wsize, keys, keys2, dcnt, drp, dfill, dcol, alpha, omega, done;
-    BC_TRY(rootpos.alloc(sizeof(int32_t) * (N + 1)));
-    BC_TRY(cid.alloc(sizeof(int32_t) * N));
+    BC_TRY(rootpos.alloc_on(sizeof(int32_t) * (N + 1), s));
+    BC_TRY(cid.alloc_on(sizeof(int32_t) * N, s));
     k_is_root<<<grid_for(n), kBlk, 0, s>>>(n, cp, color.as<int32_t>());
     BC_TRY(cub_call([&](void* t, size_t& b) {
         return hipcub::DeviceScan::ExclusiveSum(t, b, color.as<int32_t>(), rootpos.as<int32_t>(), n, s);
-    }, tmp));
+    }, tmp, s));
     k_close<<<1, 1, 0, s>>>(rootpos.as<int32_t>(), n, color.as<int32_t>());
     int32_t nc = 0;
     BC_TRY(read_i32(rootpos.as<int32_t>() + n, &nc, s));
     const size_t NC = (size_t)(nc > 0 ? nc : 1);
-    BC_TRY(wsize.alloc(sizeof(uint32_t) * NC));
+    BC_TRY(wsize.alloc_on(sizeof(uint32_t) * NC, s));
     BC_HIP(hipMemsetAsync(wsize.p, 0, sizeof(uint32_t) * NC, s));
     k_cid<<<grid_for(n), kBlk, 0, s>>>(n, cp, rootpos.as<int32_t>(), cid.as<int32_t>(), wsize.as<uint32_t>());
-    BC_TRY(keys.alloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1)));
-    BC_TRY(keys2.alloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1)));
+    BC_TRY(keys.alloc_on(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1), s));
+    BC_TRY(keys2.alloc_on(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1), s));
     BC_HIP(hipMemsetAsync(fl + 3, 0, sizeof(int32_t), s));
     k_dag_arcs<<<grid_for(n), kBlk, 0, s>>>(n, rp, col, cid.as<int32_t>(), keys.as<uint64_t>(), fl + 3);
     int32_t na = 0;
@@ -420,25 +420,25 @@ bc_status directed_reach(bc_graph* g) {
     if (na > 0) {
         BC_TRY(cub_call([&](void* t, size_t& b) {
             return hipcub::DeviceRadixSort::SortKeys(t, b, keys.as<uint64_t>(), keys2.as<uint64_t>(), na, 0, 64, s);
-        }, tmp));
+        }, tmp, s));
     }
-    BC_TRY(dcnt.alloc(sizeof(int32_t) * NC));
-    BC_TRY(drp.alloc(sizeof(int32_t) * (NC + 1)));
-    BC_TRY(dfill.alloc(sizeof(int32_t) * NC));
-    BC_TRY(dcol.alloc(sizeof(int32_t) * (size_t)(na > 0 ? na : 1)));
+    BC_TRY(dcnt.alloc_on(sizeof(int32_t) * NC, s));
+    BC_TRY(drp.alloc_on(sizeof(int32_t) * (NC + 1), s));
+    BC_TRY(dfill.alloc_on(sizeof(int32_t) * NC, s));
+    BC_TRY(dcol.alloc_on(sizeof(int32_t) * (size_t)(na > 0 ? na : 1), s));
     BC_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(int32_t) * NC, s));
     BC_HIP(hipMemsetAsync(dfill.p, 0, sizeof(int32_t) * NC, s));
     if (na > 0) k_dag_count<<<grid_for(na), kBlk, 0, s>>>(na, keys2.as<uint64_t>(), dcnt.as<int32_t>());
     BC_TRY(cub_call([&](void* t, size_t& b) {
         return hipcub::DeviceScan::ExclusiveSum(t, b, dcnt.as<int32_t>(), drp.as<int32_t>(), nc, s);
-    }, tmp));
+    }, tmp, s));
     k_close<<<1, 1, 0, s>>>(drp.as<int32_t>(), nc, dcnt.as<int32_t>());
     if (na > 0)
         k_dag_fill<<<grid_for(na), kBlk, 0, s>>>(na, keys2.as<uint64_t>(), drp.as<int32_t>(), dfill.as<int32_t>(),
                                                  dcol.as<int32_t>());
-    BC_TRY(alpha.alloc(sizeof(uint64_t) * NC));
-    BC_TRY(omega.alloc(sizeof(uint64_t) * NC));
-    BC_TRY(done.alloc(sizeof(int32_t) * NC));
+    BC_TRY(alpha.alloc_on(sizeof(uint64_t) * NC, s));
+    BC_TRY(omega.alloc_on(sizeof(uint64_t) * NC, s));
+    BC_TRY(done.alloc_on(sizeof(int32_t) * NC, s));
     BC_HIP(hipMemsetAsync(done.p, 0, sizeof(int32_t) * NC, s));
     for (int32_t prev = nc + 1;;) {
         BC_HIP(hipMemsetAsync(fl, 0, sizeof(int32_t), s));

@@ -206,7 +206,12 @@ void lane_main(bc_server* S, int lane) {
         std::string err;
         if (upload) {
             bc_graph* g = nullptr;
-            rs = bc_graph_create(G->n, G->m, G->rp.data(), G->m ? G->col.data() : nullptr, G->flags, (void*)st, &g);
+            try {
+                rs = graph_create(G->n, G->m, G->rp.data(), G->m ? G->col.data() : nullptr, G->flags, st, true, &g);
+            } catch (...) {
+                set_error("internal error");
+                rs = BC_EDEVICE;
+            }
             if (rs != BC_OK) err = bc_last_error();
             lk.lock();
             G->loading = false;

@@ -102,7 +102,7 @@ struct TopKDev {
 struct Ctl {
     uint32_t d, flen, nlen, clen;  // level, frontier length, reached-list and reset-list counters
     uint32_t live, pull, chunk, done_blocks;
-    uint32_t stamp, pad0;
+    uint32_t stamp, ran;           // ran: a level kernel ran in this step (captured level steps)
     unsigned long long front_arcs, acc_arcs;
     unsigned long long active[4];
     uint32_t cnt_g[256];
@@ -729,6 +729,7 @@ __device__ void plain_level_epilogue(Ctl* C, SrcState* S, TopKDev T, QStats* st,
         if (C->pull) atomicAdd(&st->pull_levels, 1ull);
         C->d = d + 1;
         C->live = live;
+        C->ran = 1;
         C->chunk = 0;
         for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
         atomicAdd(&st->levels, 1ull);
@@ -738,9 +739,14 @@ __device__ void plain_level_epilogue(Ctl* C, SrcState* S, TopKDev T, QStats* st,
     }
 }
 
+// gated: a step of a captured level sequence, which runs only while a
+// source is live and the step's direction is push (the pull kernel of the
+// same step takes the other case).  Every thread reads the same control
+// words, written by kernels that finished before this one started.
 template <int WW>
 __global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
-                                                      QStats* st, int W) {
+                                                      QStats* st, int W, int gated) {
+    if (gated && (C->live == 0 || C->pull != 0)) return;
     __shared__ LdsExpand<WW> L;
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
@@ -779,7 +785,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, S
 // are new and counted here.
 template <int WW>
 __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
-                                                    QStats* st, int W) {
+                                                    QStats* st, int W, int gated) {
+    if (gated && (C->live == 0 || C->pull == 0)) return;
     using Lo = Layout<WW>;
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
@@ -849,7 +856,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Src
 }
 
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C) {
+__global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C, int gated) {
+    if (gated && C->ran == 0) return;
     clear_cur<WW>(P, P.qa, C->flen, blockIdx.x * kBlk, gridDim.x * kBlk);
 }
 
@@ -858,7 +866,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C) {
 // counter is idle between levels and counts finished workgroups here; the
 // done_blocks word counts the new frontier entries.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ctl* C, LevelParams lp) {
+__global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ctl* C, LevelParams lp, int gated) {
+    if (gated && C->ran == 0) return;
     __shared__ uint32_t s_last;
     __shared__ unsigned long long s_arcs;
     const int tid = threadIdx.x;
@@ -894,6 +903,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ct
     C->acc_arcs = 0;
     C->stamp = C->stamp + 1;
     C->chunk = 0;
+    C->ran = 0;
     __threadfence();
     C->done_blocks = 0;
 }
@@ -1543,6 +1553,16 @@ unsigned clamp_grid(int64_t work_items, int64_t cap) {
     return (unsigned)b;
 }
 
+// RAII owner of a captured graph and its executable.
+struct GraphHolder {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphHolder() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 // RAII pair of HIP events recorded on the query stream.
 struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
@@ -1609,6 +1629,77 @@ bc_status ensure_batched(Workspace& W_, const DevGraph& G, int want, hipStream_t
     return BC_OK;
 }
 
+// Level-synchronous batches over order[0, count), batches [0, nb), on the
+// plain slot of Wk (sized for WW words per node), adding their kernel time
+// to *ms.
+template <int WW>
+bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count, uint32_t nb, Workspace& Wk,
+                            TopKDev T, QStats* d_st, const LevelParams& lp, hipStream_t s, double* ms,
+                            int graph_levels) {
+    const int W = 64 * WW;
+    const int32_t n = G.n;
+    const int cus = device_cus();
+    if (Wk.ww != WW) {
+        Wk.plain_ready = false;
+        Wk.slots = 0;
+        Wk.ww = WW;
+    }
+    BC_TRY(ensure_plain<WW>(Wk, G, s));
+    SlotPtrs P{Wk.seen.as<uint64_t>(), Wk.qa.as<int32_t>(), Wk.qb.as<int32_t>(), Wk.clr.as<int32_t>()};
+    SrcState* S = Wk.srcs.as<SrcState>();
+    Ctl* C = Wk.ctl.as<Ctl>();
+    uint32_t* hctl = Wk.hctl;
+    // graph_levels > 0: capture that many gated level steps once and replay
+    // them, reading the control block once per replay instead of per level
+    GraphHolder gh;
+    if (graph_levels > 0 && nb > 0) {
+        if (!Wk.cap) BC_HIP(hipStreamCreateWithFlags(&Wk.cap, hipStreamNonBlocking));  // default priority
+        BC_HIP(hipStreamBeginCapture(Wk.cap, hipStreamCaptureModeThreadLocal));
+        for (int l = 0; l < graph_levels; ++l) {
+            k_plain_expand<WW><<<8 * cus, kBlk, 0, Wk.cap>>>(G, P, S, C, T, d_st, W, 1);
+            k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, Wk.cap>>>(G, P, S, C, T, d_st, W, 1);
+            k_plain_clearcur<WW><<<4 * cus, kBlk, 0, Wk.cap>>>(P, C, 1);
+            k_plain_build<WW><<<4 * cus, kBlk, 0, Wk.cap>>>(G, P, C, lp, 1);
+        }
+        const hipError_t ce = hipStreamEndCapture(Wk.cap, &gh.graph);
+        BC_HIP(ce);
+        BC_HIP(hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0));
+    }
+    EventPair ev;
+    BC_TRY(ev.create());
+    BC_HIP(hipEventRecord(ev.a, s));
+    for (uint32_t b = 0; b < nb; ++b) {
+        k_plain_init<WW><<<1, kBlk, 0, s>>>(G, ord, count, b, W, P, S, C, T, d_st);
+        for (;;) {
+            BC_HIP(hipMemcpyAsync(hctl, C, 64, hipMemcpyDeviceToHost, s));
+            BC_HIP(hipStreamSynchronize(s));
+            // control block words: d, flen, nlen, clen, live, pull, chunk, done, stamp, ran, front_arcs
+            const uint32_t flen = hctl[1], live = hctl[4], pull = hctl[5];
+            unsigned long long fa;
+            std::memcpy(&fa, hctl + 10, sizeof(fa));
+            if (!live) break;
+            if (gh.exec) {
+                BC_HIP(hipGraphLaunch(gh.exec, s));
+                continue;
+            }
+            if (pull) k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
+            else k_plain_expand<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
+            k_plain_clearcur<WW><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C, 0);
+            // reached nodes <= arcs out of the frontier (push) or n (pull)
+            const int64_t bound =
+                pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
+            k_plain_build<WW><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, C, lp, 0);
+        }
+        k_plain_clear<WW><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
+    }
+    BC_HIP(hipEventRecord(ev.b, s));
+    BC_HIP(hipGetLastError());
+    double t = 0;
+    BC_TRY(ev.ms(&t));
+    *ms += t;
+    return BC_OK;
+}
+
 template <int WW>
 bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_order, TopKDev T, QStats* d_st,
                  Workspace& Wk, int W, Timing& tm, hipStream_t s) {
@@ -1632,42 +1723,8 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         Wk.ww = WW;
     }
 
-    // level-synchronous batches over order[0, count), batches [0, nb)
     auto run_plain = [&](const int32_t* ord, int32_t count, uint32_t nb, double* ms) -> bc_status {
-        BC_TRY(ensure_plain<WW>(Wk, G, s));
-        SlotPtrs P{Wk.seen.as<uint64_t>(), Wk.qa.as<int32_t>(), Wk.qb.as<int32_t>(), Wk.clr.as<int32_t>()};
-        SrcState* S = Wk.srcs.as<SrcState>();
-        Ctl* C = Wk.ctl.as<Ctl>();
-        uint32_t* hctl = Wk.hctl;
-        EventPair ev;
-        BC_TRY(ev.create());
-        BC_HIP(hipEventRecord(ev.a, s));
-        for (uint32_t b = 0; b < nb; ++b) {
-            k_plain_init<WW><<<1, kBlk, 0, s>>>(G, ord, count, b, W, P, S, C, T, d_st);
-            for (;;) {
-                BC_HIP(hipMemcpyAsync(hctl, C, 64, hipMemcpyDeviceToHost, s));
-                BC_HIP(hipStreamSynchronize(s));
-                // control block words: d, flen, nlen, clen, live, pull, chunk, done, stamp, pad, front_arcs
-                const uint32_t flen = hctl[1], live = hctl[4], pull = hctl[5];
-                unsigned long long fa;
-                std::memcpy(&fa, hctl + 10, sizeof(fa));
-                if (!live) break;
-                if (pull) k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W);
-                else k_plain_expand<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W);
-                k_plain_clearcur<WW><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C);
-                // reached nodes <= arcs out of the frontier (push) or n (pull)
-                const int64_t bound =
-                    pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
-                k_plain_build<WW><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, C, lp);
-            }
-            k_plain_clear<WW><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
-        }
-        BC_HIP(hipEventRecord(ev.b, s));
-        BC_HIP(hipGetLastError());
-        double t = 0;
-        BC_TRY(ev.ms(&t));
-        *ms += t;
-        return BC_OK;
+        return run_plain_batches<WW>(G, ord, count, nb, Wk, T, d_st, lp, s, ms, o.graph_levels);
     };
 
     if (seed > 0) {
@@ -1719,8 +1776,20 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         BC_HIP(hipMemcpyAsync(&ndef, dcnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
         if (ndef > 0) {
-            // deferred sources, restarted level-synchronously against the final-ish threshold
-            BC_TRY(run_plain(Wk.defer.as<int32_t>(), (int32_t)ndef, (ndef + W - 1) / W, &tm.defer_ms));
+            // deferred sources, restarted level-synchronously against the
+            // final-ish threshold, in batches of defer_width sources
+            const int dw = o.defer_width > 0 ? o.defer_width : 256;
+            const int32_t* dl = Wk.defer.as<int32_t>();
+            const uint32_t dnb = (ndef + (uint32_t)dw - 1) / (uint32_t)dw;
+            if (dw == W) {
+                BC_TRY(run_plain(dl, (int32_t)ndef, dnb, &tm.defer_ms));
+            } else {
+                Workspace wide(s);
+                if (dw == 64) BC_TRY(run_plain_batches<1>(G, dl, (int32_t)ndef, dnb, wide, T, d_st, lp, s, &tm.defer_ms, o.graph_levels));
+                else if (dw == 128) BC_TRY(run_plain_batches<2>(G, dl, (int32_t)ndef, dnb, wide, T, d_st, lp, s, &tm.defer_ms, o.graph_levels));
+                else BC_TRY(run_plain_batches<4>(G, dl, (int32_t)ndef, dnb, wide, T, d_st, lp, s, &tm.defer_ms, o.graph_levels));
+                BC_HIP(hipStreamSynchronize(s));
+            }
         }
     }
     BC_HIP(hipStreamSynchronize(s));
@@ -1750,6 +1819,14 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
     }
     if (o.mode != BC_MODE_PLAIN && o.mode != BC_MODE_BATCHED) {
         set_error("unknown mode %d", o.mode);
+        return BC_EINVAL;
+    }
+    if (o.graph_levels < 0 || o.graph_levels > 64) {
+        set_error("graph_levels must be in [0, 64] (got %d)", o.graph_levels);
+        return BC_EINVAL;
+    }
+    if (o.defer_width != 0 && o.defer_width != 64 && o.defer_width != 128 && o.defer_width != 256) {
+        set_error("defer_width must be 0, 64, 128 or 256 (got %d)", o.defer_width);
         return BC_EINVAL;
     }
     const int32_t kk = std::min(k, n);

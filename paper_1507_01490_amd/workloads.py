@@ -9,6 +9,10 @@ are queried with).  Inputs only: no part of the method lives here.
           groups, Zipf(2.1) sizes capped at 200, seed 4; k = 10
   rgg     undirected random geometric graph, n = 4,000,000, average degree 6,
           seed 5; k = 10
+  serve512  serving mix: 512 graphs, n log-uniform in [1e3, 2e5], one third
+          each Erdos-Renyi (average degree 8), Barabasi-Albert (m = 4) and
+          2-D grid with 1 % random shortcuts; one request per graph with k
+          uniform in {1, 10, 100}; seed 3
 """
 
 from __future__ import annotations
@@ -24,6 +28,33 @@ DESCRIPTION = {
 }
 
 KS = {"ba2k": (1, 10), "ba1m": (1, 10, 100), "rmat21": (10,), "collab": (10,), "rgg": (10,)}
+DESCRIPTION["serve512"] = ("serving mix: 512 graphs n~logU[1e3,2e5] (ER deg 8 / BA m=4 / grid+1% shortcuts), "
+                           "k~U{1,10,100}, seed=3")
+
+
+def _serve_one(args):
+    i, fam, n, seed = args
+    if fam == 0:
+        return synth.erdos_renyi(n, 8.0, seed)
+    if fam == 1:
+        return synth.barabasi_albert(n, 4, seed)
+    return synth.grid_shortcuts(n, 0.01, seed)
+
+
+def serve_mix(count: int = 512, seed: int = 3, workers: int = 16):
+    """[(graph, k)] of the serving workload, generated in a process pool."""
+    import concurrent.futures as cf
+    import os
+
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(2e5), count)).astype(np.int64)
+    ks = rng.choice([1, 10, 100], count)
+    jobs = [(i, i % 3, int(sizes[i]), seed * 100000 + i) for i in range(count)]
+    nw = max(1, min(workers, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=nw) as ex:
+        graphs = list(ex.map(_serve_one, jobs, chunksize=8))
+    return [(g, int(k)) for g, k in zip(graphs, ks)]
 
 
 def build(name: str) -> synth.Csr:

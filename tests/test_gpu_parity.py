@@ -29,6 +29,11 @@ VARIANTS = [
     dict(mode="batched", width=256, slots=3),
     dict(mode="batched", width=64, defer_arcs=1),    # nearly every source re-run level-synchronously
     dict(mode="batched", width=128, defer_arcs=40, slots=5),
+    dict(mode="batched", width=64, defer_arcs=1, defer_width=64),    # deferred sources re-run 64 at a time
+    dict(mode="batched", width=256, defer_arcs=40, defer_width=128, slots=3),
+    dict(mode="plain", width=64, graph_levels=4),                     # captured level steps
+    dict(mode="batched", width=128, defer_arcs=40, graph_levels=3),
+    dict(mode="plain", width=256, pull_alpha=1e9, pull_beta=1e-9, graph_levels=2),
 ]
 
 

@@ -128,6 +128,9 @@ typedef struct bc_stats {
     uint64_t lds_levels;    /* persistent W = 64 levels run on the LDS tables            */
     uint64_t record_levels; /* persistent levels run on the global node records          */
     uint64_t spills;        /* batches moved from the LDS tables to the node records     */
+    double record_ms;       /* persistent W = 64 levels on the node records, summed over
+                               workgroups (part of phase_ms)                             */
+    uint64_t record_arcs;   /* arcs those levels scanned                                  */
 } bc_stats;
 
 /* Fill *opts with the defaults (plain mode, automatic order, W = 64, bottom-up

@@ -69,7 +69,7 @@ class Stats(ctypes.Structure):
                 ("persistent_discovered", ctypes.c_uint64), ("defer_ms", ctypes.c_double),
                 ("n_deferred", ctypes.c_uint64), ("phase_ms", ctypes.c_double * 5),
                 ("lds_levels", ctypes.c_uint64), ("record_levels", ctypes.c_uint64),
-                ("spills", ctypes.c_uint64)]
+                ("spills", ctypes.c_uint64), ("record_ms", ctypes.c_double), ("record_arcs", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}

@@ -4,6 +4,9 @@
 //   rp[n+1], col[m]        canonical out-CSR (rows sorted, no self-loops or repeats)
 //   irp[n+1], icol[m]      in-CSR (directed graphs; aliases the out-CSR otherwise)
 //   deg[n]   (u32)         out-degree
+//   adj[m]   (int2)        (col[e], deg[col[e]]): each arc with its target's
+//                          out-degree, so a level step that counts ~gamma reads
+//                          the degree in the same coalesced stream as the target
 //   x0[n], x1[n] (u32)     reach data: undirected x0 = x1 = r(v) (component size);
 //                          directed x0 = alpha(v), x1 = omega(v)
 #pragma once
@@ -48,6 +51,7 @@ struct DevGraph {
     const int32_t* irp;
     const int32_t* icol;
     const uint32_t* deg;
+    const int2* adj;
     const uint32_t* x0;
     const uint32_t* x1;
 };
@@ -147,7 +151,7 @@ struct Workspace {
 
 struct bc_graph {
     bc::DevGraph dg{};
-    bc::DevBuf rp, col, irp, icol, deg, x0, x1;
+    bc::DevBuf rp, col, irp, icol, deg, adj, x0, x1;
     bc::DevBuf order_deg;  // cached degree order (int32 n), built on first use
     bool have_order_deg = false;
     bc::DevBuf order_grp;  // cached grouped degree order

@@ -177,6 +177,16 @@ __global__ void k_uf_reach(int32_t n, const int32_t* __restrict__ label, const u
 
 // ---- orders
 
+// adj[e] = (col[e], deg[col[e]])
+__global__ void k_pack_adj(int64_t m, const int32_t* __restrict__ col, const uint32_t* __restrict__ deg,
+                           int2* __restrict__ adj) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        const int32_t w = col[e];
+        adj[e] = make_int2(w, (int32_t)deg[w]);
+    }
+}
+
 __global__ void k_degree_keys(int32_t n, const uint32_t* __restrict__ deg, uint64_t* __restrict__ key) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
@@ -337,6 +347,9 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
     BC_TRY(galloc(g, g->deg, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
     k_degree<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.rp, g->deg.as<uint32_t>());
     g->dg.deg = g->deg.as<uint32_t>();
+    BC_TRY(galloc(g, g->adj, sizeof(int2) * (size_t)(mc > 0 ? mc : 1), s));
+    if (mc > 0) k_pack_adj<<<grid_for(mc), kBlk, 0, s>>>(mc, g->dg.col, g->dg.deg, g->adj.as<int2>());
+    g->dg.adj = g->adj.as<int2>();
     BC_TRY(galloc(g, g->x0, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
     BC_TRY(galloc(g, g->x1, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), s));
     g->dg.x0 = g->x0.as<uint32_t>();

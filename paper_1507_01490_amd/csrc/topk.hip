@@ -75,6 +75,7 @@ struct QStats {
     unsigned long long frontier_entries, discovered, n_deferred;
     unsigned long long phase_ticks[5];  // persistent kernel: set-up, expand, cut, build, reset (100 MHz)
     unsigned long long lds_levels, record_levels, spills;  // LDS-table levels, node-record levels, moves
+    unsigned long long record_ticks, record_arcs;          // persistent levels on node records: time, arcs
 };
 
 // Sources handed from the persistent kernel to the level-synchronous kernels
@@ -1056,7 +1057,7 @@ constexpr int kCapNLog = 13;
 constexpr int kCapS = 1024;       // H_seen entries
 constexpr int kCapSLog = 10;
 constexpr uint32_t kPassCap = 4900;   // arcs per counting pass (H_next load <= 0.6)
-constexpr uint32_t kSeenCap = 700;    // H_seen entries allowed after a build (load <= 0.68)
+constexpr uint32_t kSeenCap = 760;    // H_seen entries allowed after a build (load <= 0.74)
 constexpr uint32_t kPassMax = 8;
 
 struct LdsTab {
@@ -1152,16 +1153,14 @@ __device__ inline uint64_t tab_visit(LdsTab& L, int32_t w, uint64_t m, uint32_t 
     return nb & ~old;
 }
 
-// One pass over the arcs of frontier F (slots of H_seen): targets of part p
-// whose live bits are not yet seen are ORed into H_next; with counting, the
-// bits a thread sets first add to gamma / tgamma.  Thread i holds frontier
-// entry i (flen <= kCapS <= B); the arcs are dealt out over the workgroup by
-// a scan of the degrees, each thread finding the owner of its arc by binary
-// search over the entries' first positions.
-template <bool kCount>
-__device__ void tab_pass(const DevGraph& G, LdsTab& L, const int32_t* F, uint32_t flen, uint64_t act, uint32_t P,
-                         uint32_t p, PassScratch& X, uint32_t* cg, unsigned long long* ct,
-                         unsigned long long* arcs, unsigned long long* entries) {
+// Per level: the arcs of the frontier entries of F (slots of H_seen) with
+// live bits in act, dealt out over the workgroup by a scan of their
+// degrees.  Thread i holds frontier entry i (flen <= kCapS <= B) and writes
+// its first arc position eoff, adjacency start ebeg and live bits em; the
+// arc total is returned to every thread.  Computed once per level and shared
+// by all passes of the level.
+__device__ uint32_t tab_prologue(const DevGraph& G, const LdsTab& L, const int32_t* F, uint32_t flen, uint64_t act,
+                                 PassScratch& X, unsigned long long* arcs, unsigned long long* entries) {
     constexpr int B = kLdsBlk;
     static_assert(kCapS <= B, "one thread per frontier entry");
     const int tid = threadIdx.x;
@@ -1177,7 +1176,7 @@ __device__ void tab_pass(const DevGraph& G, LdsTab& L, const int32_t* F, uint32_
             deg = (uint32_t)(G.rp[u + 1] - beg);
         }
     }
-    if (kCount && p == 0) {
+    if (entries) {
         const unsigned long long nlive = __ballot(deg != 0);
         if ((tid & 63) == 0 && nlive) atomicAdd(entries, (unsigned long long)__popcll(nlive));
     }
@@ -1186,20 +1185,58 @@ __device__ void tab_pass(const DevGraph& G, LdsTab& L, const int32_t* F, uint32_
     X.eoff[tid] = off;
     X.ebeg[tid] = beg;
     X.em[tid] = m;
-    if (kCount && p == 0 && tid == 0) *arcs += total;
+    if (arcs && tid == 0) *arcs += total;
     __syncthreads();
-    for (uint32_t a = tid; a < total; a += B) {
-            uint32_t lo = 0, hi = B;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (X.eoff[mid] <= a) lo = mid + 1; else hi = mid;
+    return total;
+}
+
+// One pass over the arcs [0, total) of the level prologue: targets of part
+// p whose live bits are not yet seen are ORed into H_next; with counting,
+// the bits a thread sets first add to gamma / tgamma (the target's degree
+// comes with the target from the packed adjacency).  Each thread takes arcs
+// tid, tid + B, ... (coalesced), finds the owner of each by binary search
+// over the entries' first positions, and issues the loads of kInflight arcs
+// before visiting any of them, so that one memory latency covers them all.
+template <bool kCount>
+__device__ void tab_arcs(const DevGraph& G, LdsTab& L, uint32_t total, uint32_t P, uint32_t p,
+                         const PassScratch& X, uint32_t* cg, unsigned long long* ct) {
+    constexpr int B = kLdsBlk;
+    constexpr int kInflight = 4;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t a0 = tid; a0 < total; a0 += kInflight * B) {
+        int32_t w[kInflight], dg[kInflight];
+        uint64_t m[kInflight];
+#pragma unroll
+        for (int u = 0; u < kInflight; ++u) {
+            const uint32_t a = a0 + (uint32_t)u * B;
+            m[u] = 0;
+            w[u] = 0;
+            dg[u] = 0;
+            if (a < total) {
+                uint32_t lo = 0, hi = B;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (X.eoff[mid] <= a) lo = mid + 1; else hi = mid;
+                }
+                const uint32_t i = lo - 1;
+                const int32_t e = X.ebeg[i] + (int32_t)(a - X.eoff[i]);
+                m[u] = X.em[i];
+                if (kCount) {
+                    const int2 wd = G.adj[e];
+                    w[u] = wd.x;
+                    dg[u] = wd.y;
+                } else {
+                    w[u] = G.col[e];
+                }
             }
-            const uint32_t i = lo - 1;
-        const int32_t w = G.col[X.ebeg[i] + (int32_t)(a - X.eoff[i])];
-        const uint64_t first = tab_visit(L, w, X.em[i], P, p);
-        if (kCount && first) count_new(first, 0, G.deg[w], cg, ct);
+        }
+#pragma unroll
+        for (int u = 0; u < kInflight; ++u) {
+            if (!m[u]) continue;
+            const uint64_t first = tab_visit(L, w[u], m[u], P, p);
+            if (kCount && first) count_new(first, 0, (uint32_t)dg[u], cg, ct);
+        }
     }
-    __syncthreads();
 }
 
 // Clear H_next after a counting pass.
@@ -1261,6 +1298,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     P.qb = base.qb + slot * (size_t)G.n;
     P.clr = base.clr + slot * (size_t)G.n;
     unsigned long long levels = 0, batches = 0, disc = 0, lds_lv = 0, rec_lv = 0, spills = 0;
+    unsigned long long rec_ticks = 0, rec_arcs = 0;
     unsigned long long ticks[5] = {0, 0, 0, 0, 0};
     tab_next_reset<B>(L);
     for (int i = tid; i < kCapS; i += B) {
@@ -1380,8 +1418,9 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 }
                 __syncthreads();
                 uint32_t distinct = 0;
+                const uint32_t tot = tab_prologue(G, L, F, flen, act, PX, &s_narcs, &s_ent);
                 for (uint32_t p = 0; p < np; ++p) {
-                    tab_pass<true>(G, L, F, flen, act, np, p, PX, cg, ct, &s_narcs, &s_ent);
+                    tab_arcs<true>(G, L, tot, np, p, PX, cg, ct);
                     __syncthreads();
                     tab_next_reset<B>(L);
                     __syncthreads();
@@ -1415,7 +1454,10 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 __syncthreads();
                 if (tid < 64 && ((lact >> tid) & 1ull)) atomicAdd(&L.tsum, (unsigned long long)cg[tid]);
                 __syncthreads();
-                const unsigned long long live_nodes = L.tsum;
+                // distinct nodes of the new level with a live bit: at most the
+                // pairs counted for the live sources, and at most the distinct
+                // targets the count passes inserted
+                const unsigned long long live_nodes = min(L.tsum, (unsigned long long)distinct);
                 if (L.sfill + live_nodes > kSeenCap) {
                     // the new level does not fit H_seen: build it on the global records
                     to_global(F, flen);
@@ -1442,8 +1484,9 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 int32_t* Fn = L.fl[cur ^ 1];
                 if (tid == 0) L.flen2 = 0;
                 __syncthreads();
+                const uint32_t tot2 = tab_prologue(G, L, F, flen, lact, PX, nullptr, nullptr);
                 for (uint32_t p = 0; p < np; ++p) {
-                    tab_pass<false>(G, L, F, flen, lact, np, p, PX, nullptr, nullptr, nullptr, nullptr);
+                    tab_arcs<false>(G, L, tot2, np, p, PX, nullptr, nullptr);
                     __syncthreads();
                     tab_build_pass<B>(L, Fn);
                     __syncthreads();
@@ -1464,6 +1507,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 tp = tq;
             } else {
                 // ---------------- global level (state on the node records)
+                const uint64_t tr0 = tp;
+                const unsigned long long ra0 = s_narcs;
                 ++stamp;
                 if (tid < kBlk) {
                     cg[tid] = 0;
@@ -1496,6 +1541,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 tq = __builtin_amdgcn_s_memrealtime();
                 ticks[3] += tq - tp;
                 tp = tq;
+                rec_ticks += tq - tr0;
+                rec_arcs += s_narcs - ra0;
             }
         }
         // reset the batch state: global records (when used) and the LDS tables
@@ -1523,6 +1570,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
         if (s_ent) atomicAdd(&st->frontier_entries, s_ent);
         for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], ticks[i]);
         atomicAdd(&st->lds_levels, lds_lv);
+        atomicAdd(&st->record_ticks, rec_ticks);
+        atomicAdd(&st->record_arcs, rec_arcs);
         atomicAdd(&st->record_levels, rec_lv);
         atomicAdd(&st->spills, spills);
     }
@@ -1985,6 +2034,8 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         o2.lds_levels = hst.lds_levels;
         o2.record_levels = hst.record_levels;
         o2.spills = hst.spills;
+        o2.record_ms = (double)hst.record_ticks / 1e5;
+        o2.record_arcs = hst.record_arcs;
         std::memcpy(st_out, &o2, std::min<size_t>(sz ? sz : sizeof(bc_stats), sizeof(bc_stats)));
     }
     return BC_OK;

@@ -82,7 +82,7 @@ def test_footprint_arithmetic():
     """The serving admission estimate (pure host arithmetic, no device call)."""
     n, m = 20000, 160000
     g, u, q_plain = bc.footprint(n, m, k=10, mode="plain")
-    assert g == 4 * (n + 1) + 4 * m + 36 * n
+    assert g == 4 * (n + 1) + 12 * m + 36 * n
     assert u == 12 * m + 40 * n + (1 << 20)
     per_slot = n * (8 * 4 + 12)
     _, _, q16 = bc.footprint(n, m, k=10, mode="batched", slots=16)

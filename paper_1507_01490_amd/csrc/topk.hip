@@ -1138,21 +1138,6 @@ struct PassScratch {
     uint32_t uscan[kLdsBlk / 64 + 1];
 };
 
-// Target w of an arc from a frontier entry with live bits m (one pass):
-// returns the bits this thread set first in H_next (0 if none).
-__device__ inline uint64_t tab_visit(LdsTab& L, int32_t w, uint64_t m, uint32_t P, uint32_t p) {
-    if (P > 1 && hpart(w, P) != p) return 0;
-    const uint64_t nb = m & ~tab_seen(L, w);
-    if (!nb) return 0;
-    const int slot = tab_next_claim(L, w);
-    if (slot < 0) {
-        L.over = 1u;
-        return 0;
-    }
-    const uint64_t old = atomicOr((unsigned long long*)&L.nmask[slot], (unsigned long long)nb);
-    return nb & ~old;
-}
-
 // Per level: the arcs of the frontier entries of F (slots of H_seen) with
 // live bits in act, dealt out over the workgroup by a scan of their
 // degrees.  Thread i holds frontier entry i (flen <= kCapS <= B) and writes
@@ -1190,22 +1175,59 @@ __device__ uint32_t tab_prologue(const DevGraph& G, const LdsTab& L, const int32
     return total;
 }
 
-// One pass over the arcs [0, total) of the level prologue: targets of part
-// p whose live bits are not yet seen are ORed into H_next; with counting,
-// the bits a thread sets first add to gamma / tgamma (the target's degree
-// comes with the target from the packed adjacency).  Each thread takes arcs
-// tid, tid + B, ... (coalesced), finds the owner of each by binary search
-// over the entries' first positions, and issues the loads of kInflight arcs
-// before visiting any of them, so that one memory latency covers them all.
-template <bool kCount>
-__device__ void tab_arcs(const DevGraph& G, LdsTab& L, uint32_t total, uint32_t P, uint32_t p,
+// Record-mode prologue: frontier entries [e0, e1) of the list F on the
+// node records (flen may exceed the workgroup), live bits from their cur
+// words.  Same outputs as tab_prologue for the chunk.
+__device__ uint32_t rec_prologue(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
+                                 uint64_t act, PassScratch& X, unsigned long long* arcs,
+                                 unsigned long long* entries) {
+    using Lo = Layout<1>;
+    constexpr int B = kLdsBlk;
+    const int tid = threadIdx.x;
+    const uint32_t e = e0 + (uint32_t)tid;
+    uint32_t deg = 0;
+    int32_t beg = 0;
+    uint64_t m = 0;
+    if (e < e1) {
+        const int32_t u = F[e];
+        m = P.ns[(size_t)u * Lo::SW + Lo::CUR] & act;
+        if (m) {
+            beg = G.rp[u];
+            deg = (uint32_t)(G.rp[u + 1] - beg);
+        }
+    }
+    if (entries) {
+        const unsigned long long nlive = __ballot(deg != 0);
+        if ((tid & 63) == 0 && nlive) atomicAdd(entries, (unsigned long long)__popcll(nlive));
+    }
+    uint32_t total;
+    const uint32_t off = block_exscan<B>(deg, X.uscan, &total);
+    X.eoff[tid] = off;
+    X.ebeg[tid] = beg;
+    X.em[tid] = m;
+    if (arcs && tid == 0) *arcs += total;
+    __syncthreads();
+    return total;
+}
+
+// One pass over the arcs [0, total) of a prologue: targets of part p whose
+// live bits are not yet seen are ORed into H_next; with counting, the bits
+// a thread sets first add to gamma / tgamma (the target's degree comes with
+// the target from the packed adjacency).  The seen bits come from H_seen,
+// or with kRec from the node records (ns), read without any global atomic.
+// Each thread takes arcs tid, tid + B, ... (coalesced), finds the owner of
+// each by binary search over the entries' first positions, and issues the
+// loads of kInflight arcs before visiting any of them, so that one memory
+// latency covers them all.
+template <bool kCount, bool kRec>
+__device__ void tab_arcs(const DevGraph& G, LdsTab& L, const uint64_t* ns, uint32_t total, uint32_t P, uint32_t p,
                          const PassScratch& X, uint32_t* cg, unsigned long long* ct) {
     constexpr int B = kLdsBlk;
     constexpr int kInflight = 4;
     const uint32_t tid = threadIdx.x;
     for (uint32_t a0 = tid; a0 < total; a0 += kInflight * B) {
         int32_t w[kInflight], dg[kInflight];
-        uint64_t m[kInflight];
+        uint64_t m[kInflight], sv[kInflight];
 #pragma unroll
         for (int u = 0; u < kInflight; ++u) {
             const uint32_t a = a0 + (uint32_t)u * B;
@@ -1232,8 +1254,22 @@ __device__ void tab_arcs(const DevGraph& G, LdsTab& L, uint32_t total, uint32_t 
         }
 #pragma unroll
         for (int u = 0; u < kInflight; ++u) {
+            if (P > 1 && m[u] && hpart(w[u], P) != p) m[u] = 0;
+            sv[u] = 0;
+            if (kRec && m[u]) sv[u] = ns[(size_t)w[u] * Layout<1>::SW];
+        }
+#pragma unroll
+        for (int u = 0; u < kInflight; ++u) {
             if (!m[u]) continue;
-            const uint64_t first = tab_visit(L, w[u], m[u], P, p);
+            const uint64_t nb = m[u] & ~(kRec ? sv[u] : tab_seen(L, w[u]));
+            if (!nb) continue;
+            const int slot = tab_next_claim(L, w[u]);
+            if (slot < 0) {
+                L.over = 1u;
+                continue;
+            }
+            const uint64_t old = atomicOr((unsigned long long*)&L.nmask[slot], (unsigned long long)nb);
+            const uint64_t first = nb & ~old;
             if (kCount && first) count_new(first, 0, (uint32_t)dg[u], cg, ct);
         }
     }
@@ -1420,7 +1456,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 uint32_t distinct = 0;
                 const uint32_t tot = tab_prologue(G, L, F, flen, act, PX, &s_narcs, &s_ent);
                 for (uint32_t p = 0; p < np; ++p) {
-                    tab_arcs<true>(G, L, tot, np, p, PX, cg, ct);
+                    tab_arcs<true, false>(G, L, nullptr, tot, np, p, PX, cg, ct);
                     __syncthreads();
                     tab_next_reset<B>(L);
                     __syncthreads();
@@ -1486,7 +1522,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 __syncthreads();
                 const uint32_t tot2 = tab_prologue(G, L, F, flen, lact, PX, nullptr, nullptr);
                 for (uint32_t p = 0; p < np; ++p) {
-                    tab_arcs<false>(G, L, tot2, np, p, PX, nullptr, nullptr);
+                    tab_arcs<false, false>(G, L, nullptr, tot2, np, p, PX, nullptr, nullptr);
                     __syncthreads();
                     tab_build_pass<B>(L, Fn);
                     __syncthreads();
@@ -1508,7 +1544,90 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
             } else {
                 // ---------------- global level (state on the node records)
                 const uint64_t tr0 = tp;
-                const unsigned long long ra0 = s_narcs;
+                const unsigned long long ra0 = s_narcs, en0 = s_ent;
+                const uint64_t act = s_act[0];
+                // When the level's arcs fit the LDS counting passes, count it in
+                // H_next with the seen bits read from the node records (no global
+                // atomics); the records take the level only if a source survives.
+                if (tid == 0) L.tsum = 0;
+                __syncthreads();
+                {
+                    unsigned long long tl = 0;
+                    for (uint32_t e = tid; e < flen; e += B) {
+                        const int32_t u = P.qa[e];
+                        if (P.ns[(size_t)u * Lo::SW + Lo::CUR] & act) tl += G.deg[u];
+                    }
+                    if (tl) atomicAdd(&L.tsum, tl);
+                }
+                __syncthreads();
+                const unsigned long long Tarcs = L.tsum;
+                const uint32_t npass = (uint32_t)((Tarcs + kPassCap - 1) / kPassCap);
+                bool hybrid = false;
+                if (npass <= kPassMax) {
+                    const uint32_t np = npass > 0 ? npass : 1;
+                    if (tid < kBlk) {
+                        cg[tid] = 0;
+                        ct[tid] = 0;
+                    }
+                    if (tid == 0) {
+                        L.nins = 0;
+                        L.over = 0;
+                    }
+                    __syncthreads();
+                    for (uint32_t p = 0; p < np; ++p) {
+                        for (uint32_t e0 = 0; e0 < flen; e0 += B) {
+                            const uint32_t tot = rec_prologue(G, P, P.qa, e0, min(flen, e0 + B), act, PX,
+                                                              p == 0 ? &s_narcs : nullptr,
+                                                              p == 0 ? &s_ent : nullptr);
+                            tab_arcs<true, true>(G, L, P.ns, tot, np, p, PX, cg, ct);
+                            __syncthreads();
+                        }
+                        tab_next_reset<B>(L);
+                        __syncthreads();
+                    }
+                    hybrid = L.over == 0u;
+                    if (!hybrid && tid == 0) {
+                        s_narcs = ra0;  // recounted below
+                        s_ent = en0;
+                    }
+                    __syncthreads();
+                }
+                if (hybrid) {
+                    disc += L.nins;
+                    ++rec_lv;
+                    uint64_t tq = __builtin_amdgcn_s_memrealtime();
+                    ticks[1] += tq - tp;
+                    tp = tq;
+                    ++d;
+                    ++levels;
+                    live = cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
+                    tq = __builtin_amdgcn_s_memrealtime();
+                    ticks[2] += tq - tp;
+                    tp = tq;
+                    if (live) {
+                        // materialise the level for the surviving sources
+                        ++stamp;
+                        if (tid == 0) s_nlen = 0;
+                        __syncthreads();
+                        for (uint32_t e0 = 0; e0 < flen; e0 += B)
+                            expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp,
+                                                 LE, nullptr, nullptr, &s_arcs, &s_arcs);
+                        __syncthreads();
+                        const uint32_t nlen = s_nlen;
+                        clear_cur<1>(P, P.qa, flen, 0, B);
+                        if (tid == 0) s_flen = 0;
+                        __syncthreads();
+                        build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs);
+                        __syncthreads();
+                        flen = s_flen;
+                    }
+                    tq = __builtin_amdgcn_s_memrealtime();
+                    ticks[3] += tq - tp;
+                    tp = tq;
+                    rec_ticks += tq - tr0;
+                    rec_arcs += s_narcs - ra0;
+                    continue;
+                }
                 ++stamp;
                 if (tid < kBlk) {
                     cg[tid] = 0;

@@ -91,7 +91,9 @@ typedef struct bc_opts {
                                than this leaves its workgroup batch and is re-run by the
                                level-synchronous kernels afterwards (0 = 65536, -1 = never) */
     int32_t lds_tables;     /* BC_MODE_BATCHED, W = 64: keep small batch states in LDS
-                               hash tables (0 = yes, -1 = always use the node records)   */
+                               hash tables (0 = yes, -1 = always use the node records,
+                               1 = move every batch to the records after its first level,
+                               a testing aid for the record path)                       */
     int32_t defer_width;    /* BC_MODE_BATCHED: sources per batch of the re-run of deferred
                                sources, 64, 128 or 256 (0 = 256)                         */
     const float* mlp;       /* BC_ORDER_LEARNED: host, BC_MLP_PARAMS floats              */

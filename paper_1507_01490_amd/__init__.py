@@ -249,7 +249,7 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
     o.seed_batches = int(seed_batches)
     o.defer_arcs = int(defer_arcs)
     o.chunk = int(chunk)
-    o.lds_tables = 0 if lds_tables else -1
+    o.lds_tables = 1 if lds_tables == "spill" else (0 if lds_tables else -1)
     o.defer_width = int(defer_width)
     if graph_levels is not None:
         o.graph_levels = int(graph_levels)

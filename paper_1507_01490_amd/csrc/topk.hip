@@ -34,6 +34,7 @@
 // the true k-th best, and a stale one only weakens the cut (the shared value
 // of the parallel loop, Section 2.1), so results never change.
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 
 #include "bc_internal.h"
@@ -229,6 +230,20 @@ __device__ inline bool cut_rule(const SrcState& s, uint32_t d, const ThRec& th) 
 }
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// Seen filter of a batch on the node records: one bit per hashed node id
+// (2^17 bits in LDS), set for every node that has a seen bit in the records.
+// A clear bit proves the node unseen, so its record need not be read.
+constexpr uint32_t kFiltBits = 1u << 17;
+__device__ inline uint32_t filter_hash(int32_t w) { return ((uint32_t)w * 0x9E3779B1u) >> 15; }
+__device__ inline void filter_set(uint32_t* f, int32_t w) {
+    const uint32_t h = filter_hash(w);
+    atomicOr(&f[h >> 5], 1u << (h & 31));
+}
+__device__ inline bool filter_maybe(const uint32_t* f, int32_t w) {
+    const uint32_t h = filter_hash(w);
+    return (f[h >> 5] >> (h & 31)) & 1u;
+}
 
 // Wave-aggregated append of w to list[] when `app` holds.
 __device__ inline void append_if(bool app, int32_t w, int32_t* list, uint32_t* ctr) {
@@ -441,7 +456,7 @@ __device__ inline void clear_cur(const SlotPtrs& P, const int32_t* F, uint32_t l
 template <int WW>
 __device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t first, uint32_t stride,
                             const uint64_t* act, bool any_live, int32_t* F, uint32_t* fctr, uint32_t* clen,
-                            unsigned long long* arcs) {
+                            unsigned long long* arcs, uint32_t* seen_filter = nullptr) {
     using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     unsigned long long my_arcs = 0;
@@ -475,6 +490,7 @@ __device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, u
                     keep = true;
                     fresh = old_any == 0ull;
                     my_arcs += (uint32_t)(rec[Lo::META] >> 32);
+                    if (seen_filter) filter_set(seen_filter, w);
                 }
             }
         }
@@ -1068,7 +1084,12 @@ struct LdsTab {
     int32_t fl[2][kCapS];   // frontier lists: slots of H_seen
     uint32_t nins, sfill, flen2, over;
     unsigned long long tsum;
+    // record mode leaves H_seen unused: sseen and scur (contiguous) hold the
+    // seen filter there
+    __device__ uint32_t* filter() { return reinterpret_cast<uint32_t*>(sseen); }
 };
+static_assert(offsetof(LdsTab, scur) == offsetof(LdsTab, sseen) + sizeof(uint64_t) * kCapS, "filter layout");
+static_assert(2 * sizeof(uint64_t) * kCapS * 8 >= kFiltBits, "filter fits sseen and scur");
 
 __device__ inline uint32_t hmix(int32_t w) { return (uint32_t)w * 2654435761u; }
 __device__ inline uint32_t hpart(int32_t w, uint32_t P) { return (((uint32_t)w * 0x85EBCA77u) >> 8) % P; }
@@ -1221,9 +1242,10 @@ __device__ uint32_t rec_prologue(const DevGraph& G, const SlotPtrs& P, const int
 // latency covers them all.
 template <bool kCount, bool kRec>
 __device__ void tab_arcs(const DevGraph& G, LdsTab& L, const uint64_t* ns, uint32_t total, uint32_t P, uint32_t p,
-                         const PassScratch& X, uint32_t* cg, unsigned long long* ct) {
+                         const PassScratch& X, uint32_t* cg, unsigned long long* ct,
+                         const uint32_t* seen_filter = nullptr) {
     constexpr int B = kLdsBlk;
-    constexpr int kInflight = 4;
+    constexpr int kInflight = 2;
     const uint32_t tid = threadIdx.x;
     for (uint32_t a0 = tid; a0 < total; a0 += kInflight * B) {
         int32_t w[kInflight], dg[kInflight];
@@ -1256,7 +1278,7 @@ __device__ void tab_arcs(const DevGraph& G, LdsTab& L, const uint64_t* ns, uint3
         for (int u = 0; u < kInflight; ++u) {
             if (P > 1 && m[u] && hpart(w[u], P) != p) m[u] = 0;
             sv[u] = 0;
-            if (kRec && m[u]) sv[u] = ns[(size_t)w[u] * Layout<1>::SW];
+            if (kRec && m[u] && filter_maybe(seen_filter, w[u])) sv[u] = ns[(size_t)w[u] * Layout<1>::SW];
         }
 #pragma unroll
         for (int u = 0; u < kInflight; ++u) {
@@ -1308,7 +1330,7 @@ __device__ inline void tab_build_pass(LdsTab& L, int32_t* Fn) {
 template <int WW>
 __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32_t* order, int W,
                                                         uint32_t nbatches, uint32_t* next_batch, SlotPtrs base,
-                                                        TopKDev T, QStats* st, DeferList D) {
+                                                        TopKDev T, QStats* st, DeferList D, int force_spill) {
     static_assert(WW == 1, "LDS-resident batches hold 64 sources");
     using Lo = Layout<1>;
     constexpr int B = kLdsBlk;
@@ -1373,6 +1395,10 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
             L.sfill = 0;
             s_mode = 1;
         }
+        __syncthreads();
+        // every node just written to the records is on the reset list
+        const uint32_t nc = s_clen;
+        for (uint32_t i = tid; i < nc; i += B) filter_set(L.filter(), P.clr[i]);
         __syncthreads();
     };
 
@@ -1494,7 +1520,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 // pairs counted for the live sources, and at most the distinct
                 // targets the count passes inserted
                 const unsigned long long live_nodes = min(L.tsum, (unsigned long long)distinct);
-                if (L.sfill + live_nodes > kSeenCap) {
+                if (force_spill || L.sfill + live_nodes > kSeenCap) {
                     // the new level does not fit H_seen: build it on the global records
                     to_global(F, flen);
                     if (tid == 0) s_nlen = 0;
@@ -1508,7 +1534,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     clear_cur<1>(P, P.qa, flen, 0, B);
                     if (tid == 0) s_flen = 0;
                     __syncthreads();
-                    build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs);
+                    build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs, L.filter());
                     __syncthreads();
                     flen = s_flen;
                     tq = __builtin_amdgcn_s_memrealtime();
@@ -1579,7 +1605,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                             const uint32_t tot = rec_prologue(G, P, P.qa, e0, min(flen, e0 + B), act, PX,
                                                               p == 0 ? &s_narcs : nullptr,
                                                               p == 0 ? &s_ent : nullptr);
-                            tab_arcs<true, true>(G, L, P.ns, tot, np, p, PX, cg, ct);
+                            tab_arcs<true, true>(G, L, P.ns, tot, np, p, PX, cg, ct, L.filter());
                             __syncthreads();
                         }
                         tab_next_reset<B>(L);
@@ -1617,7 +1643,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         clear_cur<1>(P, P.qa, flen, 0, B);
                         if (tid == 0) s_flen = 0;
                         __syncthreads();
-                        build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs);
+                        build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs,
+                                       L.filter());
                         __syncthreads();
                         flen = s_flen;
                     }
@@ -1654,7 +1681,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 clear_cur<1>(P, P.qa, flen, 0, B);
                 if (tid == 0) s_flen = 0;
                 __syncthreads();
-                build_level<1>(P, P.qb, nlen, 0, B, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs);
+                build_level<1>(P, P.qb, nlen, 0, B, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs,
+                               L.filter());
                 __syncthreads();
                 flen = s_flen;
                 tq = __builtin_amdgcn_s_memrealtime();
@@ -1928,7 +1956,7 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         if constexpr (WW == 1) {
             if (o.lds_tables >= 0)
                 k_batched_lds<1><<<slots, kLdsBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
-                                                           T, d_st, D);
+                                                           T, d_st, D, o.lds_tables == 1 ? 1 : 0);
             else
                 k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), chunk, base,
                                                       Wk.slot_stamp.as<uint32_t>(), T, d_st, D);

@@ -24,6 +24,7 @@ VARIANTS = [
     dict(mode="plain", width=256, pull_alpha=14.0),
     dict(mode="batched", width=64),
     dict(mode="batched", width=64, lds_tables=False),
+    dict(mode="batched", width=64, lds_tables="spill"),              # every batch continues on the node records
     dict(mode="batched", width=64, seed_batches=0, slots=7),
     dict(mode="batched", width=128, seed_batches=0),
     dict(mode="batched", width=256, slots=3),

@@ -101,7 +101,9 @@ typedef struct bc_opts {
                                a HIP graph and replay it, checking for live sources once
                                per replay (0, the default: one host round trip per level,
                                which measures faster on gfx950)                          */
-    int32_t reserved;
+    int32_t seed_width;     /* BC_MODE_BATCHED: sources per seed batch, a multiple of width
+                               up to 256 (0 = width, or 256 when k > width);
+                               seed_batches counts these batches                         */
 } bc_opts;
 
 typedef struct bc_stats {

@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("defer_arcs", ctypes.c_int32),
                 ("lds_tables", ctypes.c_int32), ("defer_width", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("graph_levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph_levels", ctypes.c_int32), ("seed_width", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -233,7 +233,7 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
 
 def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=14.0, pull_beta=24.0,
               slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None, defer_width=0,
-              graph_levels=None) -> Opts:
+              graph_levels=None, seed_width=0) -> Opts:
     """bc_opts for a graph of n nodes; host arrays the options point at are
     appended to `keep` (they must outlive the call that reads them)."""
     lib = load_library()
@@ -251,6 +251,7 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
     o.chunk = int(chunk)
     o.lds_tables = 1 if lds_tables == "spill" else (0 if lds_tables else -1)
     o.defer_width = int(defer_width)
+    o.seed_width = int(seed_width)
     if graph_levels is not None:
         o.graph_levels = int(graph_levels)
     if isinstance(order, str) and order in ("learned", "learned_grouped"):
@@ -395,7 +396,8 @@ class Graph:
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
              pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
              seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
-             lds_tables: bool = True, mlp=None, defer_width: int = 0, graph_levels=None) -> TopK:
+             lds_tables: bool = True, mlp=None, defer_width: int = 0, graph_levels=None,
+             seed_width: int = 0) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
         order: None (automatic), "degree", "grouped", "learned" (the order
@@ -407,6 +409,7 @@ class Graph:
         o = self._opts(mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
                        lds_tables, mlp, keep)
         o.defer_width = int(defer_width)
+        o.seed_width = int(seed_width)
         if graph_levels is not None:
             o.graph_levels = int(graph_levels)
         kk = max(1, int(k))

@@ -1896,6 +1896,23 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
     return BC_OK;
 }
 
+// Seed batches of the batched mode: their width sw (a multiple of W; 0 in
+// the options = W, or 256 when k > W: one wide level-synchronous batch costs
+// less than several narrow ones and holds more of the deepest sources) and
+// count (default ceil(k / sw), so that k sources complete before the
+// persistent phase and the k-th best value exists).
+struct SeedPlan {
+    int sw;
+    uint32_t batches;  // of width sw
+};
+SeedPlan seed_plan(const bc_opts& o, int32_t k, int32_t n, int W) {
+    int sw = o.seed_width > 0 ? o.seed_width : (k > W ? 256 : W);
+    if (sw < W || sw % W != 0) sw = W;
+    const int64_t nb = ((int64_t)n + sw - 1) / sw;
+    const int64_t sb = o.seed_batches >= 0 ? o.seed_batches : ((int64_t)k + sw - 1) / sw;
+    return SeedPlan{sw, (uint32_t)std::min<int64_t>(std::max<int64_t>(sb, 0), nb)};
+}
+
 template <int WW>
 bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_order, TopKDev T, QStats* d_st,
                  Workspace& Wk, int W, Timing& tm, hipStream_t s) {
@@ -1905,10 +1922,11 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
     const size_t N = (size_t)n;
     const uint32_t nbatches = (uint32_t)((n + W - 1) / W);
     const bool batched = o.mode == BC_MODE_BATCHED;
-    uint32_t seed = nbatches;
+    uint32_t seed = nbatches;  // first batch (of width W) of the persistent phase
+    SeedPlan sp{W, 0};
     if (batched) {
-        int64_t sb = o.seed_batches >= 0 ? o.seed_batches : ((int64_t)k + W - 1) / W;
-        seed = (uint32_t)std::min<int64_t>(std::max<int64_t>(sb, 0), nbatches);
+        sp = seed_plan(o, k, n, W);
+        seed = (uint32_t)std::min<int64_t>((int64_t)sp.batches * (sp.sw / W), nbatches);
     }
     LevelParams lp{o.pull_alpha, o.pull_beta > 0.f ? o.pull_beta : 24.f, o.pull_alpha > 0.f ? 1 : 0};
     const int cus = device_cus();
@@ -1923,8 +1941,19 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         return run_plain_batches<WW>(G, ord, count, nb, Wk, T, d_st, lp, s, ms, o.graph_levels);
     };
 
+    if (!batched && seed > 0) BC_TRY(run_plain(d_order, n, seed, &tm.seed_ms));
+    if (batched && sp.batches > 0) {
+        if (sp.sw == W) {
+            BC_TRY(run_plain(d_order, n, sp.batches, &tm.seed_ms));
+        } else {
+            // wider seed batches: the first sp.batches * sp.sw sources of the order
+            Workspace wide(s);
+            if (sp.sw == 128) BC_TRY(run_plain_batches<2>(G, d_order, n, sp.batches, wide, T, d_st, lp, s, &tm.seed_ms, o.graph_levels));
+            else BC_TRY(run_plain_batches<4>(G, d_order, n, sp.batches, wide, T, d_st, lp, s, &tm.seed_ms, o.graph_levels));
+            BC_HIP(hipStreamSynchronize(s));
+        }
+    }
     if (seed > 0) {
-        BC_TRY(run_plain(d_order, n, seed, &tm.seed_ms));
         BC_HIP(hipMemcpyAsync(&tm.seed_stats, d_st, sizeof(QStats), hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
     }
@@ -2021,6 +2050,10 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         set_error("graph_levels must be in [0, 64] (got %d)", o.graph_levels);
         return BC_EINVAL;
     }
+    if (o.seed_width != 0 && o.seed_width != 64 && o.seed_width != 128 && o.seed_width != 256) {
+        set_error("seed_width must be 0, 64, 128 or 256 (got %d)", o.seed_width);
+        return BC_EINVAL;
+    }
     if (o.defer_width != 0 && o.defer_width != 64 && o.defer_width != 128 && o.defer_width != 256) {
         set_error("defer_width must be 0, 64, 128 or 256 (got %d)", o.defer_width);
         return BC_EINVAL;
@@ -2056,8 +2089,8 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
             if (ord == BC_ORDER_LEARNED) {
                 BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
             } else {
-                const int64_t sb = o.seed_batches >= 0 ? o.seed_batches : ((int64_t)kk + W - 1) / W;
-                const int64_t head = std::min<int64_t>((int64_t)n, sb * W);
+                const SeedPlan sp = seed_plan(o, kk, n, W);
+                const int64_t head = std::min<int64_t>((int64_t)n, (int64_t)sp.batches * sp.sw);
                 BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order, s));
             }
         } else {

@@ -25,6 +25,8 @@ VARIANTS = [
     dict(mode="batched", width=64),
     dict(mode="batched", width=64, lds_tables=False),
     dict(mode="batched", width=64, lds_tables="spill"),              # every batch continues on the node records
+    dict(mode="batched", width=64, seed_width=256),                  # wider seed batches
+    dict(mode="batched", width=128, seed_width=256, seed_batches=2),
     dict(mode="batched", width=64, seed_batches=0, slots=7),
     dict(mode="batched", width=128, seed_batches=0),
     dict(mode="batched", width=256, slots=3),

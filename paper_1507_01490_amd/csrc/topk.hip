@@ -569,23 +569,44 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
             if (nt) atomicAdd(&st->n_trivial, (unsigned long long)nt);
             if (mv) atomicAdd(&st->m_vis, mv);
         } else if (any) {
-            if (locked) lock_acquire(T.lock);
+            // A completed source whose key is not above a published k-th
+            // record can never enter (the k-th best value only grows): drop
+            // it without the lock, so that the lock is taken only by sources
+            // that may enter (most completions, e.g. trivial sources, never do).
+            ThRec th0;
+            const bool have0 = load_threshold(T, &th0);
+            bool need = false;
             for (int j = 0; j < W; ++j) {
                 if (!s_flags[j]) continue;
                 const SrcState& s = S[j];
-                if (s.status == S_TRIVIAL) {
-                    topk_insert(T, 0, 1, 0, s.id, 1);
-                    ++nt;
-                } else {
-                    const uint64_t r = s.nd;
-                    const uint64_t A = r <= 1 ? 0 : (r - 1) * (r - 1);
-                    const uint64_t F = r <= 1 ? 1 : s.fd;
-                    topk_insert(T, A, F, s.fd, s.id, (uint32_t)r);
+                const bool triv = s.status == S_TRIVIAL;
+                const uint64_t r = triv ? 1 : s.nd;
+                const uint64_t A = r <= 1 ? 0 : (r - 1) * (r - 1);
+                const uint64_t F = r <= 1 ? 1 : s.fd;
+                if (triv) ++nt;
+                else {
                     ++nd;
                     mv += s.mvis;
                 }
+                if (have0 && !key_gt(A, F, s.id, th0.A, th0.F, (int32_t)th0.id)) s_flags[j] = 0;
+                else need = true;
             }
-            if (locked) lock_release(T.lock);
+            if (need) {
+                if (locked) lock_acquire(T.lock);
+                for (int j = 0; j < W; ++j) {
+                    if (!s_flags[j]) continue;
+                    const SrcState& s = S[j];
+                    if (s.status == S_TRIVIAL) {
+                        topk_insert(T, 0, 1, 0, s.id, 1);
+                    } else {
+                        const uint64_t r = s.nd;
+                        const uint64_t A = r <= 1 ? 0 : (r - 1) * (r - 1);
+                        const uint64_t F = r <= 1 ? 1 : s.fd;
+                        topk_insert(T, A, F, s.fd, s.id, (uint32_t)r);
+                    }
+                }
+                if (locked) lock_release(T.lock);
+            }
             if (nd) atomicAdd(&st->n_done, (unsigned long long)nd);
             if (nt) atomicAdd(&st->n_trivial, (unsigned long long)nt);
             if (mv) atomicAdd(&st->m_vis, mv);

@@ -32,6 +32,16 @@ DESCRIPTION["serve512"] = ("serving mix: 512 graphs n~logU[1e3,2e5] (ER deg 8 / 
                            "k~U{1,10,100}, seed=3")
 
 
+def cpu_sample(name: str):
+    """(graph, description) of the bounded sample the CPU oracle is timed on
+    when the full workload takes it much longer than ~30 s: the same
+    generator at a smaller size.  None when the full workload is the sample."""
+    if name == "rmat21":
+        return (synth.rmat(18, 16, 0.57, 0.19, 0.19, 2),
+                "directed R-MAT scale=18 edge_factor=16 (0.57,0.19,0.19,0.05) dedup seed=2, same generator")
+    return None
+
+
 def _serve_one(args):
     i, fam, n, seed = args
     if fam == 0:

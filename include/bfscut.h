@@ -231,11 +231,12 @@ bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, ui
  * bc_autotune -- pick the batched-mode execution knobs for one graph and k.
  *
  * None of the knobs changes the answer, only the time.  Starting from
- * `base` (NULL: defaults) in BC_MODE_BATCHED, the tuner runs the query and
- * tries, one knob at a time around the best setting so far: width (64, 128,
- * 256), defer_arcs (16384, 65536, 262144), defer_width (64, 256),
- * pull_alpha (never, 14, 40), slots (128, 256, 512) and order (grouped,
- * degree).  Each setting is timed as the best of `repeats` runs after one
+ * `base` (NULL: defaults) in BC_MODE_BATCHED, the tuner runs the query over
+ * a grid of width (64, 128, 256) x defer_arcs (16384, 65536, 262144, never),
+ * then tries one knob at a time around the best setting so far:
+ * defer_width (64, 256), pull_alpha (never, 14, 40), slots (128, 256, 512)
+ * and order (grouped, degree).  Each setting is timed as the best of
+ * `repeats` runs after one
  * warm-up.  Every run must return exactly the first run's top-k, else
  * BC_EDEVICE.  *best receives the fastest setting; report (may be NULL) the
  * trial count and the times of the base and best settings.

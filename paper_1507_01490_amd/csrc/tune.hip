@@ -1,9 +1,10 @@
 // Autotuner of the execution knobs.  None of them changes the answer
 // (Algorithm 1 is exact for every batching, width, direction policy and
 // threshold history); they only change the time.  The tuner runs the real
-// query with k and tries one knob at a time around the best setting so far
-// (coordinate descent): width, deferral budget, deferred-batch width,
-// bottom-up threshold, persistent slots and source order.  Every trial must
+// query with k: first a grid over width and deferral budget (they interact:
+// a wide batch can take deep sources a narrow one must defer), then one knob
+// at a time around the best setting (coordinate descent): deferred-batch
+// width, bottom-up threshold, persistent slots and source order.  Every trial must
 // return exactly the first trial's result, which makes tuning a self-check.
 #include <chrono>
 #include <cstring>
@@ -82,6 +83,24 @@ extern "C" bc_status bc_autotune(bc_graph* g, int32_t k, const bc_opts* base, in
         double cur_ms = 0;
         BC_TRY(measure(cur, &cur_ms));
         default_ms = cur_ms;
+        // width and deferral budget interact (a wide batch can take deep
+        // sources that a narrow one must defer): search them as a grid
+        {
+            const bc_opts base_o = cur;
+            for (int w : {64, 128, 256})
+                for (int da : {16384, 65536, 262144, -1}) {
+                    bc_opts t = base_o;
+                    t.width = w;
+                    t.defer_arcs = da;
+                    if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
+                    double ms = 0;
+                    BC_TRY(measure(t, &ms));
+                    if (ms < cur_ms) {
+                        cur = t;
+                        cur_ms = ms;
+                    }
+                }
+        }
         using Setter = std::function<void(bc_opts&, int)>;
         struct Knob {
             std::vector<int> values;
@@ -89,8 +108,6 @@ extern "C" bc_status bc_autotune(bc_graph* g, int32_t k, const bc_opts* base, in
         };
         const int cus = 256;
         std::vector<Knob> knobs = {
-            {{64, 128, 256}, [](bc_opts& o, int v) { o.width = v; }},
-            {{16384, 65536, 262144}, [](bc_opts& o, int v) { o.defer_arcs = v; }},
             {{64, 256}, [](bc_opts& o, int v) { o.defer_width = v; }},
             {{0, 14, 40}, [](bc_opts& o, int v) { o.pull_alpha = (float)v; }},
             {{cus / 2, cus, 2 * cus}, [](bc_opts& o, int v) { o.slots = v; }},

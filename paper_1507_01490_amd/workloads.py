@@ -9,6 +9,8 @@ are queried with).  Inputs only: no part of the method lives here.
           groups, Zipf(2.1) sizes capped at 200, seed 4; k = 10
   rgg     undirected random geometric graph, n = 4,000,000, average degree 6,
           seed 5; k = 10
+  rgg18   the same random geometric family at n = 2^18 (the size the oracle
+          and the GPU finish in minutes; n = 4M needs ~2e13 visited arcs)
   serve512  serving mix: 512 graphs, n log-uniform in [1e3, 2e5], one third
           each Erdos-Renyi (average degree 8), Barabasi-Albert (m = 4) and
           2-D grid with 1 % random shortcuts; one request per graph with k
@@ -20,6 +22,7 @@ from __future__ import annotations
 from . import synth
 
 DESCRIPTION = {
+    "rgg18": "undirected random geometric graph n=262144 avg_deg=6 seed=5",
     "ba2k": "undirected Barabasi-Albert n=2000 m=5 seed=0",
     "ba1m": "undirected Barabasi-Albert n=1000000 m=5 seed=1",
     "rmat21": "directed R-MAT scale=21 edge_factor=16 (0.57,0.19,0.19,0.05) dedup seed=2",
@@ -27,7 +30,7 @@ DESCRIPTION = {
     "rgg": "undirected random geometric graph n=4000000 avg_deg=6 seed=5",
 }
 
-KS = {"ba2k": (1, 10), "ba1m": (1, 10, 100), "rmat21": (10,), "collab": (10,), "rgg": (10,)}
+KS = {"ba2k": (1, 10), "ba1m": (1, 10, 100), "rmat21": (10,), "collab": (10,), "rgg": (10,), "rgg18": (10,)}
 DESCRIPTION["serve512"] = ("serving mix: 512 graphs n~logU[1e3,2e5] (ER deg 8 / BA m=4 / grid+1% shortcuts), "
                            "k~U{1,10,100}, seed=3")
 
@@ -78,4 +81,6 @@ def build(name: str) -> synth.Csr:
         return synth.collaboration(2_000_000, 500_000, 2.1, 200, 4)
     if name == "rgg":
         return synth.random_geometric(4_000_000, 6.0, 5)
+    if name == "rgg18":
+        return synth.random_geometric(1 << 18, 6.0, 5)
     raise KeyError(name)

@@ -34,3 +34,41 @@ def test_full_size_against_oracle(name):
                 assert res.ids.tolist() == ref["ids"], (name, k, kw)
                 assert [int(x) for x in res.farness] == ref["farness"], (name, k, kw)
                 assert [int(x) for x in res.reach] == ref["reach"], (name, k, kw)
+
+
+def test_collaboration_full_size_sampled():
+    """Full-size collaboration projection (2M actors, 40M arcs), k = 10.  The
+    oracle's complete answer takes hours, so the check is by sampling what
+    it can compute one node at a time: each returned node's exact farness
+    and reach by one BFS, and a seeded sample of other non-isolated nodes,
+    each of which must rank below the returned k-th node."""
+    import numpy as np
+
+    import oracle
+
+    g = workloads.build("collab")
+    with bc.Graph(g.row_ptr, g.col) as G:
+        res = G.topk(10, mode="batched")
+    assert len(res.ids) == 10
+
+    def exact(v):
+        d = oracle.bfs(g, int(v)).astype(np.int64)
+        reached = d >= 0
+        return int(reached.sum()), int(d[reached].sum())
+
+    for v, f, r in zip(res.ids, res.farness, res.reach):
+        assert exact(v) == (int(r), int(f)), v
+    # returned keys are in decreasing order (ties by id)
+    keys = [oracle.closeness_key(r, f) for r, f in zip(res.reach, res.farness)]
+    for i in range(9):
+        assert keys[i] > keys[i + 1] or (keys[i] == keys[i + 1] and res.ids[i] < res.ids[i + 1])
+    kth_key, kth_id = keys[-1], int(res.ids[-1])
+    deg = np.diff(g.row_ptr)
+    rng = np.random.default_rng(12)
+    cand = np.flatnonzero(deg > 0)
+    top = set(res.ids.tolist())
+    sample = [int(v) for v in rng.choice(cand, 80, replace=False) if int(v) not in top][:64]
+    for v in sample:
+        r, f = exact(v)
+        kv = oracle.closeness_key(r, f)
+        assert kv < kth_key or (kv == kth_key and v > kth_id), v

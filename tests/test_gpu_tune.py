@@ -20,7 +20,7 @@ def test_autotune_keeps_the_answer(which):
     ref = oracle.topk(g, 10, nthreads=8)
     with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
         tuned, rep = G.autotune(10)
-        assert rep["trials"] >= 7
+        assert rep["trials"] >= 12
         assert rep["best_ms"] <= rep["default_ms"]
         res = G.topk(10, **tuned)
     assert res.ids.tolist() == ref["ids"].tolist()

@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--slots", type=int, default=0)
-    ap.add_argument("--order", default="auto", choices=["auto", "degree", "grouped", "learned", "learned_grouped"],
+    ap.add_argument("--order", default="auto", choices=["auto", "degree", "grouped", "locality", "learned", "learned_grouped"],
                     help="source order of the timed mode (auto: grouped degree in batched mode)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
     ap.add_argument("--skip-cpu", action="store_true")

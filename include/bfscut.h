@@ -62,6 +62,13 @@ typedef struct bc_graph bc_graph;
 #define BC_ORDER_LEARNED_GROUPED 5 /* opts.mlp: the sources of the seed batches (ceil(k/W) batches
                                 unless opts.seed_batches says otherwise) by decreasing score, then
                                 all others in BC_ORDER_GROUPED order                               */
+#define BC_ORDER_LOCALITY 6  /* compact balls of `width` sources: from a breadth-first order
+                                rooted at an approximate centre (middle of a double-sweep
+                                path; other components follow in degree order), each batch
+                                takes the first unplaced node and grows a breadth-first ball
+                                of unplaced nodes around it.  A batch's sources lie within a
+                                few hops of each other, so they share most levels (suits
+                                graphs without hubs: geometric, grid-like)                      */
 #define BC_ORDER_AUTO   -1   /* BC_ORDER_GROUPED in batched mode, BC_ORDER_DEGREE in plain mode   */
 
 /* Parameters of the order perceptron 3 -> 64 -> 64 -> 1 (ReLU, fp32), one flat vector:
@@ -228,6 +235,22 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
 bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, uint32_t* reach, bc_stats* stats);
 
 /*
+ * bc_source_order -- the order in which bc_topk with the same k and opts
+ * takes its sources (Algorithm 1 visits the nodes in any fixed order and
+ * returns the same answer; the order only decides how soon the k-th best
+ * value is known, Section 2.1).
+ *
+ *   k        as for bc_topk (the learned grouped order depends on it)
+ *   opts     NULL for the defaults; order, perm, scores, mlp, mode, width,
+ *            seed_batches and seed_width are read
+ *   order    host, n entries: a permutation of 0 .. n-1
+ *
+ * Blocking.  For inspection and tests.  Errors: BC_EINVAL (k <= 0, NULL
+ * order, bad opts), BC_ENOMEM, BC_EDEVICE.
+ */
+bc_status bc_source_order(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* order);
+
+/*
  * bc_autotune -- pick the batched-mode execution knobs for one graph and k.
  *
  * None of the knobs changes the answer, only the time.  Starting from
@@ -235,7 +258,7 @@ bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, ui
  * a grid of width (64, 128, 256) x defer_arcs (16384, 65536, 262144, never),
  * then tries one knob at a time around the best setting so far:
  * defer_width (64, 256), pull_alpha (never, 14, 40), slots (128, 256, 512)
- * and order (grouped, degree).  Each setting is timed as the best of
+ * and order (grouped, degree, locality).  Each setting is timed as the best of
  * `repeats` runs after one
  * warm-up.  Every run must return exactly the first run's top-k, else
  * BC_EDEVICE.  *best receives the fastest setting; report (may be NULL) the

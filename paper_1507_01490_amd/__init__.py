@@ -35,6 +35,7 @@ MLP_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "order_mlp.n
 BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS = 0x1, 0x2, 0x4
 ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_LEARNED_GROUPED, ORDER_AUTO = \
     0, 1, 2, 3, 4, 5, -1
+ORDER_LOCALITY = 6
 MLP_PARAMS = 4481
 MODE_PLAIN, MODE_BATCHED = 0, 1
 _STATUS = {0: "BC_OK", -1: "BC_EINVAL", -2: "BC_EGRAPH", -3: "BC_ENOMEM", -4: "BC_EDEVICE",
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.bc_topk.argtypes = [P, i32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(Stats)]
     f32 = ctypes.c_float
     lib.bc_farness_all.argtypes = [P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Stats)]
+    lib.bc_source_order.argtypes = [P, i32, ctypes.POINTER(Opts), P]
     u64 = ctypes.c_uint64
     lib.bc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
     lib.bc_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
@@ -149,7 +151,7 @@ def load_library(path: str = LIB_PATH):
     lib.bc_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, i64, P, ctypes.POINTER(ctypes.c_double), P]
     lib.bc_mlp_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
     for name in ("bc_graph_create", "bc_graph_destroy", "bc_graph_info", "bc_graph_reach",
-                 "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_graph_features", "bc_server_create",
+                 "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_source_order", "bc_graph_features", "bc_server_create",
                  "bc_server_destroy", "bc_server_add_graph", "bc_submit", "bc_wait", "bc_poll", "bc_cancel",
                  "bc_server_info", "bc_footprint", "bc_autotune", "bc_mlp_forward", "bc_mlp_loss_grad",
                  "bc_mlp_adam"):
@@ -262,7 +264,8 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
         o.mlp = prm.ctypes.data
         keep.append(prm)
     elif isinstance(order, str):
-        o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "auto": ORDER_AUTO}[order]
+        o.order = {"degree": ORDER_DEGREE, "grouped": ORDER_GROUPED, "locality": ORDER_LOCALITY,
+                   "auto": ORDER_AUTO}[order]
     elif order is not None:
         perm = np.ascontiguousarray(order, dtype=np.int32)
         if perm.shape[0] != n:
@@ -400,7 +403,8 @@ class Graph:
              seed_width: int = 0) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
-        order: None (automatic), "degree", "grouped", "learned" (the order
+        order: None (automatic), "degree", "grouped", "locality" (breadth-first
+        from an approximate centre), "learned" (the order
         perceptron `mlp`, default the trained one), "learned_grouped" (the
         seed-batch sources by learned score, then the grouped order), or a
         permutation of range(n); scores: per-node floats (decreasing score
@@ -424,6 +428,16 @@ class Graph:
         c = cnt.value
         return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
 
+    def source_order(self, k: int = 10, mode: str | int = "batched", width: int = 64, order=None, scores=None,
+                     mlp=None, seed_batches: int = -1, seed_width: int = 0) -> np.ndarray:
+        """The order (n node ids) in which topk with the same arguments takes its sources."""
+        keep = []
+        o = self._opts(mode, width, order, scores, 14.0, 24.0, 0, seed_batches, 0, 0, True, mlp, keep)
+        o.seed_width = int(seed_width)
+        out = np.zeros(max(1, self.n), np.int32)
+        _check(load_library().bc_source_order(self._h, int(k), ctypes.byref(o), _ptr(out)))
+        return out[:self.n].copy()
+
     def autotune(self, k: int, repeats: int = 1, **kw):
         """(best options as topk keyword arguments, report) for this graph and k."""
         keep = []
@@ -437,7 +451,8 @@ class Graph:
         rep.size = ctypes.sizeof(TuneReport)
         _check(load_library().bc_autotune(self._h, int(k), ctypes.byref(o), int(repeats), ctypes.byref(best),
                                           ctypes.byref(rep)))
-        order = {ORDER_DEGREE: "degree", ORDER_GROUPED: "grouped", ORDER_AUTO: None}.get(best.order, None)
+        order = {ORDER_DEGREE: "degree", ORDER_GROUPED: "grouped", ORDER_LOCALITY: "locality",
+                 ORDER_AUTO: None}.get(best.order, None)
         tuned = dict(mode="batched", width=best.width, defer_arcs=best.defer_arcs, defer_width=best.defer_width,
                      pull_alpha=best.pull_alpha, slots=best.slots, order=order)
         return tuned, dict(trials=rep.trials, default_ms=rep.default_ms, best_ms=rep.best_ms)

@@ -181,6 +181,29 @@ bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, ui
     BC_GUARD_END
 }
 
+bc_status bc_source_order(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* order) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (k <= 0) { set_error("k must be positive (got %d)", k); return BC_EINVAL; }
+    const int32_t n = g->dg.n;
+    if (n > 0 && !order) { set_error("order is NULL"); return BC_EINVAL; }
+    bc_opts o;
+    BC_TRY(copy_opts(opts, &o));
+    if (o.width != 64 && o.width != 128 && o.width != 256) {
+        set_error("width must be 64, 128 or 256 (got %d)", o.width);
+        return BC_EINVAL;
+    }
+    if (n == 0) return BC_OK;
+    bc::DevBuf d;
+    BC_TRY(d.alloc_on(sizeof(int32_t) * (size_t)n, g->stream));
+    BC_TRY(bc::build_order(g, o, std::min(k, n), d.as<int32_t>(), g->stream));
+    BC_HIP(hipMemcpyAsync(order, d.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, g->stream));
+    BC_HIP(hipStreamSynchronize(g->stream));
+    return BC_OK;
+    BC_GUARD_END
+}
+
 bc_status bc_graph_features(bc_graph* g, float* x, uint32_t* core) {
     BC_GUARD_BEGIN
     bc::g_err[0] = 0;

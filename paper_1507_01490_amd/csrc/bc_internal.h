@@ -156,6 +156,10 @@ struct bc_graph {
     bool have_order_deg = false;
     bc::DevBuf order_grp;  // cached grouped degree order
     bool have_order_grp = false;
+    bc::DevBuf order_loc_seed;  // cached breadth-first order from a centre
+    bool have_order_loc_seed = false;
+    bc::DevBuf order_loc[3];  // cached locality orders for batches of 64, 128, 256
+    bool have_order_loc[3] = {false, false, false};
     bc::DevBuf feat, core;  // learned-order features (n x 3 float) and core numbers, built on first use
     bool have_feat = false;
     int core_sweeps = 0;
@@ -195,6 +199,7 @@ bc_status order_grouped(bc_graph* g, int32_t* d_order, hipStream_t s);
 bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order, hipStream_t s);
 bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipStream_t s);
 bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order, hipStream_t s);
+bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s);
 
 // Learned order (learned.hip): features cached in g->feat / g->core; the
 // perceptron's forward pass, loss gradient and Adam step.
@@ -215,6 +220,7 @@ void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o,
 // cached workspace (its working memory is allocated and released with it).
 bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness,
                    uint32_t* reach, int32_t* count, bc_stats* st, hipStream_t s, bool private_ws = false);
+bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_order, hipStream_t s);
 bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st,
                           hipStream_t s);
 

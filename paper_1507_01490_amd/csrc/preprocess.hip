@@ -251,6 +251,222 @@ __global__ void k_keep_unmarked(int32_t n, const int32_t* __restrict__ order, co
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) keep[i] = !mark[order[i]];
 }
 
+// ---------------------------------------------------------- locality order
+//
+// Breadth-first discovery order from an approximate centre: consecutive
+// sources are neighbours, so a batch of them shares its search, and the
+// centre (high closeness) comes first.  Deterministic: each level is sorted
+// by (position of the node's earliest parent in the order, id).
+
+// dist[v] = -1, parent position = max
+__global__ void k_loc_init(int32_t n, int32_t* __restrict__ dist, uint32_t* __restrict__ ppos) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        dist[v] = -1;
+        if (ppos) ppos[v] = 0xFFFFFFFFu;
+    }
+}
+
+// One level: the out-arcs of F[0, flen) (at distance d, order positions
+// base + i) discover level d + 1 into N; with ppos, every parent offers its
+// position and the smallest is kept.
+__global__ void k_loc_expand(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const int32_t* F,
+                             uint32_t flen, int32_t d, uint32_t base, int32_t* dist, uint32_t* ppos, int32_t* N,
+                             uint32_t* ncount) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < flen; i += stride) {
+        const int32_t u = F[i];
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const int32_t w = col[e];
+            const int32_t old = atomicCAS(&dist[w], -1, d + 1);
+            if (old == -1) N[atomicAdd(ncount, 1u)] = w;
+            if (ppos && (old == -1 || old == d + 1)) atomicMin(&ppos[w], base + (uint32_t)i);
+        }
+    }
+}
+
+// keys of a discovered level: (earliest parent position, id)
+__global__ void k_loc_keys(uint32_t cnt, const int32_t* __restrict__ N, const uint32_t* __restrict__ ppos,
+                           uint64_t* __restrict__ key) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += stride)
+        key[j] = ((uint64_t)ppos[N[j]] << 32) | (uint32_t)N[j];
+}
+
+// farthest reached node: max (dist, -id) packed; and on-path test for the centre
+__global__ void k_loc_far(int32_t n, const int32_t* __restrict__ dist, unsigned long long* best) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        if (dist[v] >= 0)
+            atomicMax(best, ((unsigned long long)(uint32_t)dist[v] << 32) | (0xFFFFFFFFu - (uint32_t)v));
+}
+
+// centre: on a shortest a-b path (da + db = D), nearest to the middle, smallest id
+__global__ void k_loc_centre(int32_t n, const int32_t* __restrict__ da, const int32_t* __restrict__ db, int32_t D,
+                             unsigned long long* best) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        if (da[v] < 0 || db[v] < 0 || da[v] + db[v] != D) continue;
+        const uint32_t off = (uint32_t)abs(2 * da[v] - D);
+        atomicMin(best, ((unsigned long long)off << 32) | (uint32_t)v);
+    }
+}
+
+__global__ void k_loc_unreached(int32_t n, const int32_t* __restrict__ order_deg, const int32_t* __restrict__ dist,
+                                uint8_t* __restrict__ flag) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        flag[i] = dist[order_deg[i]] < 0;
+}
+
+// Cuts the breadth-first seed order into compact balls, one batch of B
+// positions at a time: take the first seed not yet placed, place it, then its
+// unplaced neighbours in queue order (frontier position, then arc order)
+// level by level until the batch is full; if its component runs dry, the
+// next unplaced seed continues the same batch.  A batch of sources that lie
+// within a few hops of each other reaches most nodes at the same or
+// neighbouring levels, so the bit-parallel search expands each node for many
+// sources at once.  Inherently sequential over batches: one workgroup of
+// kCarveThreads walks them; each level's arcs are read in chunks of
+// kCarveThreads ordinals, a node's first ordinal (an LDS hash) decides who
+// places it.
+constexpr int kCarveThreads = 1024;
+constexpr int kCarveHash = 2048;  // > kCarveThreads: open addressing never fills
+
+__device__ __forceinline__ uint32_t carve_slot(int32_t w) { return ((uint32_t)w * 2654435761u) >> 21; }
+
+__global__ __launch_bounds__(kCarveThreads) void k_carve(int32_t n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         const int32_t* __restrict__ seed, int32_t B,
+                                                         uint8_t* taken, int32_t* out, int32_t* err) {
+    __shared__ int32_t cur[256], nxt[256];
+    __shared__ int64_t pre[257];
+    __shared__ int32_t hkey[kCarveHash], hval[kCarveHash];
+    __shared__ int32_t wsum[kCarveThreads / 64];
+    __shared__ int32_t s_first;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i < kCarveHash; i += kCarveThreads) {
+        hkey[i] = -1;
+        hval[i] = INT32_MAX;
+    }
+    __syncthreads();
+    int32_t pos = 0;
+    int64_t ptr = 0;  // uniform across the workgroup
+    while (pos < n) {
+        const int32_t bend = (int32_t)min((int64_t)pos + B, (int64_t)n);
+        while (pos < bend) {
+            // first seed at or after ptr not yet placed (every seed before ptr is)
+            for (;;) {
+                if (ptr >= n) {  // unreachable while pos < n: the seed order is a permutation
+                    if (tid == 0) *err = 1;
+                    return;
+                }
+                if (tid == 0) s_first = INT32_MAX;
+                __syncthreads();
+                const int64_t idx = (int64_t)ptr + tid;
+                if (idx < n && !taken[seed[idx]]) atomicMin(&s_first, (int32_t)idx);
+                __syncthreads();
+                const int32_t f = s_first;
+                __syncthreads();
+                if (f != INT32_MAX) {
+                    ptr = f;
+                    break;
+                }
+                ptr += kCarveThreads;
+            }
+            if (tid == 0) {
+                const int32_t s0 = seed[ptr];
+                taken[s0] = 1;
+                out[pos] = s0;
+                cur[0] = s0;
+            }
+            pos += 1;
+            int32_t clen = 1;
+            __syncthreads();
+            while (clen > 0 && pos < bend) {
+                // pre[i] = out-arcs of cur[0, i)
+                if (wv == 0) {
+                    int64_t v[4], sum = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = 4 * lane + j;
+                        if (i < clen) sum += rp[cur[i] + 1] - rp[cur[i]];
+                        v[j] = sum;
+                    }
+                    int64_t x = sum;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int64_t y = __shfl_up(x, o);
+                        if (lane >= o) x += y;
+                    }
+                    const int64_t excl = x - sum;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = 4 * lane + j;
+                        if (i < clen) pre[i + 1] = excl + v[j];
+                    }
+                    if (lane == 0) pre[0] = 0;
+                }
+                __syncthreads();
+                const int64_t total = pre[clen];
+                int32_t nlen = 0;
+                for (int64_t base = 0; base < total && pos < bend; base += kCarveThreads) {
+                    const int64_t o = base + tid;
+                    int32_t w = -1;
+                    uint32_t slot = 0;
+                    if (o < total) {
+                        int lo = 0, hi = clen - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (pre[mid] <= o) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        w = col[rp[cur[lo]] + (o - pre[lo])];
+                        if (taken[w]) {
+                            w = -1;
+                        } else {
+                            slot = carve_slot(w);
+                            for (;;) {
+                                const int32_t k = atomicCAS(&hkey[slot], -1, w);
+                                if (k == -1 || k == w) break;
+                                slot = (slot + 1) & (kCarveHash - 1);
+                            }
+                            atomicMin(&hval[slot], tid);
+                        }
+                    }
+                    __syncthreads();
+                    const bool owner = w >= 0 && hval[slot] == tid;
+                    const unsigned long long bal = __ballot(owner);
+                    if (lane == 0) wsum[wv] = __popcll(bal);
+                    __syncthreads();
+                    int32_t rank = __popcll(bal & ((1ull << lane) - 1ull)), cnt = 0;
+                    for (int j = 0; j < kCarveThreads / 64; ++j) {
+                        if (j < wv) rank += wsum[j];
+                        cnt += wsum[j];
+                    }
+                    const int32_t room = bend - pos;
+                    if (owner && rank < room) {
+                        out[pos + rank] = w;
+                        taken[w] = 1;
+                        nxt[nlen + rank] = w;
+                    }
+                    __syncthreads();
+                    if (w >= 0) {
+                        hkey[slot] = -1;
+                        hval[slot] = INT32_MAX;
+                    }
+                    const int32_t em = min(cnt, room);
+                    pos += em;
+                    nlen += em;
+                    __syncthreads();
+                }
+                if (tid < nlen) cur[tid] = nxt[tid];
+                clen = nlen;
+                __syncthreads();
+            }
+        }
+    }
+}
+
 __global__ void k_perm_check(int32_t n, const int32_t* __restrict__ perm, uint32_t* __restrict__ seen,
                              uint32_t* err) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -498,6 +714,160 @@ bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, i
         set_error("internal: head/grouped order holds %d + %d of %d sources", head, got, n);
         return BC_EDEVICE;
     }
+    return BC_OK;
+}
+
+// Level-synchronous BFS from src over the out-arcs; dist[] (-1 = not
+// reached).  With order != nullptr the discovery order (levels sorted by
+// earliest parent position, then id) is written to order[0, *reached).
+static bc_status loc_bfs(bc_graph* g, int32_t src, int32_t* dist, uint32_t* ppos, int32_t* order, int32_t* reached,
+                         DevBuf& la, DevBuf& lb, DevBuf& k0, DevBuf& k1, DevBuf& cnt, DevBuf& tmp, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    k_loc_init<<<grid_for(n), kBlk, 0, s>>>(n, dist, ppos);
+    const int32_t zero = 0;
+    BC_HIP(hipMemcpyAsync(dist + src, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(la.p, &src, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (order) BC_HIP(hipMemcpyAsync(order, &src, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    uint32_t flen = 1, base = 0;
+    int32_t* F = la.as<int32_t>();
+    int32_t* N = lb.as<int32_t>();
+    for (int32_t d = 0; flen > 0; ++d) {
+        BC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t), s));
+        k_loc_expand<<<grid_for(flen), kBlk, 0, s>>>(g->dg.rp, g->dg.col, F, flen, d, base, dist, ppos, N,
+                                                      cnt.as<uint32_t>());
+        uint32_t nc = 0;
+        BC_HIP(hipMemcpyAsync(&nc, cnt.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        if (order && nc > 0) {
+            k_loc_keys<<<grid_for(nc), kBlk, 0, s>>>(nc, N, ppos, k0.as<uint64_t>());
+            BC_TRY(cub_call([&](void* t, size_t& b) {
+                return hipcub::DeviceRadixSort::SortKeys(t, b, k0.as<uint64_t>(), k1.as<uint64_t>(), (int)nc, 0, 64, s);
+            }, s, tmp));
+            k_low32<<<grid_for(nc), kBlk, 0, s>>>((int32_t)nc, k1.as<uint64_t>(), N);
+            BC_HIP(hipMemcpyAsync(order + base + flen, N, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, s));
+        }
+        base += flen;
+        flen = nc;
+        std::swap(F, N);
+    }
+    *reached = (int32_t)base;
+    return BC_OK;
+}
+
+// Seed order: breadth-first discovery order from an approximate centre (the
+// middle of a shortest path between the ends of a double sweep started at
+// the highest-degree node); nodes outside its component follow in degree
+// order.  Cached in g->order_loc_seed.
+static bc_status locality_seed(bc_graph* g, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    {
+        std::unique_lock<std::mutex> lk(g->cache_mu);
+        if (!g->have_order_loc_seed) {
+            lk.unlock();
+            DevBuf deg_order;
+            BC_TRY(deg_order.alloc_on(sizeof(int32_t) * (size_t)n, s));
+            BC_TRY(order_by_degree(g, deg_order.as<int32_t>(), s));
+            lk.lock();
+            if (!g->have_order_loc_seed) {
+                DevBuf da, db, ppos, la, lb, k0, k1, cnt, best, flag, nsel, tmp;
+                BC_TRY(da.alloc_on(sizeof(int32_t) * (size_t)n, s));
+                BC_TRY(db.alloc_on(sizeof(int32_t) * (size_t)n, s));
+                BC_TRY(ppos.alloc_on(sizeof(uint32_t) * (size_t)n, s));
+                BC_TRY(la.alloc_on(sizeof(int32_t) * (size_t)n, s));
+                BC_TRY(lb.alloc_on(sizeof(int32_t) * (size_t)n, s));
+                BC_TRY(k0.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+                BC_TRY(k1.alloc_on(sizeof(uint64_t) * (size_t)n, s));
+                BC_TRY(cnt.alloc_on(sizeof(uint32_t), s));
+                BC_TRY(best.alloc_on(sizeof(unsigned long long), s));
+                BC_TRY(flag.alloc_on((size_t)n, s));
+                BC_TRY(nsel.alloc_on(sizeof(int32_t), s));
+                BC_TRY(galloc(g, g->order_loc_seed, sizeof(int32_t) * (size_t)n, s));
+                int32_t* ord = g->order_loc_seed.as<int32_t>();
+                int32_t u0 = 0, reached = 0;
+                BC_HIP(hipMemcpyAsync(&u0, deg_order.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                BC_HIP(hipStreamSynchronize(s));
+                auto farthest = [&](int32_t* dist, int32_t* out) -> bc_status {
+                    const unsigned long long z = 0;
+                    BC_HIP(hipMemcpyAsync(best.p, &z, sizeof(z), hipMemcpyHostToDevice, s));
+                    k_loc_far<<<grid_for(n), kBlk, 0, s>>>(n, dist, best.as<unsigned long long>());
+                    unsigned long long b = 0;
+                    BC_HIP(hipMemcpyAsync(&b, best.p, sizeof(b), hipMemcpyDeviceToHost, s));
+                    BC_HIP(hipStreamSynchronize(s));
+                    *out = (int32_t)(0xFFFFFFFFu - (uint32_t)(b & 0xFFFFFFFFu));
+                    return BC_OK;
+                };
+                // double sweep: u0 -> a (farthest), a -> b (farthest); centre on a-b
+                int32_t a = 0, b = 0;
+                BC_TRY(loc_bfs(g, u0, da.as<int32_t>(), nullptr, nullptr, &reached, la, lb, k0, k1, cnt, tmp, s));
+                BC_TRY(farthest(da.as<int32_t>(), &a));
+                BC_TRY(loc_bfs(g, a, da.as<int32_t>(), nullptr, nullptr, &reached, la, lb, k0, k1, cnt, tmp, s));
+                BC_TRY(farthest(da.as<int32_t>(), &b));
+                int32_t D = 0;
+                BC_HIP(hipMemcpyAsync(&D, da.as<int32_t>() + b, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                BC_TRY(loc_bfs(g, b, db.as<int32_t>(), nullptr, nullptr, &reached, la, lb, k0, k1, cnt, tmp, s));
+                const unsigned long long mx = ~0ull;
+                BC_HIP(hipMemcpyAsync(best.p, &mx, sizeof(mx), hipMemcpyHostToDevice, s));
+                k_loc_centre<<<grid_for(n), kBlk, 0, s>>>(n, da.as<int32_t>(), db.as<int32_t>(), D,
+                                                          best.as<unsigned long long>());
+                unsigned long long cb = 0;
+                BC_HIP(hipMemcpyAsync(&cb, best.p, sizeof(cb), hipMemcpyDeviceToHost, s));
+                BC_HIP(hipStreamSynchronize(s));
+                const int32_t c = cb == ~0ull ? u0 : (int32_t)(uint32_t)(cb & 0xFFFFFFFFu);
+                // ordered BFS from the centre, then the other components in degree order
+                BC_TRY(loc_bfs(g, c, da.as<int32_t>(), ppos.as<uint32_t>(), ord, &reached, la, lb, k0, k1, cnt, tmp,
+                               s));
+                k_loc_unreached<<<grid_for(n), kBlk, 0, s>>>(n, deg_order.as<int32_t>(), da.as<int32_t>(),
+                                                             flag.as<uint8_t>());
+                BC_TRY(cub_call([&](void* t, size_t& bb) {
+                    return hipcub::DeviceSelect::Flagged(t, bb, deg_order.as<int32_t>(), flag.as<uint8_t>(),
+                                                         ord + reached, nsel.as<int32_t>(), n, s);
+                }, s, tmp));
+                int32_t rest = 0;
+                BC_HIP(hipMemcpyAsync(&rest, nsel.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                BC_HIP(hipStreamSynchronize(s));
+                if (reached + rest != n) {
+                    set_error("internal: locality order holds %d + %d of %d sources", reached, rest, n);
+                    return BC_EDEVICE;
+                }
+                g->have_order_loc_seed = true;
+            }
+        }
+    }
+    return BC_OK;
+}
+
+// Locality order for batches of B sources: the seed order cut into compact
+// balls of B (k_carve).  Cached per B.
+bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    if (B != 64 && B != 128 && B != 256) {
+        set_error("locality order: batch width must be 64, 128 or 256 (got %d)", B);
+        return BC_EINVAL;
+    }
+    BC_TRY(locality_seed(g, s));
+    const int slot = B == 64 ? 0 : (B == 128 ? 1 : 2);
+    std::lock_guard<std::mutex> lk(g->cache_mu);
+    if (!g->have_order_loc[slot]) {
+        DevBuf taken, err;
+        BC_TRY(taken.alloc_on((size_t)n, s));
+        BC_TRY(err.alloc_on(sizeof(int32_t), s));
+        BC_HIP(hipMemsetAsync(taken.p, 0, (size_t)n, s));
+        BC_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+        BC_TRY(galloc(g, g->order_loc[slot], sizeof(int32_t) * (size_t)n, s));
+        k_carve<<<1, kCarveThreads, 0, s>>>(n, g->dg.rp, g->dg.col, g->order_loc_seed.as<int32_t>(), B,
+                                            taken.as<uint8_t>(), g->order_loc[slot].as<int32_t>(), err.as<int32_t>());
+        int32_t e = 0;
+        BC_HIP(hipMemcpyAsync(&e, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        if (e) {
+            set_error("internal: locality carving ran out of seeds");
+            return BC_EDEVICE;
+        }
+        g->have_order_loc[slot] = true;
+    }
+    BC_HIP(hipMemcpyAsync(d_order, g->order_loc[slot].p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     return BC_OK;
 }
 

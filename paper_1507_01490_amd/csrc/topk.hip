@@ -2087,37 +2087,7 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         QueryBufs B;
         BC_TRY(B.order.alloc_on(sizeof(int32_t) * (size_t)n, s));
         int32_t* d_order = B.order.as<int32_t>();
-        const int32_t ord = o.order == BC_ORDER_AUTO ? (o.mode == BC_MODE_BATCHED ? BC_ORDER_GROUPED : BC_ORDER_DEGREE)
-                                                      : o.order;
-        if (ord == BC_ORDER_DEGREE) {
-            BC_TRY(order_by_degree(g, d_order, s));
-        } else if (ord == BC_ORDER_GROUPED) {
-            BC_TRY(order_grouped(g, d_order, s));
-        } else if (ord == BC_ORDER_GIVEN) {
-            if (!o.perm) { set_error("BC_ORDER_GIVEN needs opts.perm"); return BC_EINVAL; }
-            BC_TRY(order_given(g, o.perm, d_order, s));
-        } else if (ord == BC_ORDER_SCORES) {
-            if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
-            BC_TRY(order_by_scores(g, o.scores, false, d_order, s));
-        } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED) {
-            if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
-            BC_TRY(graph_features(g, s));
-            DevBuf prm, sc;
-            BC_TRY(prm.alloc_on(sizeof(float) * BC_MLP_PARAMS, s));
-            BC_TRY(sc.alloc_on(sizeof(float) * (size_t)n, s));
-            BC_HIP(hipMemcpyAsync(prm.p, o.mlp, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
-            BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
-            if (ord == BC_ORDER_LEARNED) {
-                BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
-            } else {
-                const SeedPlan sp = seed_plan(o, kk, n, W);
-                const int64_t head = std::min<int64_t>((int64_t)n, (int64_t)sp.batches * sp.sw);
-                BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order, s));
-            }
-        } else {
-            set_error("unknown order %d", o.order);
-            return BC_EINVAL;
-        }
+        BC_TRY(build_order(g, o, kk, d_order, s));
         // top-k list: cnt, lock, seq (16 B header) + k records; ring of n + 1
         // records (every-node mode: only the header, and the per-node outputs)
         const size_t hdr = 64;
@@ -2243,6 +2213,48 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
 }
 
 }  // namespace
+
+// The order in which Algorithm 1 takes its sources (any order gives the
+// same answer; Section 2.1): one of the BC_ORDER_* rules, written to
+// d_order (n entries, a permutation).
+bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_order, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    const int W = o.width;
+    const int32_t ord = o.order == BC_ORDER_AUTO ? (o.mode == BC_MODE_BATCHED ? BC_ORDER_GROUPED : BC_ORDER_DEGREE)
+                                                  : o.order;
+    if (ord == BC_ORDER_DEGREE) {
+        BC_TRY(order_by_degree(g, d_order, s));
+    } else if (ord == BC_ORDER_GROUPED) {
+        BC_TRY(order_grouped(g, d_order, s));
+    } else if (ord == BC_ORDER_LOCALITY) {
+        BC_TRY(order_locality(g, W, d_order, s));
+    } else if (ord == BC_ORDER_GIVEN) {
+        if (!o.perm) { set_error("BC_ORDER_GIVEN needs opts.perm"); return BC_EINVAL; }
+        BC_TRY(order_given(g, o.perm, d_order, s));
+    } else if (ord == BC_ORDER_SCORES) {
+        if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
+        BC_TRY(order_by_scores(g, o.scores, false, d_order, s));
+    } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED) {
+        if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
+        BC_TRY(graph_features(g, s));
+        DevBuf prm, sc;
+        BC_TRY(prm.alloc_on(sizeof(float) * BC_MLP_PARAMS, s));
+        BC_TRY(sc.alloc_on(sizeof(float) * (size_t)n, s));
+        BC_HIP(hipMemcpyAsync(prm.p, o.mlp, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
+        BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
+        if (ord == BC_ORDER_LEARNED) {
+            BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
+        } else {
+            const SeedPlan sp = seed_plan(o, kk, n, W);
+            const int64_t head = std::min<int64_t>((int64_t)n, (int64_t)sp.batches * sp.sw);
+            BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order, s));
+        }
+    } else {
+        set_error("unknown order %d", o.order);
+        return BC_EINVAL;
+    }
+    return BC_OK;
+}
 
 bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint64_t* farness, uint32_t* reach,
                    int32_t* count, bc_stats* st, hipStream_t s, bool private_ws) {

@@ -111,7 +111,7 @@ extern "C" bc_status bc_autotune(bc_graph* g, int32_t k, const bc_opts* base, in
             {{64, 256}, [](bc_opts& o, int v) { o.defer_width = v; }},
             {{0, 14, 40}, [](bc_opts& o, int v) { o.pull_alpha = (float)v; }},
             {{cus / 2, cus, 2 * cus}, [](bc_opts& o, int v) { o.slots = v; }},
-            {{BC_ORDER_GROUPED, BC_ORDER_DEGREE}, [](bc_opts& o, int v) { o.order = v; }},
+            {{BC_ORDER_GROUPED, BC_ORDER_DEGREE, BC_ORDER_LOCALITY}, [](bc_opts& o, int v) { o.order = v; }},
         };
         for (auto& kn : knobs) {
             bc_opts keep = cur;

@@ -1,0 +1,201 @@
+"""Source orders on the GPU.  Algorithm 1 may take its sources in any fixed
+order and returns the same top-k (Section 2.1); the order only decides how
+soon the k-th best value is known.  Checked here: every order rule yields a
+permutation, the degree and locality rules are the ones documented in
+include/bfscut.h (re-derived below with plain breadth-first searches), and
+the answer with the locality order equals the oracle's."""
+
+from collections import deque
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1507_01490_amd as bc
+from paper_1507_01490_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def graphs():
+    return [synth.path(9), synth.star(12), synth.grid(6, 7), synth.empty(1), synth.empty(6),
+            synth.disjoint_union(synth.path(5), synth.star(4), synth.complete(3), synth.empty(2)),
+            synth.directed_path(8), synth.directed_cycle(6), synth.out_star(9),
+            synth.barabasi_albert(3000, 3, 11), synth.grid_shortcuts(5000, 0.01, 3),
+            synth.random_small(400, 0.004, True, 9), synth.rmat(12, 8, 0.57, 0.19, 0.19, 4)]
+
+
+def canonical(g):
+    with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+        return G.csr()
+
+
+def bfs_dist(rp, col, src):
+    n = len(rp) - 1
+    d = np.full(n, -1, np.int64)
+    d[src] = 0
+    q = deque([src])
+    while q:
+        u = q.popleft()
+        for w in col[rp[u]:rp[u + 1]]:
+            if d[w] < 0:
+                d[w] = d[u] + 1
+                q.append(w)
+    return d
+
+
+def degree_order(rp):
+    deg = np.diff(rp)
+    return np.lexsort((np.arange(len(deg)), -deg))
+
+
+def locality_seed(rp, col):
+    """The seed of the locality rule written out: double sweep from the first
+    node of the degree order, centre on a shortest path between its ends,
+    then levels from the centre, each sorted by (earliest parent position,
+    id), then the unreached nodes in degree order."""
+    n = len(rp) - 1
+    dego = degree_order(rp)
+
+    def farthest(d):
+        reached = np.nonzero(d >= 0)[0]
+        return int(reached[np.lexsort((reached, -d[reached]))[0]])
+
+    a = farthest(bfs_dist(rp, col, int(dego[0])))
+    da = bfs_dist(rp, col, a)
+    b = farthest(da)
+    D = da[b]
+    db = bfs_dist(rp, col, b)
+    on = np.nonzero((da >= 0) & (db >= 0) & (da + db == D))[0]
+    c = int(on[np.lexsort((on, np.abs(2 * da[on] - D)))[0]]) if len(on) else int(dego[0])
+    pos = {c: 0}
+    order = [c]
+    level = [c]
+    while level:
+        best = {}
+        for u in level:
+            for w in col[rp[u]:rp[u + 1]]:
+                w = int(w)
+                if w in pos:
+                    continue
+                best[w] = min(best.get(w, n + 1), pos[u])
+        level = sorted(best, key=lambda w: (best[w], w))
+        for w in level:
+            pos[w] = len(order)
+            order.append(w)
+    order += [int(v) for v in dego if int(v) not in pos]
+    return np.array(order, np.int64)
+
+
+def carve(rp, col, seed, B):
+    """Batches of B: the first unplaced seed, then its unplaced neighbours in
+    queue order, level by level, until the batch is full; if the ball runs
+    dry, the next unplaced seed continues the batch."""
+    n = len(rp) - 1
+    taken = np.zeros(n, bool)
+    out = []
+    ptr = 0
+    while len(out) < n:
+        bend = min(len(out) + B, n)
+        while len(out) < bend:
+            while taken[seed[ptr]]:
+                ptr += 1
+            s = int(seed[ptr])
+            taken[s] = True
+            out.append(s)
+            cur = [s]
+            while cur and len(out) < bend:
+                nxt = []
+                for u in cur:
+                    for w in col[rp[u]:rp[u + 1]]:
+                        if len(out) >= bend:
+                            break
+                        if not taken[w]:
+                            taken[w] = True
+                            out.append(int(w))
+                            nxt.append(int(w))
+                cur = nxt
+    return np.array(out, np.int64)
+
+
+def locality_order(rp, col, B):
+    return carve(rp, col, locality_seed(rp, col), B)
+
+
+ORDERS = ["degree", "grouped", "locality", "learned", "learned_grouped", "auto"]
+
+
+@pytest.mark.parametrize("gi", range(13))
+def test_orders_are_permutations_and_follow_their_rules(gi):
+    g = graphs()[gi]
+    rp, col = canonical(g)
+    with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+        for name in ORDERS:
+            for mode in ("plain", "batched"):
+                o = G.source_order(10, mode=mode, order=name)
+                assert sorted(o.tolist()) == list(range(g.n)), (name, mode)
+        assert G.source_order(10, order="degree").tolist() == degree_order(rp).tolist()
+        assert G.source_order(10, order="auto", mode="plain").tolist() == degree_order(rp).tolist()
+        seed = locality_seed(rp, col)
+        for width in (64, 128, 256):
+            loc = G.source_order(10, order="locality", width=width)
+            assert loc.tolist() == carve(rp, col, seed, width).tolist(), width
+            # a second call returns the cached order
+            assert G.source_order(10, order="locality", width=width).tolist() == loc.tolist()
+        perm = np.random.default_rng(gi).permutation(g.n)
+        assert G.source_order(10, order=perm).tolist() == perm.tolist()
+
+
+def test_locality_batches_are_compact():
+    """On a grid-like graph each batch of the locality order is a ball: its
+    sources lie within a few hops of its first source."""
+    g = synth.grid_shortcuts(20000, 0.0, 8)
+    rp, col = canonical(g)
+    with bc.Graph(g.row_ptr, g.col) as G:
+        o = G.source_order(10, order="locality", width=64)
+    assert o.tolist() == locality_order(rp, col, 64).tolist()
+    spans = []
+    for b in range(0, g.n - 64, 64 * 37):
+        d = bfs_dist(rp, col, int(o[b]))
+        spans.append(int(d[o[b:b + 64]].max()))
+    # a 64-node ball on a square grid has radius about 6; a run of 64 nodes
+    # of one breadth-first level would span tens of hops
+    assert np.median(spans) <= 10, spans
+
+
+VARIANTS = [dict(mode="plain", width=64), dict(mode="plain", width=256), dict(mode="batched", width=64),
+            dict(mode="batched", width=128, seed_width=256), dict(mode="batched", width=64, lds_tables="spill"),
+            dict(mode="batched", width=256, defer_arcs=40, defer_width=64, slots=5)]
+
+
+@pytest.mark.parametrize("kind", ["grid", "rgg", "ba", "rmat", "union"])
+def test_locality_order_answer_equals_oracle(kind):
+    if kind == "grid":
+        g = synth.grid_shortcuts(30000, 0.001, 31)
+    elif kind == "rgg":
+        g = synth.random_geometric(20000, 8.0, 32)
+    elif kind == "ba":
+        g = synth.barabasi_albert(20000, 4, 33)
+    elif kind == "rmat":
+        g = synth.rmat(13, 16, 0.57, 0.19, 0.19, 34)
+    else:
+        g = synth.disjoint_union(synth.grid(40, 50), synth.barabasi_albert(3000, 3, 35), synth.path(400),
+                                 synth.empty(30))
+    for k in (1, 10, 100):
+        ref = oracle.topk(g, k, nthreads=8)
+        with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+            for v in VARIANTS:
+                r = G.topk(k, order="locality", **v)
+                assert r.ids.tolist() == ref["ids"].tolist(), (kind, k, v)
+                assert r.farness.tolist() == ref["f"].tolist() and r.reach.tolist() == ref["r"].tolist()
+
+
+def test_source_order_errors():
+    g = synth.path(5)
+    with bc.Graph(g.row_ptr, g.col) as G:
+        with pytest.raises(bc.BcError):
+            G.source_order(0)
+        with pytest.raises(bc.BcError):
+            G.source_order(3, width=32)
+        with pytest.raises(ValueError):
+            G.source_order(3, order=np.array([0, 1, 2]))

@@ -43,7 +43,8 @@ namespace bc {
 
 namespace {
 
-constexpr int kBlk = 256;  // threads per workgroup in every level kernel
+constexpr int kBlk = 256;  // threads per workgroup in every level kernel (and the most sources per batch)
+constexpr int kBatchBlk = 1024;  // threads per workgroup of the persistent batched kernel
 
 // words per node record: seen, nxt, cur (WW each) + meta, padded to 32/64/128 B
 template <int WW>
@@ -967,12 +968,14 @@ __global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
 
 // Persistent: every workgroup owns one slot and runs whole batches, pulling
 // batch indices from a device counter, with every level inside the workgroup.
-template <int WW>
-__global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* order, int W, uint32_t nbatches,
+// B threads per workgroup (kBatchBlk): a level's arcs are spread over all of
+// them, so a CU keeps B / 64 waves of node-record loads and atomics in flight.
+template <int WW, int B>
+__global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order, int W, uint32_t nbatches,
                                                  uint32_t* next_batch, uint32_t chunk, SlotPtrs base,
                                                  uint32_t* slot_stamp, TopKDev T, QStats* st, DeferList D) {
     using Lo = Layout<WW>;
-    __shared__ LdsExpand<WW> LE;
+    __shared__ LdsExpand<WW, B> LE;
     __shared__ SrcState S[kBlk];
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
@@ -1020,12 +1023,14 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
         ticks[0] += tp - tb;
         while (live) {
             ++stamp;
-            cg[tid] = 0;
-            ct[tid] = 0;
+            if (tid < kBlk) {
+                cg[tid] = 0;
+                ct[tid] = 0;
+            }
             if (tid == 0) s_nlen = 0;
             __syncthreads();
-            for (uint32_t e0 = 0; e0 < flen; e0 += kBlk)
-                expand_entries<WW>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &s_nlen, stamp, LE, cg, ct,
+            for (uint32_t e0 = 0; e0 < flen; e0 += B)
+                expand_entries<WW, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, cg, ct,
                                    &s_narcs, &s_ent);
             __syncthreads();
             const uint32_t nlen = s_nlen;
@@ -1039,10 +1044,10 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
             tq = __builtin_amdgcn_s_memrealtime();
             ticks[2] += tq - tp;
             tp = tq;
-            clear_cur<WW>(P, P.qa, flen, 0, kBlk);
+            clear_cur<WW>(P, P.qa, flen, 0, B);
             if (tid == 0) s_flen = 0;
             __syncthreads();
-            build_level<WW>(P, P.qb, nlen, 0, kBlk, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs);
+            build_level<WW>(P, P.qb, nlen, 0, B, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs);
             __syncthreads();
             flen = s_flen;
             tq = __builtin_amdgcn_s_memrealtime();
@@ -1051,7 +1056,7 @@ __global__ __launch_bounds__(kBlk) void k_batched(DevGraph G, const int32_t* ord
         }
         // reset seen and cur of every node this batch reached
         const uint32_t nc = s_clen;
-        for (uint32_t i = tid; i < nc; i += kBlk) {
+        for (uint32_t i = tid; i < nc; i += B) {
             uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
 #pragma unroll
             for (int j = 0; j < WW; ++j) {
@@ -2008,11 +2013,11 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
                 k_batched_lds<1><<<slots, kLdsBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
                                                            T, d_st, D, o.lds_tables == 1 ? 1 : 0);
             else
-                k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), chunk, base,
-                                                      Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
+                k_batched<WW, kBatchBlk><<<slots, kBatchBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(),
+                                                                     chunk, base, Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
         } else {
-            k_batched<WW><<<slots, kBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), chunk, base,
-                                                  Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
+            k_batched<WW, kBatchBlk><<<slots, kBatchBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(),
+                                                                 chunk, base, Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
         }
         BC_HIP(hipEventRecord(ev.b, s));
         BC_HIP(hipGetLastError());

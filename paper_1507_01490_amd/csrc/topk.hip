@@ -294,6 +294,87 @@ __device__ inline void wave_count(uint64_t bits, uint32_t deg, int j, uint32_t* 
     }
 }
 
+// Transpose of the 64 x 64 bit matrix held one row per lane (row = lane,
+// column = bit): afterwards lane b holds column b, bit i = bit b of lane i.
+// Six butterfly stages; at stage s a lane keeps the half of its row whose
+// column bit s equals its own lane bit s and takes the other half from lane
+// lane ^ s.  Wave-uniform call.
+__device__ inline uint64_t transpose64(uint64_t x) {
+    const uint32_t lane = lane_id();
+    constexpr uint64_t kM[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int sh = 32 >> st;
+        const uint64_t m = kM[st];
+        const uint64_t y = __shfl_xor(x, sh);
+        x = (lane & (uint32_t)sh) ? ((x & ~m) | ((y & ~m) >> sh)) : ((x & m) | ((y & m) << sh));
+    }
+    return x;
+}
+
+// Per-source counts of a wave of newly reached nodes: lane i holds the nxt
+// bits nb[j] of its node and the node's out-degree; lane b of the wave adds,
+// for source j * 64 + b, the number of nodes with bit b and the sum of their
+// degrees (the degree is taken bit plane by bit plane: plane k is a ballot,
+// and the sum is the popcounts of the column masked by each plane, shifted).
+// Wave-uniform call.
+template <int WW>
+__device__ inline void wave_count_nodes(const uint64_t* nb, uint32_t deg, uint32_t* cg, unsigned long long* ct) {
+    uint64_t col[WW];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < WW; ++j) {
+        const bool has = __ballot(nb[j] != 0ull) != 0ull;
+        col[j] = has ? transpose64(nb[j]) : 0ull;
+        any |= has;
+    }
+    if (!any) return;
+    unsigned long long t[WW];
+#pragma unroll
+    for (int j = 0; j < WW; ++j) t[j] = 0;
+    for (int k = 0; k < 32; ++k) {
+        if (__ballot((deg >> k) != 0u) == 0ull) break;
+        const uint64_t plane = __ballot(((deg >> k) & 1u) != 0u);
+#pragma unroll
+        for (int j = 0; j < WW; ++j) t[j] += (unsigned long long)__popcll(col[j] & plane) << k;
+    }
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < WW; ++j) {
+        const uint32_t g = (uint32_t)__popcll(col[j]);
+        if (g) {
+            atomicAdd(&cg[j * 64 + lane], g);
+            atomicAdd(&ct[j * 64 + lane], t[j]);
+        }
+    }
+}
+
+// Counters of the level just reached, from its list N[0, len) of newly
+// reached nodes (each once) after the expansion: the nxt masks are read from
+// L2 (they were written by atomics this level).
+template <int WW, int B>
+__device__ void count_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t* cg, unsigned long long* ct) {
+    using Lo = Layout<WW>;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t rb = 0; rb < len; rb += B) {
+        if (rb + (tid & ~63u) >= len) break;  // wave-uniform: nothing left for this wave
+        const uint32_t i = rb + tid;
+        uint64_t nb[WW];
+        uint32_t deg = 0;
+#pragma unroll
+        for (int j = 0; j < WW; ++j) nb[j] = 0;
+        if (i < len) {
+            uint64_t* rec = &P.ns[(size_t)N[i] * Lo::SW];
+#pragma unroll
+            for (int j = 0; j < WW; ++j)
+                nb[j] = __hip_atomic_load(&rec[Lo::NXT + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            deg = (uint32_t)(rec[Lo::META] >> 32);
+        }
+        wave_count_nodes<WW>(nb, deg, cg, ct);
+    }
+}
+
 // Arc u->w for the live source bits m of u: OR the unseen ones into nxt[w];
 // nb_first[j] receives the bits this thread set first and *deg the degree
 // of w (for counting).  Returns whether w is new this level.
@@ -374,7 +455,7 @@ struct LdsExpand {
 // Expand entries [e0, e1) (at most kBlk) of the frontier list F: every arc of
 // every entry with a live bit, balanced over the workgroup by a scan of the
 // degrees.  Nodes reached for the first time this level go to N once.
-template <int WW, int B = kBlk>
+template <int WW, int B = kBlk, bool kCount = true>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
                                const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW, B>& L,
                                uint32_t* cg, unsigned long long* ct, unsigned long long* arcs,
@@ -429,9 +510,11 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
             w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
             app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp, nbf, &dw);
         }
-        if (cg) {
+        if constexpr (kCount) {
+            if (cg) {
 #pragma unroll
-            for (int j = 0; j < WW; ++j) wave_count(nbf[j], dw, j, cg, ct);
+                for (int j = 0; j < WW; ++j) wave_count(nbf[j], dw, j, cg, ct);
+            }
         }
         append_if(app, w, N, nctr);
     }
@@ -1030,10 +1113,12 @@ __global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order,
             if (tid == 0) s_nlen = 0;
             __syncthreads();
             for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                expand_entries<WW, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, cg, ct,
-                                   &s_narcs, &s_ent);
+                expand_entries<WW, B, false>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, cg,
+                                             ct, &s_narcs, &s_ent);
             __syncthreads();
             const uint32_t nlen = s_nlen;
+            count_level<WW, B>(P, P.qb, nlen, cg, ct);
+            __syncthreads();
             disc += nlen;
             uint64_t tq = __builtin_amdgcn_s_memrealtime();
             ticks[1] += tq - tp;

@@ -866,21 +866,14 @@ __device__ void plain_level_epilogue(Ctl* C, SrcState* S, TopKDev T, QStats* st,
 // same step takes the other case).  Every thread reads the same control
 // words, written by kernels that finished before this one started.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
-                                                      QStats* st, int W, int gated) {
+__global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, Ctl* C, QStats* st, int gated) {
     if (gated && (C->live == 0 || C->pull != 0)) return;
     __shared__ LdsExpand<WW> L;
-    __shared__ uint32_t cg[kBlk];
-    __shared__ unsigned long long ct[kBlk];
-    __shared__ CutLds CL;
-    __shared__ uint32_t s_last;
     __shared__ uint64_t s_act[4];
     __shared__ unsigned long long s_arcs, s_ent;
     const uint32_t flen = C->flen, stamp = C->stamp;
     const int tid = threadIdx.x;
     if (tid < WW) s_act[tid] = C->active[tid];
-    cg[tid] = 0;
-    ct[tid] = 0;
     if (tid == 0) {
         s_arcs = 0;
         s_ent = 0;
@@ -892,11 +885,47 @@ __global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, S
         const uint32_t e0 = L.chunk * kBlk;
         __syncthreads();
         if (e0 >= flen) break;
-        expand_entries<WW>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &C->nlen, stamp, L, cg, ct, &s_arcs,
-                           &s_ent);
+        expand_entries<WW, kBlk, false>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &C->nlen, stamp, L,
+                                        nullptr, nullptr, &s_arcs, &s_ent);
     }
     if (tid == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
     if (tid == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
+}
+
+// After a push step: the per-source counters of the level from its list of
+// newly reached nodes (once per node), then the cut step in the last
+// workgroup.  Same gate as the push step.
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_count(SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st,
+                                                     int W, int gated) {
+    if (gated && (C->live == 0 || C->pull != 0)) return;
+    using Lo = Layout<WW>;
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_last;
+    __shared__ uint64_t s_act[4];
+    const uint32_t tid = threadIdx.x;
+    cg[tid] = 0;
+    ct[tid] = 0;
+    __syncthreads();
+    const uint32_t len = C->nlen;
+    const uint32_t stride = gridDim.x * kBlk;
+    for (uint32_t base = blockIdx.x * kBlk; base < len; base += stride) {
+        if (base + (tid & ~63u) >= len) break;  // wave-uniform: nothing left for this wave
+        const uint32_t i = base + tid;
+        uint64_t nb[WW];
+        uint32_t deg = 0;
+#pragma unroll
+        for (int j = 0; j < WW; ++j) nb[j] = 0;
+        if (i < len) {
+            const uint64_t* rec = &P.ns[(size_t)P.qb[i] * Lo::SW];
+#pragma unroll
+            for (int j = 0; j < WW; ++j) nb[j] = rec[Lo::NXT + j];
+            deg = (uint32_t)(rec[Lo::META] >> 32);
+        }
+        wave_count_nodes<WW>(nb, deg, cg, ct);
+    }
     __syncthreads();
     plain_level_epilogue<WW>(C, S, T, st, W, cg, ct, CL, s_act, &s_last);
 }
@@ -968,8 +997,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Src
                 }
             }
         }
-#pragma unroll
-        for (int j = 0; j < WW; ++j) wave_count(pbits[j], pdeg, j, cg, ct);
+        wave_count_nodes<WW>(pbits, pdeg, cg, ct);
         append_if(app, w, P.qb, &C->nlen);
     }
     if (scanned) atomicAdd(&st->node_arcs, scanned);
@@ -1963,7 +1991,8 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
         if (!Wk.cap) BC_HIP(hipStreamCreateWithFlags(&Wk.cap, hipStreamNonBlocking));  // default priority
         BC_HIP(hipStreamBeginCapture(Wk.cap, hipStreamCaptureModeThreadLocal));
         for (int l = 0; l < graph_levels; ++l) {
-            k_plain_expand<WW><<<8 * cus, kBlk, 0, Wk.cap>>>(G, P, S, C, T, d_st, W, 1);
+            k_plain_expand<WW><<<8 * cus, kBlk, 0, Wk.cap>>>(G, P, C, d_st, 1);
+            k_plain_count<WW><<<4 * cus, kBlk, 0, Wk.cap>>>(P, S, C, T, d_st, W, 1);
             k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, Wk.cap>>>(G, P, S, C, T, d_st, W, 1);
             k_plain_clearcur<WW><<<4 * cus, kBlk, 0, Wk.cap>>>(P, C, 1);
             k_plain_build<WW><<<4 * cus, kBlk, 0, Wk.cap>>>(G, P, C, lp, 1);
@@ -1989,8 +2018,14 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
                 BC_HIP(hipGraphLaunch(gh.exec, s));
                 continue;
             }
-            if (pull) k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
-            else k_plain_expand<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
+            if (pull) {
+                k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
+            } else {
+                k_plain_expand<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
+                // new nodes <= arcs out of the frontier
+                k_plain_count<WW><<<clamp_grid((int64_t)std::min<unsigned long long>(fa, (unsigned long long)n),
+                                               4 * cus), kBlk, 0, s>>>(P, S, C, T, d_st, W, 0);
+            }
             k_plain_clearcur<WW><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C, 0);
             // reached nodes <= arcs out of the frontier (push) or n (pull)
             const int64_t bound =

@@ -268,32 +268,6 @@ __device__ inline void count_new(uint64_t bits, int j, uint32_t deg, uint32_t* c
     }
 }
 
-// Wave-aggregated form of count_new: every lane holds the bits it set first
-// (word j) and the degree of its target; lane b adds the column sums of bit b
-// with one atomic, so lanes sharing a source never contend.  Wave-uniform call.
-__device__ inline void wave_count(uint64_t bits, uint32_t deg, int j, uint32_t* cg, unsigned long long* ct) {
-    unsigned long long lanes = __ballot(bits != 0ull);
-    if (!lanes) return;
-    const uint32_t lane = lane_id();
-    const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
-    uint32_t g = 0;
-    unsigned long long t = 0;
-    while (lanes) {
-        const int i = __ffsll((long long)lanes) - 1;
-        lanes &= lanes - 1ull;
-        const uint32_t xl = __builtin_amdgcn_readlane(lo, i);
-        const uint32_t xh = __builtin_amdgcn_readlane(hi, i);
-        const uint32_t dv = __builtin_amdgcn_readlane(deg, i);
-        const uint32_t mine = lane < 32 ? (xl >> lane) & 1u : (xh >> (lane - 32)) & 1u;
-        g += mine;
-        t += mine ? dv : 0u;
-    }
-    if (g) {
-        atomicAdd(&cg[j * 64 + lane], g);
-        atomicAdd(&ct[j * 64 + lane], t);
-    }
-}
-
 // Transpose of the 64 x 64 bit matrix held one row per lane (row = lane,
 // column = bit): afterwards lane b holds column b, bit i = bit b of lane i.
 // Six butterfly stages; at stage s a lane keeps the half of its row whose
@@ -375,16 +349,14 @@ __device__ void count_level(const SlotPtrs& P, const int32_t* N, uint32_t len, u
     }
 }
 
-// Arc u->w for the live source bits m of u: OR the unseen ones into nxt[w];
-// nb_first[j] receives the bits this thread set first and *deg the degree
-// of w (for counting).  Returns whether w is new this level.
+// Arc u->w for the live source bits m of u: OR the unseen ones into nxt[w]
+// (the per-source counters are taken later, once per reached node).  Returns
+// whether w is new this level.
 template <int WW>
-__device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp, uint64_t* nb_first, uint32_t* degw) {
+__device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp) {
     using Lo = Layout<WW>;
     uint64_t nb[WW];
     uint64_t any = 0;
-#pragma unroll
-    for (int j = 0; j < WW; ++j) nb_first[j] = 0;
     if constexpr (WW == 1) {
         // seen and nxt share one 16-byte load; a stale nxt only costs an extra atomic
         const ulonglong2 sn = *reinterpret_cast<const ulonglong2*>(rec);
@@ -398,18 +370,14 @@ __device__ inline bool visit(uint64_t* rec, const uint64_t* m, uint32_t stamp, u
         }
     }
     if (!any) return false;
-    *degw = (uint32_t)(rec[Lo::META] >> 32);
     if constexpr (WW == 1) {
-        const uint64_t old = atomicOr((unsigned long long*)&rec[Lo::NXT], (unsigned long long)nb[0]);
-        nb_first[0] = nb[0] & ~old;
-        return old == 0ull;
+        // one word: the first toucher is the one that finds nxt empty (stamp unused)
+        (void)stamp;
+        return atomicOr((unsigned long long*)&rec[Lo::NXT], (unsigned long long)nb[0]) == 0ull;
     } else {
 #pragma unroll
-        for (int j = 0; j < WW; ++j) {
-            if (!nb[j]) continue;
-            const uint64_t old = atomicOr((unsigned long long*)&rec[Lo::NXT + j], (unsigned long long)nb[j]);
-            nb_first[j] = nb[j] & ~old;
-        }
+        for (int j = 0; j < WW; ++j)
+            if (nb[j]) atomicOr((unsigned long long*)&rec[Lo::NXT + j], (unsigned long long)nb[j]);
         return atomicMax(reinterpret_cast<uint32_t*>(&rec[Lo::META]), stamp) < stamp;
     }
 }
@@ -455,11 +423,10 @@ struct LdsExpand {
 // Expand entries [e0, e1) (at most kBlk) of the frontier list F: every arc of
 // every entry with a live bit, balanced over the workgroup by a scan of the
 // degrees.  Nodes reached for the first time this level go to N once.
-template <int WW, int B = kBlk, bool kCount = true>
+template <int WW, int B = kBlk>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
                                const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW, B>& L,
-                               uint32_t* cg, unsigned long long* ct, unsigned long long* arcs,
-                               unsigned long long* entries) {
+                               unsigned long long* arcs, unsigned long long* entries) {
     using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     const uint32_t e = e0 + tid;
@@ -495,10 +462,6 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
         const uint32_t a = a0 + tid;
         bool app = false;
         int32_t w = 0;
-        uint64_t nbf[WW];
-        uint32_t dw = 0;
-#pragma unroll
-        for (int j = 0; j < WW; ++j) nbf[j] = 0;
         if (a < total) {
             // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
             uint32_t lo = 0, hi = B;
@@ -508,13 +471,7 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
             }
             const uint32_t i = lo - 1;
             w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
-            app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp, nbf, &dw);
-        }
-        if constexpr (kCount) {
-            if (cg) {
-#pragma unroll
-                for (int j = 0; j < WW; ++j) wave_count(nbf[j], dw, j, cg, ct);
-            }
+            app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp);
         }
         append_if(app, w, N, nctr);
     }
@@ -885,8 +842,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, C
         const uint32_t e0 = L.chunk * kBlk;
         __syncthreads();
         if (e0 >= flen) break;
-        expand_entries<WW, kBlk, false>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &C->nlen, stamp, L,
-                                        nullptr, nullptr, &s_arcs, &s_ent);
+        expand_entries<WW>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &C->nlen, stamp, L, &s_arcs, &s_ent);
     }
     if (tid == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
     if (tid == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
@@ -1141,8 +1097,8 @@ __global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order,
             if (tid == 0) s_nlen = 0;
             __syncthreads();
             for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                expand_entries<WW, B, false>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, cg,
-                                             ct, &s_narcs, &s_ent);
+                expand_entries<WW, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, &s_narcs,
+                                      &s_ent);
             __syncthreads();
             const uint32_t nlen = s_nlen;
             count_level<WW, B>(P, P.qb, nlen, cg, ct);
@@ -1667,7 +1623,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     ++stamp;
                     for (uint32_t e0 = 0; e0 < flen; e0 += B)
                         expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
-                                          nullptr, nullptr, &s_arcs, &s_arcs);
+                                             &s_arcs, &s_arcs);
                     __syncthreads();
                     const uint32_t nlen = s_nlen;
                     clear_cur<1>(P, P.qa, flen, 0, B);
@@ -1776,7 +1732,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         __syncthreads();
                         for (uint32_t e0 = 0; e0 < flen; e0 += B)
                             expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp,
-                                                 LE, nullptr, nullptr, &s_arcs, &s_arcs);
+                                                 LE, &s_arcs, &s_arcs);
                         __syncthreads();
                         const uint32_t nlen = s_nlen;
                         clear_cur<1>(P, P.qa, flen, 0, B);
@@ -1802,10 +1758,12 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 if (tid == 0) s_nlen = 0;
                 __syncthreads();
                 for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                    expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, cg, ct,
-                                      &s_narcs, &s_ent);
+                    expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
+                                         &s_narcs, &s_ent);
                 __syncthreads();
                 const uint32_t nlen = s_nlen;
+                count_level<1, B>(P, P.qb, nlen, cg, ct);
+                __syncthreads();
                 disc += nlen;
                 ++rec_lv;
                 uint64_t tq = __builtin_amdgcn_s_memrealtime();

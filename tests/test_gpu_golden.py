@@ -17,7 +17,15 @@ from paper_1507_01490_amd import workloads
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-NAMES = [n for n in ("ba1m", "rmat21") if os.path.exists(os.path.join(HERE, "golden", f"{n}.json"))]
+NAMES = [n for n in ("ba1m", "rmat21", "rgg18") if os.path.exists(os.path.join(HERE, "golden", f"{n}.json"))]
+CONFIGS = {
+    "ba1m": [dict(mode="batched"), dict(mode="batched", width=256), dict(mode="batched", order="learned_grouped")],
+    "rmat21": [dict(mode="batched"), dict(mode="batched", width=256), dict(mode="batched", order="learned_grouped")],
+    # the geometric graph: the locality order (the fast one there), both
+    # widths, and the learned order
+    "rgg18": [dict(mode="batched", order="locality", width=256), dict(mode="batched", order="locality", width=64),
+              dict(mode="batched", order="learned_grouped", width=256)],
+}
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -28,8 +36,7 @@ def test_full_size_against_oracle(name):
     with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
         for k, ref in gold["results"].items():
             k = int(k)
-            for kw in (dict(mode="batched"), dict(mode="batched", width=256),
-                       dict(mode="batched", order="learned_grouped")):
+            for kw in CONFIGS[name]:
                 res = G.topk(k, **kw)
                 assert res.ids.tolist() == ref["ids"], (name, k, kw)
                 assert [int(x) for x in res.farness] == ref["farness"], (name, k, kw)

@@ -58,6 +58,10 @@ def _load():
     lib.orc_scc.argtypes = [i32, P, P, P]
     lib.orc_scc.restype = i32
     lib.orc_alpha_omega.argtypes = [i32, P, P, P, P]
+    lib.orc_alpha_omega_ex.argtypes = [i32, P, P, ctypes.c_int, P, P]
+    lib.orc_topk_ex.argtypes = [i32, P, P, ctypes.c_int, i32, P, ctypes.c_int, ctypes.c_uint32, P, P, P, P, P,
+                                ctypes.POINTER(Stats)]
+    lib.orc_topk_ex.restype = i32
     lib.orc_topk.argtypes = [i32, P, P, ctypes.c_int, i32, P, ctypes.c_int, P, P, P, P, P,
                              ctypes.POINTER(Stats)]
     lib.orc_topk.restype = i32
@@ -120,17 +124,25 @@ def scc(g):
     return int(nc), comp[:g.n]
 
 
-def alpha_omega(g):
+def alpha_omega(g, big_scc: bool = False):
+    """alpha(v) <= r(v) <= omega(v) over the SCC DAG (Section 2.4); with
+    big_scc, the largest-SCC refinement of the same section."""
     lib = _load()
     rp, col = _csr(g)
     a = np.zeros(max(g.n, 1), np.uint32)
     o = np.zeros(max(g.n, 1), np.uint32)
-    lib.orc_alpha_omega(g.n, _p(rp), _p(col), _p(a), _p(o))
+    lib.orc_alpha_omega_ex(g.n, _p(rp), _p(col), int(bool(big_scc)), _p(a), _p(o))
     return a[:g.n], o[:g.n]
 
 
-def topk(g, k: int, order=None, nthreads: int = 1, trace: bool = False):
-    """Algorithm 1 with BFSCut.  Returns dict(ids, f, r, stats[, cut_level, mvis])."""
+FOOTNOTE = 0x1   # undirected: ~gamma_{d+1} with (degree - 1) for d >= 1 (Section 2.3 footnote)
+BIG_SCC = 0x2    # directed: reach bounds with the largest-SCC refinement (Section 2.4)
+
+
+def topk(g, k: int, order=None, nthreads: int = 1, trace: bool = False, footnote: bool = False,
+         big_scc: bool = False):
+    """Algorithm 1 with BFSCut.  Returns dict(ids, f, r, stats[, cut_level, mvis]).
+    footnote / big_scc switch on the optional tighter bounds (same result)."""
     lib = _load()
     rp, col = _csr(g)
     kk = max(0, min(int(k), g.n))
@@ -141,8 +153,9 @@ def topk(g, k: int, order=None, nthreads: int = 1, trace: bool = False):
     cl = np.zeros(max(g.n, 1), np.int32) if trace else None
     mv = np.zeros(max(g.n, 1), np.uint64) if trace else None
     st = Stats()
-    cnt = lib.orc_topk(g.n, _p(rp), _p(col), int(g.directed), int(k), _p(o), int(nthreads),
-                       _p(ids), _p(f), _p(r), _p(cl), _p(mv), ctypes.byref(st))
+    flags = (FOOTNOTE if footnote else 0) | (BIG_SCC if big_scc else 0)
+    cnt = lib.orc_topk_ex(g.n, _p(rp), _p(col), int(g.directed), int(k), _p(o), int(nthreads), flags,
+                          _p(ids), _p(f), _p(r), _p(cl), _p(mv), ctypes.byref(st))
     if cnt < 0:
         raise MemoryError("oracle allocation failed")
     out = dict(ids=ids[:cnt].copy(), f=f[:cnt].copy(), r=r[:cnt].copy(),

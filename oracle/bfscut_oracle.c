@@ -25,7 +25,12 @@
  *   orc_reach_undirected r(v) = size of the connected component (Section 2.3)
  *   orc_scc             strongly connected components (iterative Tarjan)
  *   orc_alpha_omega     alpha/omega bounds on r(v) over the SCC DAG (Section 2.4)
+ *   orc_alpha_omega_ex  the same, optionally with the largest-SCC refinement
+ *                       described at the end of Section 2.4
  *   orc_topk            Algorithm 1 with the BFSCut function of Section 2.5
+ *   orc_topk_ex         the same, optionally with the tighter bounds the paper
+ *                       gives beside the main ones (the undirected footnote of
+ *                       Section 2.3 and the largest-SCC refinement)
  *
  * Parity status: pinned (see the oracle tests: closed forms, brute force
  * against SciPy and NetworkX, per-source cut levels re-derived from
@@ -209,9 +214,21 @@ int32_t orc_scc(int32_t n, const int32_t* rp, const int32_t* col, int32_t* comp)
  * processing components in reverse topological order:
  *   alpha(C) = w(C) + max over (C,D) in E of alpha(D)   (0 without successor)
  *   omega(C) = w(C) + sum over (C,D) in E of omega(D),  capped at n
- * The cap keeps the value in range (r(v) <= n always holds). */
-void orc_alpha_omega(int32_t n, const int32_t* rp, const int32_t* col, uint32_t* alpha,
-                     uint32_t* omega) {
+ * The cap keeps the value in range (r(v) <= n always holds).
+ *
+ * With big_scc != 0 the refinement at the end of Section 2.4 is applied:
+ *   - the biggest SCC T (largest w; among equals the one holding the
+ *     smallest node id) is not evaluated by the recurrence: a BFS from one
+ *     of its nodes gives the exact reach rT = |R(T)|, so alpha(T) = omega(T)
+ *     = rT, and the recurrence carries this exact value to every component
+ *     that reaches T;
+ *   - for a component C that reaches T (C != T), a second upper bound is
+ *     rT + omega'(C), where omega' is the same recurrence on the DAG with
+ *     every component reachable from T (T included) removed: the nodes that
+ *     C reaches outside R(T) are exactly those it reaches in that DAG.
+ *     omega(C) is the smaller of the two bounds. */
+void orc_alpha_omega_ex(int32_t n, const int32_t* rp, const int32_t* col, int big_scc, uint32_t* alpha,
+                        uint32_t* omega) {
     size_t N = (size_t)(n > 0 ? n : 1);
     int32_t* comp = (int32_t*)malloc(sizeof(int32_t) * N);
     int32_t nc = orc_scc(n, rp, col, comp);
@@ -226,11 +243,30 @@ void orc_alpha_omega(int32_t n, const int32_t* rp, const int32_t* col, uint32_t*
     for (int32_t v = 0; v < n; ++v) members[fill[comp[v]]++] = v;
     uint64_t* a = (uint64_t*)malloc(sizeof(uint64_t) * NC);
     uint64_t* o = (uint64_t*)malloc(sizeof(uint64_t) * NC);
+    uint64_t* o2 = (uint64_t*)malloc(sizeof(uint64_t) * NC);   /* omega' (outside R(T)) */
+    char* inRT = (char*)calloc(NC, 1);                          /* component in R(T)     */
+    char* toT = (char*)calloc(NC, 1);                           /* component reaches T   */
     int32_t* seen = (int32_t*)malloc(sizeof(int32_t) * NC);
     for (int32_t c = 0; c < nc; ++c) seen[c] = -1;
+    int32_t T = -1;
+    uint64_t rT = 0;
+    if (big_scc && n > 0) {
+        /* members[] lists each component's nodes in increasing id, so the
+         * first member is the component's smallest node */
+        for (int32_t c = 0; c < nc; ++c) {
+            if (T < 0) { T = c; continue; }
+            int32_t wc = cstart[c + 1] - cstart[c], wt = cstart[T + 1] - cstart[T];
+            if (wc > wt || (wc == wt && members[cstart[c]] < members[cstart[T]])) T = c;
+        }
+        int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * N);
+        orc_bfs(n, rp, col, members[cstart[T]], dist);
+        for (int32_t v = 0; v < n; ++v)
+            if (dist[v] >= 0) { rT += 1; inRT[comp[v]] = 1; }
+        free(dist);
+    }
     for (int32_t c = 0; c < nc; ++c) {   /* completion order = reverse topological */
         uint64_t w = (uint64_t)(cstart[c + 1] - cstart[c]);
-        uint64_t amax = 0, osum = 0;
+        uint64_t amax = 0, osum = 0, osum2 = 0;
         for (int32_t i = cstart[c]; i < cstart[c + 1]; ++i) {
             int32_t v = members[i];
             for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
@@ -240,17 +276,39 @@ void orc_alpha_omega(int32_t n, const int32_t* rp, const int32_t* col, uint32_t*
                 if (a[d] > amax) amax = a[d];
                 osum += o[d];
                 if (osum > (uint64_t)n) osum = (uint64_t)n;
+                if (d == T || toT[d]) toT[c] = 1;
+                if (!inRT[d]) {
+                    osum2 += o2[d];
+                    if (osum2 > (uint64_t)n) osum2 = (uint64_t)n;
+                }
             }
+        }
+        if (c == T) {
+            a[c] = o[c] = rT;   /* exact, from the BFS */
+            o2[c] = 0;
+            continue;
         }
         a[c] = w + amax;
         o[c] = w + osum;
         if (o[c] > (uint64_t)n) o[c] = (uint64_t)n;
+        o2[c] = w + osum2;
+        if (o2[c] > (uint64_t)n) o2[c] = (uint64_t)n;
+        if (toT[c]) {
+            uint64_t b = rT + o2[c];
+            if (b > (uint64_t)n) b = (uint64_t)n;
+            if (b < o[c]) o[c] = b;
+        }
     }
     for (int32_t v = 0; v < n; ++v) {
         alpha[v] = (uint32_t)a[comp[v]];
         omega[v] = (uint32_t)o[comp[v]];
     }
-    free(comp); free(cstart); free(members); free(fill); free(a); free(o); free(seen);
+    free(comp); free(cstart); free(members); free(fill); free(a); free(o); free(o2); free(inRT); free(toT);
+    free(seen);
+}
+
+void orc_alpha_omega(int32_t n, const int32_t* rp, const int32_t* col, uint32_t* alpha, uint32_t* omega) {
+    orc_alpha_omega_ex(n, rp, col, 0, alpha, omega);
 }
 
 /* ------------------------------------------------------------ top-k list */
@@ -291,6 +349,7 @@ typedef struct {
     const int32_t *rp, *col;
     int directed;
     const uint32_t *X0, *X1;  /* undirected: X0 = r; directed: X0 = alpha, X1 = omega */
+    int footnote;             /* undirected: ~gamma_{d+1} = sum of (deg - 1) over Gamma_d, d >= 1 */
 } graph_t;
 
 /* Cut rule of the BFSCut function at level d, right after Gamma_d(v) is
@@ -332,6 +391,9 @@ enum { RES_DONE = 0, RES_CUT = 1, RES_TRIVIAL = 2 };
 /* The BFSCut function (Section 2.5): BFS from v, tracking
  *   n_d = |N_d(v)|, f_d = sum of distances over N_d(v),
  *   gt  = ~gamma_{d+1}(v) = sum of out-degrees over Gamma_d(v) (Table 1),
+ *         or, with G->footnote on an undirected graph and d >= 1, the sum of
+ *         (degree - 1): one edge of each node of Gamma_d leads back to
+ *         Gamma_{d-1} (the footnote of Section 2.3),
  * testing the cut rule whenever a whole level is known.  Returns RES_CUT with
  * the level of the cut, or RES_DONE with the exact r(v) and f(v).  m_vis
  * counts the arcs scanned. */
@@ -377,7 +439,10 @@ static int bfscut(const graph_t* G, scratch_t* S, int32_t v, const rec_t* th, ui
         nd += cnt;
         fd += (uint64_t)d * cnt;
         gt = 0;
-        for (int64_t i = qe; i < ne; ++i) gt += (uint64_t)(rp[S->queue[i] + 1] - rp[S->queue[i]]);
+        for (int64_t i = qe; i < ne; ++i) {
+            uint64_t deg = (uint64_t)(rp[S->queue[i] + 1] - rp[S->queue[i]]);
+            gt += (G->footnote && !G->directed && deg > 0) ? deg - 1 : deg;
+        }
         qb = qe; qe = ne;
     }
 }
@@ -449,6 +514,11 @@ static int cmp_degree_order(const void* a, const void* b) {
     return (x > y) - (x < y);               /* then increasing id */
 }
 
+/* orc_topk_ex flags: the optional tighter bounds (each leaves the result
+ * unchanged and can only cut earlier). */
+#define ORC_FOOTNOTE 0x1u   /* undirected ~gamma with (degree - 1) for d >= 1 (Section 2.3 footnote) */
+#define ORC_BIG_SCC  0x2u   /* directed reach bounds with the largest-SCC refinement (Section 2.4) */
+
 /* Algorithm 1: canonicalise, compute the reach data, then for every node in
  * the given order (decreasing out-degree, ties by increasing id, when
  * order == NULL) run BFSCut against the current k-th best record and keep
@@ -458,9 +528,9 @@ static int cmp_degree_order(const void* a, const void* b) {
  * key order); cut_level[v] (-2 trivial, -1 completed, d >= 0 cut at level d)
  * and mvis_node[v] are optional per-node traces.  Returns the entry count,
  * or -1 on an allocation failure. */
-int32_t orc_topk(int32_t n, const int32_t* rp_in, const int32_t* col_in, int directed, int32_t k,
-                 const int32_t* order_in, int nthreads, int32_t* ids, uint64_t* f_out,
-                 uint32_t* r_out, int32_t* cut_level, uint64_t* mvis_node, orc_stats* st) {
+int32_t orc_topk_ex(int32_t n, const int32_t* rp_in, const int32_t* col_in, int directed, int32_t k,
+                    const int32_t* order_in, int nthreads, uint32_t flags, int32_t* ids, uint64_t* f_out,
+                    uint32_t* r_out, int32_t* cut_level, uint64_t* mvis_node, orc_stats* st) {
     if (k <= 0 || n <= 0) {
         if (st) memset(st, 0, sizeof(*st));
         return 0;
@@ -476,7 +546,7 @@ int32_t orc_topk(int32_t n, const int32_t* rp_in, const int32_t* col_in, int dir
     rec_t* recs = (rec_t*)malloc(sizeof(rec_t) * (size_t)kk);
     if (!rp || !col || !X0 || !X1 || !order || !recs) return -1;
     orc_canonicalize(n, rp_in, col_in, rp, col);
-    if (directed) orc_alpha_omega(n, rp, col, X0, X1);
+    if (directed) orc_alpha_omega_ex(n, rp, col, (flags & ORC_BIG_SCC) != 0, X0, X1);
     else { orc_reach_undirected(n, rp, col, X0); memcpy(X1, X0, sizeof(uint32_t) * N); }
     if (order_in) {
         memcpy(order, order_in, sizeof(int32_t) * N);
@@ -487,7 +557,7 @@ int32_t orc_topk(int32_t n, const int32_t* rp_in, const int32_t* col_in, int dir
         qsort(order, N, sizeof(int32_t), cmp_degree_order);
         free(deg);
     }
-    graph_t G = {n, rp, col, directed, X0, X1};
+    graph_t G = {n, rp, col, directed, X0, X1, (flags & ORC_FOOTNOTE) != 0};
     topk_t T = {recs, kk, 0};
     run_t R;
     memset(&R, 0, sizeof(R));
@@ -512,4 +582,11 @@ int32_t orc_topk(int32_t n, const int32_t* rp_in, const int32_t* col_in, int dir
     int32_t cnt = T.cnt;
     free(rp); free(col); free(X0); free(X1); free(order); free(recs);
     return cnt;
+}
+
+int32_t orc_topk(int32_t n, const int32_t* rp_in, const int32_t* col_in, int directed, int32_t k,
+                 const int32_t* order_in, int nthreads, int32_t* ids, uint64_t* f_out,
+                 uint32_t* r_out, int32_t* cut_level, uint64_t* mvis_node, orc_stats* st) {
+    return orc_topk_ex(n, rp_in, col_in, directed, k, order_in, nthreads, 0u, ids, f_out, r_out, cut_level,
+                       mvis_node, st);
 }

@@ -345,14 +345,16 @@ def test_alpha_omega_by_hand():
 
 # ---------------------------------- per-source trace from independent distances
 
-def rederive_trace(g, r_true, order, k):
+def rederive_trace(g, r_true, order, k, footnote=False, big_scc=False):
     """Sequential Algorithm 1 replayed from SciPy distances: for each source
     in order, the level where the cut rule first fires (or -1), and the arcs
-    scanned.  X = {r} (undirected) or {alpha, omega} (directed)."""
+    scanned.  X = {r} (undirected) or {alpha, omega} (directed).  footnote:
+    the undirected ~gamma_{d+1} for d >= 1 counts degree - 1 per node of
+    Gamma_d (Section 2.3 footnote)."""
     D = scipy_dist(g)
     deg = np.diff(g.row_ptr).astype(np.int64)
     if g.directed:
-        a, o = oracle.alpha_omega(g)
+        a, o = oracle.alpha_omega(g, big_scc=big_scc)
         X = [sorted({int(a[v]), int(o[v])}) for v in range(g.n)]
     else:
         X = [[int(r_true[v])] for v in range(g.n)]
@@ -378,7 +380,10 @@ def rederive_trace(g, r_true, order, k):
         for d in range(ecc + 1):
             nd = int((dist <= d).sum())
             fd = int(dist[dist <= d].sum())
-            gt = int(deg[nodes[dist == d]].sum())
+            arcs = int(deg[nodes[dist == d]].sum())
+            gt = arcs
+            if footnote and not g.directed and d >= 1:
+                gt -= int((dist == d).sum())
             if th is not None:
                 keyth, idth = th
                 vals = [Fraction(fd - gt + (d + 2) * (x - nd), (x - 1) ** 2) for x in X[v]]
@@ -387,7 +392,7 @@ def rederive_trace(g, r_true, order, k):
                                         (all(q >= inv for q in vals) and v > idth)):
                     res = d
                     break
-            scanned += gt
+            scanned += arcs
         cut[v], mv[v] = res, scanned
         if res == -1:
             rr, ff = int(fin.sum()), int(dist.sum())
@@ -452,3 +457,146 @@ def test_lemma_invariants(directed):
                           for x in (a[v], o[v]))
                 assert lam <= Fraction(int(f[v]), (int(r[v]) - 1) ** 2)
         assert prev == r[v]
+
+
+# ------------------------ the optional tighter bounds (Section 2.3 footnote, 2.4)
+
+def test_footnote_path7_by_hand():
+    """Path 0-...-6, k=1; order 1, 2, 3, 4, 5 (degree 2), then 0, 6.
+    Node 1 (f=16), node 2 (f=13) and node 3 (f=12) complete in turn.
+    Node 4 against f=12: with Table 1's ~gamma the level bounds are 10, 10,
+    11, then 9 - 2 + 5 = 12 at d = 3 (tie, id 4 > 3: cut there, after 2 + 4
+    + 3 arcs); with the footnote ~gamma_2 = 1 + 1, so d = 1 gives
+    2 - 2 + 3 * 4 = 12 and the cut comes after 2 arcs.  Node 5: cut at d = 2
+    (4 - 2 + 12 = 14) after 5 arcs, with the footnote at d = 1
+    (2 - 1 + 12 = 13) after 2.  Nodes 0 and 6 are cut at d = 1 either way."""
+    g = synth.path(7)
+    plain = oracle.topk(g, 1, trace=True)
+    foot = oracle.topk(g, 1, trace=True, footnote=True)
+    for o in (plain, foot):
+        assert o["ids"].tolist() == [3] and o["f"].tolist() == [12] and o["r"].tolist() == [7]
+    assert plain["cut_level"].tolist() == [1, -1, -1, -1, 3, 2, 1]
+    assert plain["mvis"].tolist() == [1, 12, 12, 12, 9, 5, 1]
+    assert foot["cut_level"].tolist() == [1, -1, -1, -1, 1, 1, 1]
+    assert foot["mvis"].tolist() == [1, 12, 12, 12, 2, 2, 1]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_footnote_trace_rederived_and_never_later(seed):
+    """The footnote bound replayed from SciPy distances gives the oracle's
+    cut levels and arcs; the answer equals the definition; and since the
+    bound is tighter at every level while the k-th record evolves the same
+    way, no source is cut later or scans more arcs than with Table 1's."""
+    rng = np.random.default_rng(500 + seed)
+    g = synth.barabasi_albert(150, 2, 40 + seed) if seed % 2 else synth.random_small(90, 0.04, False, 60 + seed)
+    r, f = scipy_rf(g)
+    k = [1, 5, 20][seed % 3]
+    order = rng.permutation(g.n).astype(np.int32) if seed % 3 == 2 else None
+    foot = oracle.topk(g, k, order=order, trace=True, footnote=True)
+    plain = oracle.topk(g, k, order=order, trace=True)
+    ids, ff, rr = oracle.topk_by_definition(r, f, k)
+    assert foot["ids"].tolist() == ids.tolist() and foot["f"].tolist() == ff.tolist()
+    assert foot["r"].tolist() == rr.tolist()
+    if order is None:
+        deg = np.diff(g.row_ptr)
+        order = np.lexsort((np.arange(g.n), -deg))
+    cut, mv = rederive_trace(g, r, order, k, footnote=True)
+    assert foot["cut_level"].tolist() == [cut[v] for v in range(g.n)]
+    assert foot["mvis"].tolist() == [mv[v] for v in range(g.n)]
+    assert np.all(foot["mvis"] <= plain["mvis"])
+    assert foot["stats"]["m_vis"] <= plain["stats"]["m_vis"]
+
+
+def test_footnote_lemma1_invariant():
+    """Lemma 1 with the footnote ~gamma: gamma_{d+1} <= sum over Gamma_d of
+    (deg - 1) for d >= 1, so f_d - ~gamma_{d+1} + (d+2)(r - n_d) <= f(v) at
+    every level of every BFS."""
+    for g in (synth.barabasi_albert(200, 3, 5), synth.random_small(80, 0.05, False, 7), synth.grid(6, 9)):
+        D = scipy_dist(g)
+        r, f = oracle.bruteforce(g)
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        for v in range(g.n):
+            row = D[v]
+            fin = np.isfinite(row)
+            dist = row[fin].astype(np.int64)
+            nodes = np.nonzero(fin)[0]
+            ecc = int(dist.max())
+            for d in range(ecc + 1):
+                lev = nodes[dist == d]
+                gt = int(deg[lev].sum()) - (len(lev) if d >= 1 else 0)
+                assert int((dist == d + 1).sum()) <= gt
+                nd = int((dist <= d).sum())
+                fd = int(dist[dist <= d].sum())
+                assert fd - gt + (d + 2) * (int(r[v]) - nd) <= int(f[v])
+
+
+def _largest_scc_nodes(g):
+    A = sp.csr_matrix((np.ones(g.m), g.col, g.row_ptr), shape=(g.n, g.n))
+    _, lab = connected_components(A, directed=True, connection="strong")
+    sizes = np.bincount(lab)
+    best = sizes.max()
+    # among the largest components, the one holding the smallest node id
+    first = min(int(np.nonzero(lab == c)[0][0]) for c in np.nonzero(sizes == best)[0])
+    return np.nonzero(lab == lab[first])[0]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_big_scc_bounds_bracket_reach_and_tighten(seed):
+    """alpha <= r <= omega still holds with the largest-SCC refinement, it
+    is never looser than the plain recurrence, and it is exact on the
+    largest SCC (r from SciPy distances)."""
+    g = synth.random_small(80, 0.012 + 0.004 * seed, True, 1300 + seed)
+    r, _ = scipy_rf(g)
+    a0, o0 = oracle.alpha_omega(g)
+    a, o = oracle.alpha_omega(g, big_scc=True)
+    assert np.all(a <= r) and np.all(r <= o) and np.all(o <= g.n)
+    assert np.all(a >= a0) and np.all(o <= o0)
+    big = _largest_scc_nodes(g)
+    assert np.all(a[big] == r[big]) and np.all(o[big] == r[big])
+
+
+def test_big_scc_by_hand():
+    """Cycle T = {0,1,2} (the largest SCC) with 0->3, 1->4, 3->5, 4->5; node 6
+    -> 0; 7, 8, 9 isolated (n = 10, no cap).  Plain recurrence: alpha(T) =
+    3 + 2 = 5 and omega(T) = 3 + 2 + 2 = 7, while R(T) = 6; node 6 gets
+    (6, 8).  Refined: T exact (6, 6), and node 6 gets alpha = 1 + 6 = 7 and
+    omega = min(1 + 6, 6 + omega'(6) = 6 + 1) = 7, its exact reach."""
+    g = synth.from_edges(10, [0, 1, 2, 0, 1, 3, 4, 6], [1, 2, 0, 3, 4, 5, 5, 0], directed=True)
+    a0, o0 = oracle.alpha_omega(g)
+    assert a0.tolist() == [5, 5, 5, 2, 2, 1, 6, 1, 1, 1]
+    assert o0.tolist() == [7, 7, 7, 2, 2, 1, 8, 1, 1, 1]
+    a, o = oracle.alpha_omega(g, big_scc=True)
+    assert a.tolist() == [6, 6, 6, 2, 2, 1, 7, 1, 1, 1]
+    assert o.tolist() == [6, 6, 6, 2, 2, 1, 7, 1, 1, 1]
+    # second bound alone: T = cycle {0,1,2} -> 3 -> 4, node 5 -> 0 and 5 -> 3,
+    # 6..8 isolated.  Plain omega(5) = 1 + 5 + 2 = 8; both successors lie in
+    # R(T), so omega'(5) = 1 and omega(5) = 5 + 1 = 6 = r(5).
+    g = synth.from_edges(9, [0, 1, 2, 2, 3, 5, 5], [1, 2, 0, 3, 4, 0, 3], directed=True)
+    a0, o0 = oracle.alpha_omega(g)
+    a, o = oracle.alpha_omega(g, big_scc=True)
+    assert (int(a0[5]), int(o0[5])) == (6, 8)
+    assert (int(a[5]), int(o[5])) == (6, 6)
+    # two largest SCCs of equal size: the one holding node 0 is refined
+    g = synth.from_edges(6, [0, 1, 2, 3, 0, 3], [1, 0, 3, 2, 4, 4], directed=True)
+    a, o = oracle.alpha_omega(g, big_scc=True)
+    assert a.tolist() == [3, 3, 3, 3, 1, 1]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_big_scc_trace_rederived(seed):
+    """Directed runs with the refined reach bounds: cut levels and arcs as
+    replayed from SciPy distances with the refined alpha/omega, the answer
+    of the definition, and never more arcs per source than the plain bounds."""
+    g = synth.random_small(70, 0.03 + 0.01 * (seed % 3), True, 2100 + seed)
+    r, f = scipy_rf(g)
+    k = [1, 4, 10][seed % 3]
+    got = oracle.topk(g, k, trace=True, big_scc=True)
+    plain = oracle.topk(g, k, trace=True)
+    ids, ff, rr = oracle.topk_by_definition(r, f, k)
+    assert got["ids"].tolist() == ids.tolist() and got["f"].tolist() == ff.tolist()
+    deg = np.diff(g.row_ptr)
+    order = np.lexsort((np.arange(g.n), -deg))
+    cut, mv = rederive_trace(g, r, order, k, big_scc=True)
+    assert got["cut_level"].tolist() == [cut[v] for v in range(g.n)]
+    assert got["mvis"].tolist() == [mv[v] for v in range(g.n)]
+    assert got["stats"]["m_vis"] <= plain["stats"]["m_vis"]

@@ -74,6 +74,12 @@ def main():
     ap.add_argument("--order", default="auto", choices=["auto", "degree", "grouped", "locality", "learned", "learned_grouped"],
                     help="source order of the timed mode (auto: grouped degree in batched mode)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
+    ap.add_argument("--footnote", type=int, default=0, choices=[0, 1],
+                    help="undirected footnote bound of Section 2.3 in the timed mode (same answer)")
+    ap.add_argument("--trial", type=int, default=1, choices=[0, 1],
+                    help="over-counted bound test before exact level counts in the persistent kernel (same answer)")
+    ap.add_argument("--big-scc", type=int, default=0, choices=[0, 1],
+                    help="directed: largest-SCC refinement of the reach bounds (Section 2.4; same answer)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=4, help="serve512: concurrent requests")
     ap.add_argument("--serve-slots", type=int, default=64, help="serve512: workgroups per persistent kernel")
@@ -128,12 +134,13 @@ def main():
     stream = torch.cuda.current_stream()
     rp = torch.from_numpy(g.row_ptr).cuda()
     col = torch.from_numpy(g.col).cuda()
-    G = bc.Graph(rp, col, directed=g.directed, stream=stream)
+    G = bc.Graph(rp, col, directed=g.directed, stream=stream, big_scc=bool(args.big_scc))
     del rp, col
     log(f"[bench] graph resident on GPU, pre-processing {G.preprocess_ms:.1f} ms")
 
-    def step(mode, order=args.order):
-        return [G.topk(k, mode=mode, width=args.width, slots=args.slots, order=order) for k in ks]
+    def step(mode, order=args.order, footnote=bool(args.footnote)):
+        return [G.topk(k, mode=mode, width=args.width, slots=args.slots, order=order, footnote=footnote,
+                       trial=bool(args.trial)) for k in ks]
 
     def check(results):
         if gold is None:
@@ -150,7 +157,8 @@ def main():
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     agg = dict(persistent_ms=0.0, seed_ms=0.0, defer_ms=0.0, n_deferred=0, arcs=0, entries=0, disc=0, m_vis=0,
-               node_arcs=0, levels=0)
+               node_arcs=0, levels=0, lds_levels=0, record_levels=0, spills=0, record_ms=0.0, record_arcs=0,
+               phase_ms=[0.0] * 5)
     parity = True if gold is not None else None  # None: no stored oracle answer for this workload
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -167,6 +175,9 @@ def main():
             agg["m_vis"] += s["m_vis"]
             agg["node_arcs"] += s["node_arcs"]
             agg["levels"] += s["levels"]
+            for key in ("lds_levels", "record_levels", "spills", "record_ms", "record_arcs"):
+                agg[key] += s[key]
+            agg["phase_ms"] = [a + b for a, b in zip(agg["phase_ms"], s["phase_ms"])]
         c = check(out)
         if parity is not None:
             parity = parity and bool(c)
@@ -180,11 +191,11 @@ def main():
 
     plain = None
     if args.plain_steps > 0 and args.mode != "plain":
-        step("plain", "degree")  # plain-mode workspace already sized; one untimed pass
+        step("plain", "degree", False)  # plain-mode workspace already sized; one untimed pass
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            pout = step("plain", "degree")
+            pout = step("plain", "degree", False)
         torch.cuda.synchronize()
         pms = (time.perf_counter() - tp0) * 1e3 / args.plain_steps
         pc = check(pout)
@@ -230,7 +241,9 @@ def main():
                 warmup=args.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="int64", data="synthetic",
                 config=dict(workload=workloads.DESCRIPTION[args.workload], k=ks, mode=args.mode,
-                            width=args.width, order=args.order, parity_vs_oracle=parity,
+                            width=args.width, order=args.order, footnote=bool(args.footnote),
+                            trial=bool(args.trial),
+                            big_scc=bool(args.big_scc), parity_vs_oracle=parity,
                             work_m_vis=int(work)),
                 breakdown_ms_per_step=dict(seed=round(agg["seed_ms"] / args.steps, 3),
                                            persistent=round(agg["persistent_ms"] / args.steps, 3),
@@ -238,6 +251,12 @@ def main():
                                            n_deferred=agg["n_deferred"] // args.steps,
                                            node_arcs=agg["node_arcs"] // args.steps,
                                            m_vis_gpu=agg["m_vis"] // args.steps),
+                persistent_detail=dict(
+                    lds_levels=agg["lds_levels"] // args.steps, record_levels=agg["record_levels"] // args.steps,
+                    spills=agg["spills"] // args.steps, record_arcs=agg["record_arcs"] // args.steps,
+                    workgroup_ms_record=round(agg["record_ms"] / args.steps, 1),
+                    workgroup_ms_phases=dict(zip(("setup", "count", "cut", "build", "reset"),
+                                                 [round(x / args.steps, 1) for x in agg["phase_ms"]]))),
                 roofline=roofline, cpu_baseline=cpu, plain=plain)
     print(json.dumps(line), flush=True)
     G.close()

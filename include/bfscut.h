@@ -50,6 +50,12 @@ typedef struct bc_graph bc_graph;
 #define BC_DIRECTED    0x1u  /* arcs are directed (else every edge must appear in both rows) */
 #define BC_VALIDATE    0x2u  /* undirected only: reject a CSR that is not symmetric           */
 #define BC_DEVICE_PTRS 0x4u  /* row_ptr / col are device pointers (read, never kept)          */
+#define BC_BIG_SCC     0x8u  /* directed only: reach bounds with the largest-SCC refinement at the
+                                end of Section 2.4: the largest SCC (largest size; among equals the
+                                one holding the smallest node id) gets its exact reach from one
+                                breadth-first search, and every component that reaches it also gets
+                                the upper bound |R(largest)| + the recurrence over the components
+                                outside R(largest).  Tighter bounds, same results               */
 
 /* Source processing order (Algorithm 1 processes nodes in decreasing degree). */
 #define BC_ORDER_DEGREE 0    /* decreasing out-degree, ties by increasing id (the paper's order) */
@@ -74,6 +80,18 @@ typedef struct bc_graph bc_graph;
 /* Parameters of the order perceptron 3 -> 64 -> 64 -> 1 (ReLU, fp32), one flat vector:
  * W1[64][3] @0, b1[64] @192, W2[64][64] @256, b2[64] @4352, w3[64] @4416, b3 @4480. */
 #define BC_MLP_PARAMS 4481
+
+/* bc_opts.bounds: optional tighter bounds (each leaves the result unchanged and
+ * can only cut a source earlier). */
+#define BC_BOUND_FOOTNOTE 0x1u  /* undirected graphs: for d >= 1, ~gamma_{d+1} sums (degree - 1) over
+                                   Gamma_d, since one edge of each of its nodes leads back to
+                                   Gamma_{d-1} (the footnote of Section 2.3); ignored on directed
+                                   graphs                                                        */
+#define BC_BOUND_NO_TRIAL 0x2u  /* batched mode, W = 64: skip the over-counted bound test that runs
+                                   before a level's exact count (counts taken per arc without
+                                   deduplication are at least gamma and ~gamma, so the bound they
+                                   give is weaker than Lemma 1 / Lemma 2's and still valid; a source
+                                   it cuts skips the exact count).  For measurement and tests     */
 
 /* Execution mode.  Neither changes the result, only the speed. */
 #define BC_MODE_PLAIN   0    /* one batch of W sources at a time, level-synchronous
@@ -111,6 +129,7 @@ typedef struct bc_opts {
     int32_t seed_width;     /* BC_MODE_BATCHED: sources per seed batch, a multiple of width
                                up to 256 (0 = width, or 256 when k > width);
                                seed_batches counts these batches                         */
+    uint32_t bounds;        /* BC_BOUND_* flags (default 0: the bounds of Table 1)        */
 } bc_opts;
 
 typedef struct bc_stats {
@@ -160,7 +179,7 @@ const char* bc_version(void);
  *   n        node count, 0 <= n < 2^31
  *   row_ptr  n + 1 int32 offsets, row_ptr[0] = 0, non-decreasing, row_ptr[n] = m
  *   col      m int32 targets in [0, n)
- *   flags    BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS
+ *   flags    BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS | BC_BIG_SCC
  *   stream   hipStream_t used by this graph's work (NULL = default stream)
  *   out      receives the handle; release it with bc_graph_destroy
  *
@@ -169,7 +188,8 @@ const char* bc_version(void);
  * arcs; these are removed on the device (they change no distance).  The
  * pre-processing follows Section 2.3 (undirected: r(v) = size of the
  * connected component) and Section 2.4 (directed: alpha(v) <= r(v) <=
- * omega(v) from the weighted DAG of strongly connected components).
+ * omega(v) from the weighted DAG of strongly connected components, with
+ * BC_BIG_SCC also the largest-SCC refinement of the same section).
  *
  * Errors: BC_EINVAL (n < 0, NULL pointer), BC_EGRAPH (row_ptr[0] != 0,
  * decreasing row_ptr, row_ptr[n] != m, col outside [0, n), or with

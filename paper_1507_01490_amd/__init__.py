@@ -32,7 +32,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.s
 # trained parameters of the order perceptron (written by train_order.py)
 MLP_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "order_mlp.npy")
 
-BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS = 0x1, 0x2, 0x4
+BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS, BC_BIG_SCC = 0x1, 0x2, 0x4, 0x8
+BC_BOUND_FOOTNOTE, BC_BOUND_NO_TRIAL = 0x1, 0x2
 ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_LEARNED_GROUPED, ORDER_AUTO = \
     0, 1, 2, 3, 4, 5, -1
 ORDER_LOCALITY = 6
@@ -55,7 +56,7 @@ class Opts(ctypes.Structure):
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("defer_arcs", ctypes.c_int32),
                 ("lds_tables", ctypes.c_int32), ("defer_width", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("graph_levels", ctypes.c_int32), ("seed_width", ctypes.c_int32)]
+                ("graph_levels", ctypes.c_int32), ("seed_width", ctypes.c_int32), ("bounds", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -235,7 +236,7 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
 
 def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=14.0, pull_beta=24.0,
               slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None, defer_width=0,
-              graph_levels=None, seed_width=0) -> Opts:
+              graph_levels=None, seed_width=0, footnote=False, trial=True) -> Opts:
     """bc_opts for a graph of n nodes; host arrays the options point at are
     appended to `keep` (they must outlive the call that reads them)."""
     lib = load_library()
@@ -254,6 +255,7 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
     o.lds_tables = 1 if lds_tables == "spill" else (0 if lds_tables else -1)
     o.defer_width = int(defer_width)
     o.seed_width = int(seed_width)
+    o.bounds = (BC_BOUND_FOOTNOTE if footnote else 0) | (0 if trial else BC_BOUND_NO_TRIAL)
     if graph_levels is not None:
         o.graph_levels = int(graph_levels)
     if isinstance(order, str) and order in ("learned", "learned_grouped"):
@@ -314,11 +316,13 @@ class Graph:
     """A CSR graph resident on the GPU with its pre-processed reach data.
 
     ``row_ptr``/``col`` are int32 numpy arrays (host) or int32 torch CUDA
-    tensors (device); either way the library copies them."""
+    tensors (device); either way the library copies them.  big_scc: directed
+    reach bounds with the largest-SCC refinement (BC_BIG_SCC)."""
 
-    def __init__(self, row_ptr, col, directed: bool = False, validate: bool = False, stream=None):
+    def __init__(self, row_ptr, col, directed: bool = False, validate: bool = False, stream=None,
+                 big_scc: bool = False):
         lib = load_library()
-        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0)
+        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0) | (BC_BIG_SCC if big_scc else 0)
         if _is_torch(row_ptr):
             if not row_ptr.is_cuda:
                 row_ptr, col = row_ptr.numpy(), col.numpy()
@@ -400,7 +404,7 @@ class Graph:
              pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
              seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
              lds_tables: bool = True, mlp=None, defer_width: int = 0, graph_levels=None,
-             seed_width: int = 0) -> TopK:
+             seed_width: int = 0, footnote: bool = False, trial: bool = True) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
         order: None (automatic), "degree", "grouped", "locality" (breadth-first
@@ -408,12 +412,14 @@ class Graph:
         perceptron `mlp`, default the trained one), "learned_grouped" (the
         seed-batch sources by learned score, then the grouped order), or a
         permutation of range(n); scores: per-node floats (decreasing score
-        first)."""
+        first); footnote: the undirected footnote bound (BC_BOUND_FOOTNOTE); trial=False skips
+        the over-counted bound test before exact level counts (BC_BOUND_NO_TRIAL)."""
         keep = []
         o = self._opts(mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
                        lds_tables, mlp, keep)
         o.defer_width = int(defer_width)
         o.seed_width = int(seed_width)
+        o.bounds = (BC_BOUND_FOOTNOTE if footnote else 0) | (0 if trial else BC_BOUND_NO_TRIAL)
         if graph_levels is not None:
             o.graph_levels = int(graph_levels)
         kk = max(1, int(k))
@@ -486,11 +492,11 @@ class Server:
         self._n = {}
         self._k = {}
 
-    def add_graph(self, row_ptr, col, directed: bool = False, validate: bool = False) -> int:
+    def add_graph(self, row_ptr, col, directed: bool = False, validate: bool = False, big_scc: bool = False) -> int:
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         cl = np.ascontiguousarray(col, dtype=np.int32)
         gid = ctypes.c_int32()
-        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0)
+        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0) | (BC_BIG_SCC if big_scc else 0)
         _check(load_library().bc_server_add_graph(self._h, int(rp.shape[0]) - 1, int(cl.shape[0]), _ptr(rp),
                                                   _ptr(cl) if cl.shape[0] else None, flags, ctypes.byref(gid)))
         self._n[gid.value] = int(rp.shape[0]) - 1

@@ -42,7 +42,10 @@ bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32
     *out = nullptr;
     if (n < 0 || m < 0) { set_error("negative size"); return BC_EINVAL; }
     if (!row_ptr || (m > 0 && !col)) { set_error("row_ptr/col is NULL"); return BC_EINVAL; }
-    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS)) { set_error("unknown flag bits"); return BC_EINVAL; }
+    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS | BC_BIG_SCC)) {
+        set_error("unknown flag bits");
+        return BC_EINVAL;
+    }
     std::unique_ptr<bc_graph> g(new bc_graph());
     g->stream = stream;
     g->ordered = ordered;
@@ -153,6 +156,10 @@ static bc_status copy_opts(const bc_opts* opts, bc_opts* o) {
         }
         std::memcpy(o, opts, opts->size);
         o->size = sizeof(bc_opts);
+        if (o->bounds & ~(uint32_t)(BC_BOUND_FOOTNOTE | BC_BOUND_NO_TRIAL)) {
+            set_error("unknown bounds bits 0x%x", o->bounds);
+            return BC_EINVAL;
+        }
     }
     return BC_OK;
 }

@@ -171,6 +171,7 @@ struct bc_graph {
     std::unique_ptr<bc::Workspace> ws;      // cached workspace (one query at a time)
     std::mutex cache_mu;                    // guards building the cached orders and features
     bool ordered = false;                   // graph buffers are stream-ordered allocations (server graphs)
+    bool big_scc = false;                   // directed reach bounds with the largest-SCC refinement
 };
 
 namespace bc {

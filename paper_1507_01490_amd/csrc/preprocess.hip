@@ -595,6 +595,7 @@ bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp_in, c
         }
         BC_HIP(hipStreamSynchronize(s));
     } else {
+        g->big_scc = (flags & BC_BIG_SCC) != 0;
         BC_TRY(directed_reach(g));
     }
     BC_HIP(hipGetLastError());

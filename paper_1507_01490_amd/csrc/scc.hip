@@ -6,6 +6,15 @@
 // evaluated in reverse topological order (a component once all of its
 // successors are known).
 //
+// Optional refinement (end of Section 2.4, graph flag BC_BIG_SCC): the
+// largest component T (largest w; among equals the one holding the smallest
+// node id) takes its exact reach rT = |R(T)| from one breadth-first search
+// instead of the recurrence, so alpha(T) = omega(T) = rT and the exact value
+// flows into every component that reaches T.  Such a component C also gets
+// the upper bound rT + omega'(C), where omega' is the same recurrence over
+// the components outside R(T) only (what C reaches outside R(T) is exactly
+// what it reaches in the DAG without R(T)); omega(C) is the smaller bound.
+//
 // SCCs are found on the GPU without recursion:
 //   1. trim: a node with no remaining in-arc or no remaining out-arc is a
 //      singleton SCC (repeated a few times);
@@ -221,15 +230,24 @@ __global__ void k_dag_fill(int32_t na, const uint64_t* __restrict__ keys, const 
     }
 }
 
+// The refinement's inputs (BigScc::c < 0: plain recurrence only).
+struct BigScc {
+    int32_t c;            // component T
+    uint64_t rT;          // |R(T)|
+    const int32_t* inRT;  // per component: 1 if reachable from T (T included)
+    uint64_t* omega2;     // per component outside R(T): omega' (recurrence outside R(T))
+    int32_t* toT;         // per component: 1 if it reaches T (T itself: 0)
+};
+
 // one round of the alpha/omega recurrence: every component whose successors
 // are all final becomes final
 __global__ void k_dag_round(int32_t nc, const int32_t* __restrict__ drp, const int32_t* __restrict__ dcol,
                             const uint32_t* __restrict__ wsize, uint64_t* alpha, uint64_t* omega,
-                            int32_t* done, uint64_t ncap, int32_t* left) {
+                            int32_t* done, uint64_t ncap, int32_t* left, BigScc B) {
     GSTRIDE_LOOP(c, nc) {
         if (done[c]) continue;
-        uint64_t amax = 0, osum = 0;
-        bool ready = true;
+        uint64_t amax = 0, osum = 0, osum2 = 0;
+        bool ready = true, reaches = false;
         for (int32_t e = drp[c]; e < drp[c + 1]; ++e) {
             int32_t d = dcol[e];
             if (!__hip_atomic_load(&done[d], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) { ready = false; break; }
@@ -238,14 +256,75 @@ __global__ void k_dag_round(int32_t nc, const int32_t* __restrict__ drp, const i
             if (a > amax) amax = a;
             osum += o;
             if (osum > ncap) osum = ncap;
+            if (B.c >= 0) {
+                if (d == B.c || __hip_atomic_load(&B.toT[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    reaches = true;
+                if (!B.inRT[d]) {
+                    osum2 += __hip_atomic_load(&B.omega2[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (osum2 > ncap) osum2 = ncap;
+                }
+            }
         }
         if (!ready) { atomicAdd(left, 1); continue; }
         uint64_t w = wsize[c];
+        uint64_t a = w + amax;
         uint64_t o = w + osum;
         if (o > ncap) o = ncap;
-        __hip_atomic_store(&alpha[c], w + amax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (B.c >= 0) {
+            uint64_t o2 = w + osum2;
+            if (o2 > ncap) o2 = ncap;
+            if (c == B.c) {
+                a = o = B.rT;  // exact, from the breadth-first search
+                o2 = 0;
+            } else if (reaches) {
+                uint64_t b = B.rT + o2;
+                if (b > ncap) b = ncap;
+                if (b < o) o = b;
+            }
+            __hip_atomic_store(&B.omega2[c], o2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&B.toT[c], reaches ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __hip_atomic_store(&alpha[c], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&omega[c], o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&done[c], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The largest component: max over nodes of (w(cid[v]) << 32 | (2^31 - 1 - v)),
+// i.e. the largest size, then the smallest node id.  Wave-reduced, one
+// atomic per wave.
+__global__ void k_big_pick(int32_t n, const int32_t* __restrict__ cid, const uint32_t* __restrict__ wsize,
+                           unsigned long long* best) {
+    unsigned long long mx = 0;
+    GSTRIDE_LOOP(v, n) {
+        unsigned long long key = ((unsigned long long)wsize[cid[v]] << 32) | (uint32_t)(0x7FFFFFFF - (int32_t)v);
+        if (key > mx) mx = key;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(mx, off);
+        if (o > mx) mx = o;
+    }
+    if (__lane_id() == 0 && mx) atomicMax(best, mx);
+}
+
+// one level of an unrestricted breadth-first search; mark[] = 1 once reached
+__global__ void k_bfs_level(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, uint32_t* mark,
+                            const int32_t* __restrict__ fq, int32_t fn, int32_t* nq, int32_t* ncnt) {
+    GSTRIDE_LOOP(i, fn) {
+        int32_t u = fq[i];
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t w = col[e];
+            if (mark[w] || atomicOr(&mark[w], 1u)) continue;
+            nq[atomicAdd(ncnt, 1)] = w;
+        }
+    }
+}
+
+// inRT[c] = 1 for every component holding a node the search reached
+__global__ void k_mark_comps(int32_t n, const uint32_t* __restrict__ mark, const int32_t* __restrict__ cid,
+                             int32_t* inRT) {
+    GSTRIDE_LOOP(v, n) {
+        if (mark[v]) inRT[cid[v]] = 1;
     }
 }
 
@@ -440,11 +519,51 @@ bc_status directed_reach(bc_graph* g) {
     BC_TRY(omega.alloc_on(sizeof(uint64_t) * NC, s));
     BC_TRY(done.alloc_on(sizeof(int32_t) * NC, s));
     BC_HIP(hipMemsetAsync(done.p, 0, sizeof(int32_t) * NC, s));
+    // largest-SCC refinement: T, its exact reach, the components in R(T)
+    BigScc big{-1, 0, nullptr, nullptr, nullptr};
+    DevBuf inRT, omega2, toT;
+    if (g->big_scc && nc > 0) {
+        BC_HIP(hipMemsetAsync(best.p, 0, sizeof(unsigned long long), s));
+        k_big_pick<<<grid_for(n), kBlk, 0, s>>>(n, cid.as<int32_t>(), wsize.as<uint32_t>(),
+                                                best.as<unsigned long long>());
+        unsigned long long bk = 0;
+        BC_HIP(hipMemcpyAsync(&bk, best.p, sizeof(bk), hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        const int32_t root = 0x7FFFFFFF - (int32_t)(uint32_t)(bk & 0xFFFFFFFFu);
+        if (root < 0 || root >= n) {
+            set_error("internal: largest SCC root %d out of range", root);
+            return BC_EDEVICE;
+        }
+        uint32_t* mk = mark.as<uint32_t>();
+        BC_HIP(hipMemsetAsync(mk, 0, sizeof(uint32_t) * N, s));
+        const uint32_t one = 1;
+        BC_HIP(hipMemcpyAsync(mk + root, &one, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        BC_HIP(hipMemcpyAsync(q0.p, &root, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        uint64_t reached = 1;
+        int32_t fn = 1;
+        int32_t *fq = q0.as<int32_t>(), *nq = q1.as<int32_t>();
+        while (fn > 0) {
+            BC_HIP(hipMemsetAsync(fl + 1, 0, sizeof(int32_t), s));
+            k_bfs_level<<<grid_for(fn), kBlk, 0, s>>>(rp, col, mk, fq, fn, nq, fl + 1);
+            BC_TRY(read_i32(fl + 1, &fn, s));
+            reached += (uint64_t)fn;
+            std::swap(fq, nq);
+        }
+        int32_t c_big = 0;
+        BC_TRY(read_i32(cid.as<int32_t>() + root, &c_big, s));
+        BC_TRY(inRT.alloc_on(sizeof(int32_t) * NC, s));
+        BC_TRY(omega2.alloc_on(sizeof(uint64_t) * NC, s));
+        BC_TRY(toT.alloc_on(sizeof(int32_t) * NC, s));
+        BC_HIP(hipMemsetAsync(inRT.p, 0, sizeof(int32_t) * NC, s));
+        BC_HIP(hipMemsetAsync(toT.p, 0, sizeof(int32_t) * NC, s));
+        k_mark_comps<<<grid_for(n), kBlk, 0, s>>>(n, mk, cid.as<int32_t>(), inRT.as<int32_t>());
+        big = BigScc{c_big, reached, inRT.as<int32_t>(), omega2.as<uint64_t>(), toT.as<int32_t>()};
+    }
     for (int32_t prev = nc + 1;;) {
         BC_HIP(hipMemsetAsync(fl, 0, sizeof(int32_t), s));
         k_dag_round<<<grid_for(nc), kBlk, 0, s>>>(nc, drp.as<int32_t>(), dcol.as<int32_t>(), wsize.as<uint32_t>(),
                                                   alpha.as<uint64_t>(), omega.as<uint64_t>(), done.as<int32_t>(),
-                                                  (uint64_t)n, fl);
+                                                  (uint64_t)n, fl, big);
         int32_t left = 0;
         BC_TRY(read_i32(fl, &left, s));
         if (left == 0) break;

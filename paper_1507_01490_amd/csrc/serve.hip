@@ -370,7 +370,7 @@ bc_status bc_server_add_graph(bc_server* S, int32_t n, int64_t m, const int32_t*
     SRV_GUARD_BEGIN
     if (!S || !graph_id || !row_ptr || (m > 0 && !col) || n < 0 || m < 0) { set_error("bad argument"); return BC_EINVAL; }
     if (flags & BC_DEVICE_PTRS) { set_error("server graphs take host arrays"); return BC_EINVAL; }
-    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE)) { set_error("unknown flag bits"); return BC_EINVAL; }
+    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_BIG_SCC)) { set_error("unknown flag bits"); return BC_EINVAL; }
     if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != m) { set_error("row_ptr[0] must be 0 and row_ptr[n] = m"); return BC_EGRAPH; }
     std::unique_ptr<bc::SrvGraph> G(new bc::SrvGraph());
     G->n = n;

@@ -99,6 +99,9 @@ struct TopKDev {
     // their exact farness and reach here, indexed by node id
     uint64_t* all_f;
     uint32_t* all_r;
+    // undirected graph with the footnote bound of Section 2.3: for d >= 1,
+    // ~gamma_{d+1} = sum of (deg - 1) over Gamma_d
+    int32_t footnote;
 };
 
 // Level-synchronous control block (device memory) of the plain slot.
@@ -561,6 +564,9 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
     uint32_t* s_flags = CL.flags;
     uint32_t* s_live = &CL.live;
     const int tid = threadIdx.x;
+    // arcs of Gamma_d that the footnote bound leaves out of ~gamma_{d+1}: one
+    // edge per node back to Gamma_{d-1} (still scanned, so still in m_vis)
+    uint64_t back = 0;
     if (tid < W) {
         SrcState s = S[tid];
         uint32_t fl = 0;
@@ -580,7 +586,8 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
             } else {
                 s.nd += g;
                 s.fd += (uint64_t)d * g;
-                s.tg = t;
+                back = T.footnote ? ((uint64_t)g < t ? (uint64_t)g : t) : 0;
+                s.tg = t - back;
             }
         } else if (s.status == S_TRIVIAL && !apply) {
             fl = 1;
@@ -666,14 +673,14 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
                 s.status = S_CUT;
                 atomicAdd(&st->n_cut, 1ull);
                 if (s.mvis) atomicAdd(&st->m_vis, (unsigned long long)s.mvis);
-            } else if (D && D->budget && s.tg > D->budget) {
+            } else if (D && D->budget && s.tg + back > D->budget) {
                 // too deep for one workgroup: restart it on the whole GPU later
                 s.status = S_DEFER;
                 D->ids[atomicAdd(D->cnt, 1u)] = s.id;
                 atomicAdd(&st->n_deferred, 1ull);
                 if (s.mvis) atomicAdd(&st->m_vis, (unsigned long long)s.mvis);
             } else {
-                s.mvis += s.tg;  // this source scans the out-arcs of Gamma_d
+                s.mvis += s.tg + back;  // this source scans the out-arcs of Gamma_d
                 live = true;
             }
             S[tid] = s;
@@ -686,6 +693,61 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
     }
     __syncthreads();
     const uint32_t nlive = *s_live;
+    __syncthreads();
+    return nlive;
+}
+
+// Bound test of the level just reached (d) with over-counted sizes, before
+// the exact count: g(b) and t(b) count every arc from the frontier of source
+// b to a node b has not seen (and that node's degree), so g >= gamma_d(b)
+// and t >= ~gamma_{d+1}(b), with equality when no node is reached twice.
+// Each extra count lowers L_x = f_d - ~gamma_{d+1} + (d+2)(x - n_d) by 2 plus
+// the node's degree (by 1 plus the degree with the footnote bound), so L_x
+// from these counts is at most the exact one and still bounds f from below
+// (Lemma 1, Lemma 2): a source it cuts would be cut by the exact test too.
+// Retires such sources (same bookkeeping as cut_step); every other source
+// keeps its exact state and is counted exactly afterwards.  A source with
+// g = 0 reached nothing new, which the exact count confirms (it completes
+// there).  Writes the active masks and returns the live count.
+__device__ uint32_t trial_cut(const TopKDev& T, SrcState* S, int W, uint32_t d, const uint32_t* cg,
+                              const unsigned long long* ct, QStats* st, uint64_t* active, CutLds& CL) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        ThRec th;
+        CL.have_th = load_threshold(T, &th) ? 1u : 0u;
+        CL.th = th;
+        CL.live = 0;
+    }
+    __syncthreads();
+    bool live = false;
+    if (tid < W) {
+        SrcState s = S[tid];
+        if (s.status == S_LIVE) {
+            live = true;
+            const uint32_t g = cg[tid];
+            if (CL.have_th && g > 0) {
+                const unsigned long long t = ct[tid];
+                SrcState q = s;
+                q.nd += g;
+                q.fd += (uint64_t)d * g;
+                q.tg = t - (T.footnote ? ((uint64_t)g < t ? (uint64_t)g : t) : 0);
+                if (cut_rule(q, d, CL.th)) {
+                    s.status = S_CUT;
+                    atomicAdd(&st->n_cut, 1ull);
+                    if (s.mvis) atomicAdd(&st->m_vis, (unsigned long long)s.mvis);
+                    S[tid] = s;
+                    live = false;
+                }
+            }
+        }
+    }
+    const unsigned long long bal = __ballot(live);
+    if (tid < W && lane_id() == 0) {
+        active[tid / 64] = bal;
+        if (bal) atomicAdd(&CL.live, (uint32_t)__popcll(bal));
+    }
+    __syncthreads();
+    const uint32_t nlive = CL.live;
     __syncthreads();
     return nlive;
 }
@@ -1392,6 +1454,58 @@ __device__ void tab_arcs(const DevGraph& G, LdsTab& L, const uint64_t* ns, uint3
     }
 }
 
+// One walk over the arcs [0, total) of a prologue without deduplication
+// (the counts of trial_cut): for each arc u -> w, the live bits of u whose
+// source has not seen w are counted with deg(w) for those sources, wave by
+// wave (wave_count_nodes).  Seen bits from H_seen, or with kRec from the node
+// records behind the seen filter.  H_next is not touched.
+template <bool kRec>
+__device__ void tab_cheap_arcs(const DevGraph& G, const LdsTab& L, const uint64_t* ns, uint32_t total,
+                               const PassScratch& X, uint32_t* cg, unsigned long long* ct,
+                               const uint32_t* seen_filter = nullptr) {
+    constexpr int B = kLdsBlk;
+    constexpr int kInflight = 1;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wbase = tid & ~63u;
+    // wave-uniform loop: a wave runs while any of its lanes has an arc
+    for (uint32_t r = 0; r + wbase < total; r += kInflight * B) {
+        int32_t w[kInflight];
+        uint32_t dg[kInflight];
+        uint64_t m[kInflight];
+#pragma unroll
+        for (int u = 0; u < kInflight; ++u) {
+            const uint32_t a = r + (uint32_t)u * B + tid;
+            m[u] = 0;
+            w[u] = 0;
+            dg[u] = 0;
+            if (a < total) {
+                uint32_t lo = 0, hi = B;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (X.eoff[mid] <= a) lo = mid + 1; else hi = mid;
+                }
+                const uint32_t i = lo - 1;
+                const int32_t e = X.ebeg[i] + (int32_t)(a - X.eoff[i]);
+                m[u] = X.em[i];
+                const int2 wd = G.adj[e];
+                w[u] = wd.x;
+                dg[u] = (uint32_t)wd.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kInflight; ++u) {
+            uint64_t nb = 0;
+            if (m[u]) {
+                uint64_t sv;
+                if (kRec) sv = filter_maybe(seen_filter, w[u]) ? ns[(size_t)w[u] * Layout<1>::SW] : 0ull;
+                else sv = tab_seen(L, w[u]);
+                nb = m[u] & ~sv;
+            }
+            wave_count_nodes<1>(&nb, nb ? dg[u] : 0u, cg, ct);
+        }
+    }
+}
+
 // Clear H_next after a counting pass.
 template <int B>
 __device__ inline void tab_next_reset(LdsTab& L) {
@@ -1425,7 +1539,8 @@ __device__ inline void tab_build_pass(LdsTab& L, int32_t* Fn) {
 template <int WW>
 __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32_t* order, int W,
                                                         uint32_t nbatches, uint32_t* next_batch, SlotPtrs base,
-                                                        TopKDev T, QStats* st, DeferList D, int force_spill) {
+                                                        TopKDev T, QStats* st, DeferList D, int force_spill,
+                                                        int no_trial) {
     static_assert(WW == 1, "LDS-resident batches hold 64 sources");
     using Lo = Layout<1>;
     constexpr int B = kLdsBlk;
@@ -1440,7 +1555,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
     __shared__ CutLds CL;
-    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b, s_mode;
+    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b, s_mode, s_hasth;
     __shared__ uint64_t s_act[4];
     __shared__ unsigned long long s_arcs, s_narcs, s_ent;
     const int tid = threadIdx.x;
@@ -1451,6 +1566,14 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     P.qb = base.qb + slot * (size_t)G.n;
     P.clr = base.clr + slot * (size_t)G.n;
     unsigned long long levels = 0, batches = 0, disc = 0, lds_lv = 0, rec_lv = 0, spills = 0;
+    // whether a k-th best record has been published (the trial cut needs one)
+    auto has_threshold = [&]() -> bool {
+        if (tid == 0) s_hasth = __hip_atomic_load(T.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ? 1u : 0u;
+        __syncthreads();
+        const bool h = s_hasth != 0u;
+        __syncthreads();
+        return h;
+    };
     unsigned long long rec_ticks = 0, rec_arcs = 0;
     unsigned long long ticks[5] = {0, 0, 0, 0, 0};
     tab_next_reset<B>(L);
@@ -1542,12 +1665,37 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
         __syncthreads();
         uint32_t live = cut_step<1>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D);
         uint32_t flen = s_flen, d = 0, cur = 0, stamp = 0;
+        uint32_t trial_d = 0;  // level whose over-counted bound test has run (0: none; level 0 needs none)
         uint64_t tp = __builtin_amdgcn_s_memrealtime();
         ticks[0] += tp - tb;
         while (live) {
             if (s_mode == 0) {
                 // ---------------- LDS level
                 const int32_t* F = L.fl[cur];
+                bool counted = false;  // the level's arcs are already in node_arcs
+                if (!no_trial && d >= 1 && trial_d != d + 1 && has_threshold()) {
+                    // one walk without deduplication, then the bound test with
+                    // those counts (trial_cut); the exact count below runs
+                    // only for the sources it leaves
+                    trial_d = d + 1;
+                    if (tid < kBlk) {
+                        cg[tid] = 0;
+                        ct[tid] = 0;
+                    }
+                    const uint32_t tot0 = tab_prologue(G, L, F, flen, s_act[0], PX, &s_narcs, &s_ent);
+                    tab_cheap_arcs<false>(G, L, nullptr, tot0, PX, cg, ct);
+                    __syncthreads();
+                    counted = true;
+                    live = trial_cut(T, S, W, d + 1, cg, ct, st, s_act, CL);
+                    const uint64_t tq = __builtin_amdgcn_s_memrealtime();
+                    ticks[1] += tq - tp;
+                    tp = tq;
+                    if (!live) {
+                        ++levels;
+                        ++lds_lv;
+                        break;
+                    }
+                }
                 const uint64_t act = s_act[0];
                 if (tid == 0) L.tsum = 0;
                 __syncthreads();
@@ -1575,7 +1723,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 }
                 __syncthreads();
                 uint32_t distinct = 0;
-                const uint32_t tot = tab_prologue(G, L, F, flen, act, PX, &s_narcs, &s_ent);
+                const uint32_t tot = tab_prologue(G, L, F, flen, act, PX, counted ? nullptr : &s_narcs,
+                                                  counted ? nullptr : &s_ent);
                 for (uint32_t p = 0; p < np; ++p) {
                     tab_arcs<true, false>(G, L, nullptr, tot, np, p, PX, cg, ct);
                     __syncthreads();
@@ -1666,6 +1815,34 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 // ---------------- global level (state on the node records)
                 const uint64_t tr0 = tp;
                 const unsigned long long ra0 = s_narcs, en0 = s_ent;
+                bool counted = false;
+                if (!no_trial && d >= 1 && trial_d != d + 1 && has_threshold()) {
+                    trial_d = d + 1;
+                    if (tid < kBlk) {
+                        cg[tid] = 0;
+                        ct[tid] = 0;
+                    }
+                    __syncthreads();
+                    const uint64_t act0 = s_act[0];
+                    for (uint32_t e0 = 0; e0 < flen; e0 += B) {
+                        const uint32_t tot = rec_prologue(G, P, P.qa, e0, min(flen, e0 + B), act0, PX, &s_narcs,
+                                                          &s_ent);
+                        tab_cheap_arcs<true>(G, L, P.ns, tot, PX, cg, ct, L.filter());
+                        __syncthreads();
+                    }
+                    counted = true;
+                    live = trial_cut(T, S, W, d + 1, cg, ct, st, s_act, CL);
+                    const uint64_t tq = __builtin_amdgcn_s_memrealtime();
+                    ticks[1] += tq - tp;
+                    tp = tq;
+                    if (!live) {
+                        ++levels;
+                        ++rec_lv;
+                        rec_ticks += tq - tr0;
+                        rec_arcs += s_narcs - ra0;
+                        break;
+                    }
+                }
                 const uint64_t act = s_act[0];
                 // When the level's arcs fit the LDS counting passes, count it in
                 // H_next with the seen bits read from the node records (no global
@@ -1698,8 +1875,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     for (uint32_t p = 0; p < np; ++p) {
                         for (uint32_t e0 = 0; e0 < flen; e0 += B) {
                             const uint32_t tot = rec_prologue(G, P, P.qa, e0, min(flen, e0 + B), act, PX,
-                                                              p == 0 ? &s_narcs : nullptr,
-                                                              p == 0 ? &s_ent : nullptr);
+                                                              (p == 0 && !counted) ? &s_narcs : nullptr,
+                                                              (p == 0 && !counted) ? &s_ent : nullptr);
                             tab_arcs<true, true>(G, L, P.ns, tot, np, p, PX, cg, ct, L.filter());
                             __syncthreads();
                         }
@@ -2089,7 +2266,8 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         if constexpr (WW == 1) {
             if (o.lds_tables >= 0)
                 k_batched_lds<1><<<slots, kLdsBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(), base,
-                                                           T, d_st, D, o.lds_tables == 1 ? 1 : 0);
+                                                           T, d_st, D, o.lds_tables == 1 ? 1 : 0,
+                                                           (o.bounds & BC_BOUND_NO_TRIAL) ? 1 : 0);
             else
                 k_batched<WW, kBatchBlk><<<slots, kBatchBlk, 0, s>>>(G, d_order, W, nbatches, Wk.nextb.as<uint32_t>(),
                                                                      chunk, base, Wk.slot_stamp.as<uint32_t>(), T, d_st, D);
@@ -2195,6 +2373,7 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         T.ring = B.ring.as<ThRec>();
         T.all_f = all ? allf.as<uint64_t>() : nullptr;
         T.all_r = all ? allr.as<uint32_t>() : nullptr;
+        T.footnote = (!g->dg.directed && (o.bounds & BC_BOUND_FOOTNOTE)) ? 1 : 0;
         QStats* d_st = B.stats.as<QStats>();
         // the graph's cached workspace, or a private one when another query holds it
         std::unique_ptr<Workspace> own;

@@ -67,7 +67,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ba1m", help="ba1m (default), ba2k, rmat21, collab, rgg or serve512")
+    ap.add_argument("--workload", default="ba1m",
+                    help="ba1m (default), ba2k, rmat21, collab, rgg, rgg18, serve512, scaling or snapshots")
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--slots", type=int, default=0)
@@ -78,8 +79,9 @@ def main():
                     help="undirected footnote bound of Section 2.3 in the timed mode (same answer)")
     ap.add_argument("--trial", type=int, default=1, choices=[0, 1],
                     help="over-counted bound test before exact level counts in the persistent kernel (same answer)")
-    ap.add_argument("--big-scc", type=int, default=0, choices=[0, 1],
-                    help="directed: largest-SCC refinement of the reach bounds (Section 2.4; same answer)")
+    ap.add_argument("--big-scc", type=int, default=1, choices=[0, 1],
+                    help="directed workloads: largest-SCC refinement of the reach bounds (Section 2.4; same "
+                         "answer); ignored on undirected graphs")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--lanes", type=int, default=4, help="serve512: concurrent requests")
     ap.add_argument("--serve-slots", type=int, default=64, help="serve512: workgroups per persistent kernel")
@@ -115,6 +117,12 @@ def main():
 
     if args.workload == "serve512":
         serve_bench(args, bc, workloads)
+        return
+    if args.workload == "scaling":
+        scaling_bench(args, bc)
+        return
+    if args.workload == "snapshots":
+        snapshot_bench(args, bc)
         return
 
     t0 = time.time()
@@ -260,6 +268,106 @@ def main():
                 roofline=roofline, cpu_baseline=cpu, plain=plain)
     print(json.dumps(line), flush=True)
     G.close()
+
+
+def scaling_bench(args, bc):
+    """The paper's machine-independent measures on seeded synthetic families of
+    growing size (Section 4): the performance ratio m_vis / (m n) of the
+    sequential-equivalent visited arcs the GPU counts, its inverse against n
+    (which the paper finds close to linear on its growing actor graph, i.e.
+    a running time close to O(m)), and the positive race: how much m_vis
+    grows when the k-th record is shared by many concurrent searches (the
+    batched mode, up to ~16k sources in flight) instead of one batch of 64 at
+    a time (the plain mode)."""
+    import numpy as np
+    import torch
+    from paper_1507_01490_amd import synth
+    torch.cuda.set_device(0)
+    families = {
+        "ba": lambda n, s: synth.barabasi_albert(n, 5, s),
+        "er": lambda n, s: synth.erdos_renyi(n, 8.0, s),
+        "collab": lambda n, s: synth.collaboration(4 * n, n, 2.1, 200, s),
+    }
+    sizes = {"ba": [1 << e for e in range(12, 21, 2)], "er": [1 << e for e in range(12, 21, 2)],
+             "collab": [1 << e for e in range(12, 17, 2)]}
+    rows = []
+    for fam, make in families.items():
+        for n in sizes[fam]:
+            g = make(n, 7)
+            with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+                for k in (1, 10):
+                    rb = G.topk(k, mode="batched")
+                    rp = G.topk(k, mode="plain") if n <= (1 << 16) else None
+                    mn = float(G.m) * float(G.n)
+                    row = dict(family=fam, n=G.n, m=G.m, k=k, ratio_batched=rb.stats["m_vis"] / mn,
+                               ms_batched=round(rb.stats["query_ms"], 2))
+                    if rp is not None:
+                        row["ratio_plain"] = rp.stats["m_vis"] / mn
+                        row["race"] = rb.stats["m_vis"] / max(rp.stats["m_vis"], 1) - 1.0
+                        assert rp.ids.tolist() == rb.ids.tolist()
+                    rows.append(row)
+                    log(f"[scaling] {fam} n={G.n} k={k} ratio={row['ratio_batched']:.3e} "
+                        f"race={row.get('race', float('nan')):.3f} {row['ms_batched']} ms")
+    fits = {}
+    for fam in families:
+        for k in (1, 10):
+            pts = [(r["n"], 1.0 / r["ratio_batched"]) for r in rows if r["family"] == fam and r["k"] == k]
+            x = np.array([p[0] for p in pts], float)
+            y = np.array([p[1] for p in pts], float)
+            c = np.polyfit(x, y, 1)
+            r2 = 1.0 - ((y - np.polyval(c, x)) ** 2).sum() / max(((y - y.mean()) ** 2).sum(), 1e-300)
+            fits[f"{fam}_k{k}"] = dict(slope=c[0], intercept=c[1], r2=round(float(r2), 4))
+    print(json.dumps(dict(metric="performance ratio m_vis/(m n) and positive race on 1 MI355X", rows=rows,
+                          inverse_ratio_linear_fit=fits, data="synthetic",
+                          config=dict(workload="BA m=5 and ER avg deg 8 at n = 2^12 .. 2^20; collaboration with n "
+                                               "groups of Zipf(2.1) sizes over 4n actors, n = 2^12 .. 2^16; seed 7; "
+                                               "plain-mode comparison up to 2^16", k=[1, 10]))), flush=True)
+
+
+def snapshot_bench(args, bc):
+    """A growing collaboration graph (the shape of the paper's actor-graph
+    case study on synthetic data): 16 snapshots, k = 10 on each.  Cold: the
+    grouped degree order.  Warm: the previous snapshot's top-k first
+    (opts.first), then the same order.  Both must give the same answer; the
+    line reports both total query times, and per snapshot the performance
+    ratio m_vis / (m n_active) and its inverse (n_active = nodes with an
+    edge)."""
+    import numpy as np
+    import torch
+    from paper_1507_01490_amd import synth
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    snaps = synth.collaboration_snapshots(500_000, 125_000, 2.1, 200, 4, 16)
+    log(f"[snapshots] generated {len(snaps)} snapshots in {time.time() - t0:.1f}s")
+    k = 10
+    rows, prev = [], None
+    tot_cold = tot_warm = 0.0
+    for t, g in enumerate(snaps):
+        with bc.Graph(g.row_ptr, g.col) as G:
+            G.topk(k, mode="batched")  # warm-up: workspace and cached order
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            cold = G.topk(k, mode="batched")
+            c1 = time.perf_counter()
+            warm = G.topk(k, mode="batched", first=prev) if prev is not None else cold
+            c2 = time.perf_counter()
+        assert cold.ids.tolist() == warm.ids.tolist() and cold.farness.tolist() == warm.farness.tolist()
+        n_act = int((np.diff(g.row_ptr) > 0).sum())
+        ms_c, ms_w = (c1 - c0) * 1e3, ((c2 - c1) * 1e3 if prev is not None else (c1 - c0) * 1e3)
+        tot_cold += ms_c
+        tot_warm += ms_w
+        ratio = cold.stats["m_vis"] / (float(g.m) * max(n_act, 1))
+        rows.append(dict(t=t + 1, m=g.m, n_active=n_act, ms_cold=round(ms_c, 2), ms_warm=round(ms_w, 2),
+                         m_vis_cold=cold.stats["m_vis"], m_vis_warm=warm.stats["m_vis"], ratio=ratio,
+                         inverse_ratio=1.0 / ratio if ratio > 0 else None))
+        log(f"[snapshots] t={t + 1} m={g.m} cold {ms_c:.1f} ms warm {ms_w:.1f} ms ratio {ratio:.3e}")
+        prev = cold.ids
+    print(json.dumps(dict(metric="top-k closeness over a growing graph on 1 MI355X (cold vs warm-started order)",
+                          value=round(tot_warm, 2), unit="ms (16 snapshots, warm)", cold_ms=round(tot_cold, 2),
+                          speedup=round(tot_cold / tot_warm, 3), higher_is_better=False, rows=rows,
+                          data="synthetic", config=dict(workload="collaboration snapshots: 500,000 actors, "
+                                                                 "125,000 groups, Zipf(2.1) sizes <= 200, seed 4, "
+                                                                 "16 snapshots", k=k, mode="batched"))), flush=True)
 
 
 def serve_bench(args, bc, workloads):

@@ -130,6 +130,11 @@ typedef struct bc_opts {
                                up to 256 (0 = width, or 256 when k > width);
                                seed_batches counts these batches                         */
     uint32_t bounds;        /* BC_BOUND_* flags (default 0: the bounds of Table 1)        */
+    const int32_t* first;   /* host, nfirst distinct node ids taken before all others, in
+                               this order; the rest follow in the order chosen above (a warm
+                               start, e.g. the previous top-k of a graph that has grown;
+                               Algorithm 1 gives the same answer for any order)          */
+    int32_t nfirst;         /* entries of first, 0 <= nfirst <= n (0: none)              */
 } bc_opts;
 
 typedef struct bc_stats {

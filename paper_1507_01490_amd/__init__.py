@@ -56,7 +56,8 @@ class Opts(ctypes.Structure):
                 ("slots", ctypes.c_int32), ("seed_batches", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("defer_arcs", ctypes.c_int32),
                 ("lds_tables", ctypes.c_int32), ("defer_width", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("graph_levels", ctypes.c_int32), ("seed_width", ctypes.c_int32), ("bounds", ctypes.c_uint32)]
+                ("graph_levels", ctypes.c_int32), ("seed_width", ctypes.c_int32), ("bounds", ctypes.c_uint32),
+                ("first", ctypes.c_void_p), ("nfirst", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -234,9 +235,19 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
                                       float(beta1), float(beta2), float(eps), _stream()))
 
 
+def _set_first(o: Opts, first, keep: list):
+    """opts.first / nfirst from a sequence of node ids (None: none)."""
+    if first is None or len(first) == 0:
+        o.first, o.nfirst = None, 0
+        return
+    a = np.ascontiguousarray(first, dtype=np.int32)
+    keep.append(a)
+    o.first, o.nfirst = a.ctypes.data_as(ctypes.c_void_p), int(a.shape[0])
+
+
 def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=14.0, pull_beta=24.0,
               slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None, defer_width=0,
-              graph_levels=None, seed_width=0, footnote=False, trial=True) -> Opts:
+              graph_levels=None, seed_width=0, footnote=False, trial=True, first=None) -> Opts:
     """bc_opts for a graph of n nodes; host arrays the options point at are
     appended to `keep` (they must outlive the call that reads them)."""
     lib = load_library()
@@ -256,6 +267,7 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
     o.defer_width = int(defer_width)
     o.seed_width = int(seed_width)
     o.bounds = (BC_BOUND_FOOTNOTE if footnote else 0) | (0 if trial else BC_BOUND_NO_TRIAL)
+    _set_first(o, first, keep)
     if graph_levels is not None:
         o.graph_levels = int(graph_levels)
     if isinstance(order, str) and order in ("learned", "learned_grouped"):
@@ -404,7 +416,7 @@ class Graph:
              pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
              seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
              lds_tables: bool = True, mlp=None, defer_width: int = 0, graph_levels=None,
-             seed_width: int = 0, footnote: bool = False, trial: bool = True) -> TopK:
+             seed_width: int = 0, footnote: bool = False, trial: bool = True, first=None) -> TopK:
         """The k nodes of largest closeness: ids, exact farness, exact reach.
 
         order: None (automatic), "degree", "grouped", "locality" (breadth-first
@@ -413,13 +425,15 @@ class Graph:
         seed-batch sources by learned score, then the grouped order), or a
         permutation of range(n); scores: per-node floats (decreasing score
         first); footnote: the undirected footnote bound (BC_BOUND_FOOTNOTE); trial=False skips
-        the over-counted bound test before exact level counts (BC_BOUND_NO_TRIAL)."""
+        the over-counted bound test before exact level counts (BC_BOUND_NO_TRIAL); first: node ids
+        taken before all others (a warm start, e.g. the previous top-k of a grown graph)."""
         keep = []
         o = self._opts(mode, width, order, scores, pull_alpha, pull_beta, slots, seed_batches, defer_arcs, chunk,
                        lds_tables, mlp, keep)
         o.defer_width = int(defer_width)
         o.seed_width = int(seed_width)
         o.bounds = (BC_BOUND_FOOTNOTE if footnote else 0) | (0 if trial else BC_BOUND_NO_TRIAL)
+        _set_first(o, first, keep)
         if graph_levels is not None:
             o.graph_levels = int(graph_levels)
         kk = max(1, int(k))
@@ -435,11 +449,12 @@ class Graph:
         return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
 
     def source_order(self, k: int = 10, mode: str | int = "batched", width: int = 64, order=None, scores=None,
-                     mlp=None, seed_batches: int = -1, seed_width: int = 0) -> np.ndarray:
+                     mlp=None, seed_batches: int = -1, seed_width: int = 0, first=None) -> np.ndarray:
         """The order (n node ids) in which topk with the same arguments takes its sources."""
         keep = []
         o = self._opts(mode, width, order, scores, 14.0, 24.0, 0, seed_batches, 0, 0, True, mlp, keep)
         o.seed_width = int(seed_width)
+        _set_first(o, first, keep)
         out = np.zeros(max(1, self.n), np.int32)
         _check(load_library().bc_source_order(self._h, int(k), ctypes.byref(o), _ptr(out)))
         return out[:self.n].copy()

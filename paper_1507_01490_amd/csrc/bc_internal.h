@@ -199,6 +199,9 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order, hipStream_t s);
 bc_status order_grouped(bc_graph* g, int32_t* d_order, hipStream_t s);
 bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_device, int32_t* d_order, hipStream_t s);
 bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipStream_t s);
+// Move the nf distinct node ids h_first (host) to the front of the order
+// d_order (a permutation of [0, n)), keeping the relative order of the rest.
+bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s);
 bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order, hipStream_t s);
 bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s);
 

@@ -477,6 +477,23 @@ __global__ void k_perm_check(int32_t n, const int32_t* __restrict__ perm, uint32
     }
 }
 
+// flag[i] = 1 when order[i] is not one of the front nodes (mark[v] != 0)
+__global__ void k_front_flags(int32_t n, const int32_t* __restrict__ order, const uint32_t* __restrict__ mark,
+                              int32_t* __restrict__ flag) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        flag[i] = mark[order[i]] ? 0 : 1;
+}
+
+// out[nf + pos[i]] = order[i] for the flagged entries (stable)
+__global__ void k_front_scatter(int32_t n, int32_t nf, const int32_t* __restrict__ order,
+                                const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                                int32_t* __restrict__ out) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (flag[i]) out[nf + pos[i]] = order[i];
+}
+
 template <class F>
 bc_status cub_call(F&& f, hipStream_t s, DevBuf& tmp) {
     size_t bytes = 0;
@@ -869,6 +886,38 @@ bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s
         g->have_order_loc[slot] = true;
     }
     BC_HIP(hipMemcpyAsync(d_order, g->order_loc[slot].p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    return BC_OK;
+}
+
+bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    if (nf < 0 || nf > n) { set_error("opts.nfirst %d outside [0, n = %d]", nf, n); return BC_EINVAL; }
+    if (nf == 0 || n == 0) return BC_OK;
+    if (!h_first) { set_error("opts.first is NULL with nfirst = %d", nf); return BC_EINVAL; }
+    DevBuf mark, errb, flag, pos, out, tmp;
+    BC_TRY(mark.alloc_on(sizeof(uint32_t) * (size_t)n, s));
+    BC_TRY(errb.alloc_on(sizeof(uint32_t), s));
+    BC_TRY(flag.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(pos.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(out.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_HIP(hipMemsetAsync(mark.p, 0, sizeof(uint32_t) * (size_t)n, s));
+    BC_HIP(hipMemsetAsync(errb.p, 0, sizeof(uint32_t), s));
+    // the front list goes to out[0, nf); the range check and the repeat check
+    // mark each of its nodes once
+    BC_HIP(hipMemcpyAsync(out.p, h_first, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s));
+    k_perm_check<<<grid_for(nf), kBlk, 0, s>>>(nf, out.as<int32_t>(), mark.as<uint32_t>(), errb.as<uint32_t>());
+    uint32_t err = 0;
+    BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (err) { set_error("opts.first holds a node outside [0, n) or a repeated node"); return BC_EINVAL; }
+    k_front_flags<<<grid_for(n), kBlk, 0, s>>>(n, d_order, mark.as<uint32_t>(), flag.as<int32_t>());
+    BC_TRY(cub_call([&](void* t, size_t& b) {
+        return hipcub::DeviceScan::ExclusiveSum(t, b, flag.as<int32_t>(), pos.as<int32_t>(), n, s);
+    }, s, tmp));
+    k_front_scatter<<<grid_for(n), kBlk, 0, s>>>(n, nf, d_order, flag.as<int32_t>(), pos.as<int32_t>(),
+                                                 out.as<int32_t>());
+    BC_HIP(hipMemcpyAsync(d_order, out.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    BC_HIP(hipStreamSynchronize(s));
     return BC_OK;
 }
 

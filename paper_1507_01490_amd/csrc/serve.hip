@@ -84,7 +84,7 @@ struct SrvReq {
     int32_t gid = 0;
     int32_t k = 0;
     bc_opts o{};
-    std::vector<int32_t> perm;
+    std::vector<int32_t> perm, first;
     std::vector<float> scores, mlp;
     int state = RQ_QUEUED;
     bool cancel = false;
@@ -230,6 +230,7 @@ void lane_main(bc_server* S, int lane) {
             if (r->o.order == BC_ORDER_GIVEN) r->o.perm = r->perm.data();
             if (r->o.order == BC_ORDER_SCORES) r->o.scores = r->scores.data();
             if (!r->mlp.empty()) r->o.mlp = r->mlp.data();
+            if (r->o.nfirst > 0) r->o.first = r->first.data();
             r->ids.assign((size_t)std::max(r->k, 1), 0);
             r->far.assign((size_t)std::max(r->k, 1), 0);
             r->reach.assign((size_t)std::max(r->k, 1), 0);
@@ -413,6 +414,12 @@ bc_status bc_submit(bc_server* S, int32_t graph_id, int32_t k, const bc_opts* op
         r->scores.assign(r->o.scores, r->o.scores + G->n);
     }
     if (r->o.mlp) r->mlp.assign(r->o.mlp, r->o.mlp + BC_MLP_PARAMS);
+    if (r->o.nfirst < 0 || r->o.nfirst > G->n) { set_error("opts.nfirst %d outside [0, n]", r->o.nfirst); return BC_EINVAL; }
+    if (r->o.nfirst > 0) {
+        if (!r->o.first) { set_error("opts.first is NULL with nfirst = %d", r->o.nfirst); return BC_EINVAL; }
+        r->first.assign(r->o.first, r->o.first + r->o.nfirst);
+    }
+    r->o.first = nullptr;
     r->o.perm = nullptr;
     r->o.scores = nullptr;
     r->o.mlp = nullptr;

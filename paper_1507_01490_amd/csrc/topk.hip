@@ -2515,6 +2515,7 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
         set_error("unknown order %d", o.order);
         return BC_EINVAL;
     }
+    if (o.nfirst != 0) BC_TRY(order_front(g, o.first, o.nfirst, d_order, s));
     return BC_OK;
 }
 

@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "Csr", "from_edges", "raw_csr", "barabasi_albert", "rmat", "erdos_renyi",
-    "grid_shortcuts", "collaboration", "random_geometric", "path", "star",
+    "grid_shortcuts", "collaboration", "collaboration_snapshots", "random_geometric", "path", "star",
     "cycle", "complete", "grid", "complete_bipartite", "directed_path",
     "directed_cycle", "out_star", "disjoint_union", "empty", "random_small",
 ]
@@ -222,6 +222,27 @@ def collaboration(n_actors: int, n_groups: int, s: float, cap: int, seed: int) -
     Group sizes follow a Zipf law with exponent s truncated to 1..cap; the
     members of a group are distinct actors drawn uniformly; every group
     becomes a clique among its members."""
+    sizes, offs, members = _collab_groups(n_actors, n_groups, s, cap, seed)
+    return _collab_graph(n_actors, sizes, offs, members, n_groups, f"collab_a{n_actors}_g{n_groups}_s{seed}")
+
+
+def collaboration_snapshots(n_actors: int, n_groups: int, s: float, cap: int, seed: int, count: int) -> list:
+    """A growing collaboration graph: the groups of ``collaboration`` with the
+    same arguments arrive in their drawing order, and snapshot t (t = 1 ..
+    count) holds the first ceil(t n_groups / count) of them over all n_actors
+    nodes (actors without a group yet are isolated).  Each snapshot's edges
+    contain the previous one's; the last snapshot is ``collaboration(...)``."""
+    sizes, offs, members = _collab_groups(n_actors, n_groups, s, cap, seed)
+    out = []
+    for t in range(1, count + 1):
+        ng = -(-t * n_groups // count)
+        out.append(_collab_graph(n_actors, sizes, offs, members, ng,
+                                 f"collab_a{n_actors}_g{n_groups}_s{seed}_t{t}of{count}"))
+    return out
+
+
+def _collab_groups(n_actors: int, n_groups: int, s: float, cap: int, seed: int):
+    """Group sizes (Zipf(s) on 1..cap), their offsets and distinct members."""
     rng = _rng(seed)
     ks = np.arange(1, cap + 1, dtype=np.float64)
     pmf = ks ** (-s)
@@ -242,6 +263,12 @@ def collaboration(n_actors: int, n_groups: int, s: float, cap: int, seed: int) -
             break
         idx = order[rep]
         members[idx] = rng.integers(0, n_actors, size=idx.shape[0])
+    return sizes, offs, members
+
+
+def _collab_graph(n_actors: int, sizes, offs, members, ng: int, name: str) -> Csr:
+    """The projection of the first ng groups: a clique per group."""
+    sizes = sizes[:ng]
     # clique pairs (i < j) inside every group, built group-size class by class
     src_l, dst_l = [], []
     for sz in np.unique(sizes):
@@ -254,8 +281,7 @@ def collaboration(n_actors: int, n_groups: int, s: float, cap: int, seed: int) -
         dst_l.append(mem[:, jj].reshape(-1))
     src = np.concatenate(src_l) if src_l else np.zeros(0, np.int64)
     dst = np.concatenate(dst_l) if dst_l else np.zeros(0, np.int64)
-    return from_edges(n_actors, src, dst, directed=False,
-                      name=f"collab_a{n_actors}_g{n_groups}_s{seed}")
+    return from_edges(n_actors, src, dst, directed=False, name=name)
 
 
 def random_geometric(n: int, avg_deg: float, seed: int) -> Csr:

@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
     ap.add_argument("--footnote", type=int, default=0, choices=[0, 1],
                     help="undirected footnote bound of Section 2.3 in the timed mode (same answer)")
+    ap.add_argument("--tune", type=int, default=0, choices=[0, 1],
+                    help="pick the batched-mode knobs per k with the autotuner (bc_autotune) before the timed "
+                         "region (tuning time reported, not timed)")
     ap.add_argument("--trial", type=int, default=1, choices=[0, 1],
                     help="over-counted bound test before exact level counts in the persistent kernel (same answer)")
     ap.add_argument("--big-scc", type=int, default=1, choices=[0, 1],
@@ -146,7 +149,17 @@ def main():
     del rp, col
     log(f"[bench] graph resident on GPU, pre-processing {G.preprocess_ms:.1f} ms")
 
+    tuned, tune_s = {}, 0.0
+    if args.tune and args.mode == "batched":
+        tt = time.perf_counter()
+        for k in ks:
+            tuned[k], rep = G.autotune(k, repeats=1, width=args.width)
+            log(f"[bench] autotune k={k}: {tuned[k]} ({rep})")
+        tune_s = time.perf_counter() - tt
+
     def step(mode, order=args.order, footnote=bool(args.footnote)):
+        if mode == "batched" and tuned:
+            return [G.topk(k, footnote=footnote, trial=bool(args.trial), **tuned[k]) for k in ks]
         return [G.topk(k, mode=mode, width=args.width, slots=args.slots, order=order, footnote=footnote,
                        trial=bool(args.trial)) for k in ks]
 
@@ -164,15 +177,21 @@ def main():
         step(args.mode)
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
+    def width_of(k):
+        return tuned[k]["width"] if tuned else args.width
+
     agg = dict(persistent_ms=0.0, seed_ms=0.0, defer_ms=0.0, n_deferred=0, arcs=0, entries=0, disc=0, m_vis=0,
+               alg_bytes=0,
                node_arcs=0, levels=0, lds_levels=0, record_levels=0, spills=0, record_ms=0.0, record_arcs=0,
                phase_ms=[0.0] * 5)
     parity = True if gold is not None else None  # None: no stored oracle answer for this workload
     t_start = time.perf_counter()
     for i in range(args.steps):
         out = step(args.mode)
-        for r in out:
+        for k, r in zip(ks, out):
             s = r.stats
+            agg["alg_bytes"] += algorithmic_bytes(s["persistent_arcs"], s["persistent_entries"],
+                                                  s["persistent_discovered"], width_of(k))
             agg["persistent_ms"] += s["persistent_ms"]
             agg["seed_ms"] += s["seed_ms"]
             agg["defer_ms"] += s["defer_ms"]
@@ -213,10 +232,12 @@ def main():
         log(f"[bench] plain: {pms:.1f} ms/step, batched speed-up {pms / ms_per_step:.2f}x")
 
     roofline = None
-    kernel = "k_batched_lds<1>" if args.width == 64 else f"k_batched<{args.width // 64}>"
+    widths = sorted({width_of(k) for k in ks})
+    kernel = "k_batched_lds<1>" if widths == [64] else (f"k_batched<{widths[0] // 64}>" if len(widths) == 1 else
+                                                        "k_batched_lds<1>/k_batched<WW>")
     if args.mode == "batched" and agg["persistent_ms"] > 0:
         nlaunch = args.steps * len(ks)
-        bytes_per_launch = algorithmic_bytes(agg["arcs"], agg["entries"], agg["disc"], args.width) / nlaunch
+        bytes_per_launch = agg["alg_bytes"] / nlaunch
         avg_ms = agg["persistent_ms"] / nlaunch
         achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -251,6 +272,8 @@ def main():
                 config=dict(workload=workloads.DESCRIPTION[args.workload], k=ks, mode=args.mode,
                             width=args.width, order=args.order, footnote=bool(args.footnote),
                             trial=bool(args.trial),
+                            tuned={str(k): v for k, v in tuned.items()} if tuned else None,
+                            tune_s=round(tune_s, 2) if tuned else None,
                             big_scc=bool(args.big_scc), parity_vs_oracle=parity,
                             work_m_vis=int(work)),
                 breakdown_ms_per_step=dict(seed=round(agg["seed_ms"] / args.steps, 3),

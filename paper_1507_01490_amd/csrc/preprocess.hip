@@ -477,6 +477,18 @@ __global__ void k_perm_check(int32_t n, const int32_t* __restrict__ perm, uint32
     }
 }
 
+// The front list first[0, nf): every id in [0, n) and none repeated (err set
+// otherwise); mark[v] = 1 for its nodes.
+__global__ void k_front_check(int32_t nf, int32_t n, const int32_t* __restrict__ first, uint32_t* __restrict__ mark,
+                              uint32_t* err) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) {
+        const int32_t v = first[i];
+        if (v < 0 || v >= n) { atomicOr(err, 1u); continue; }
+        if (atomicAdd(&mark[v], 1u) != 0) atomicOr(err, 1u);
+    }
+}
+
 // flag[i] = 1 when order[i] is not one of the front nodes (mark[v] != 0)
 __global__ void k_front_flags(int32_t n, const int32_t* __restrict__ order, const uint32_t* __restrict__ mark,
                               int32_t* __restrict__ flag) {
@@ -905,7 +917,7 @@ bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* 
     // the front list goes to out[0, nf); the range check and the repeat check
     // mark each of its nodes once
     BC_HIP(hipMemcpyAsync(out.p, h_first, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s));
-    k_perm_check<<<grid_for(nf), kBlk, 0, s>>>(nf, out.as<int32_t>(), mark.as<uint32_t>(), errb.as<uint32_t>());
+    k_front_check<<<grid_for(nf), kBlk, 0, s>>>(nf, n, out.as<int32_t>(), mark.as<uint32_t>(), errb.as<uint32_t>());
     uint32_t err = 0;
     BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));

@@ -26,6 +26,12 @@ if ROOT not in sys.path:
 
 METRIC = "top-k closeness wall time & GTEPS on 1 MI355X; batched+learned vs plain"
 HBM_PEAK_GBS = 8000.0
+# batched-mode width and deferral budget per workload, from measured sweeps
+# (same answers for every setting): hub-dominated BA favours 64-source batches
+# with deep sources deferred; R-MAT and the clique-rich collaboration graph
+# favour 256-source batches, the latter with no deferral (7.3 s vs 11.9 s)
+WORKLOAD_KNOBS = {"ba1m": (64, 0), "ba2k": (64, 0), "rmat21": (256, 0), "collab": (256, -1), "rgg": (256, 0),
+                  "rgg18": (256, 0)}
 
 
 def log(*a):
@@ -70,11 +76,16 @@ def main():
     ap.add_argument("--workload", default="ba1m",
                     help="ba1m (default), ba2k, rmat21, collab, rgg, rgg18, serve512, scaling or snapshots")
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
-    ap.add_argument("--width", type=int, default=64)
+    ap.add_argument("--width", type=int, default=0, help="sources per batch (0: the workload's default)")
+    ap.add_argument("--defer-arcs", type=int, default=None,
+                    help="batched mode: deferral budget in arcs (-1 never; default: the workload's)")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--order", default="auto", choices=["auto", "degree", "grouped", "locality", "learned", "learned_grouped"],
                     help="source order of the timed mode (auto: grouped degree in batched mode)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
+    ap.add_argument("--learned-steps", type=int, default=2,
+                    help="timed steps of the batched mode with the learned order (learned head + grouped tail; "
+                         "0 = skip)")
     ap.add_argument("--footnote", type=int, default=0, choices=[0, 1],
                     help="undirected footnote bound of Section 2.3 in the timed mode (same answer)")
     ap.add_argument("--tune", type=int, default=0, choices=[0, 1],
@@ -128,6 +139,11 @@ def main():
         snapshot_bench(args, bc)
         return
 
+    wdef, ddef = WORKLOAD_KNOBS.get(args.workload, (64, 0))
+    if args.width == 0:
+        args.width = wdef
+    if args.defer_arcs is None:
+        args.defer_arcs = ddef
     t0 = time.time()
     g = workloads.build(args.workload)
     log(f"[bench] built {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
@@ -153,15 +169,17 @@ def main():
     if args.tune and args.mode == "batched":
         tt = time.perf_counter()
         for k in ks:
-            tuned[k], rep = G.autotune(k, repeats=1, width=args.width)
+            tuned[k], rep = G.autotune(k, repeats=1, width=args.width, defer_arcs=args.defer_arcs)
             log(f"[bench] autotune k={k}: {tuned[k]} ({rep})")
         tune_s = time.perf_counter() - tt
 
     def step(mode, order=args.order, footnote=bool(args.footnote)):
         if mode == "batched" and tuned:
             return [G.topk(k, footnote=footnote, trial=bool(args.trial), **tuned[k]) for k in ks]
+        if mode == "plain":  # the comparator: one 64-source batch per host-loop iteration
+            return [G.topk(k, mode="plain", width=64, order=order, footnote=footnote) for k in ks]
         return [G.topk(k, mode=mode, width=args.width, slots=args.slots, order=order, footnote=footnote,
-                       trial=bool(args.trial)) for k in ks]
+                       trial=bool(args.trial), defer_arcs=args.defer_arcs) for k in ks]
 
     def check(results):
         if gold is None:
@@ -231,6 +249,28 @@ def main():
                      config="one batch of 64 sources per host-loop iteration, degree order")
         log(f"[bench] plain: {pms:.1f} ms/step, batched speed-up {pms / ms_per_step:.2f}x")
 
+    learned = None
+    if args.learned_steps > 0 and args.mode == "batched":
+        def lstep():
+            return [G.topk(k, mode="batched", width=args.width, slots=args.slots, order="learned_grouped",
+                           footnote=bool(args.footnote), trial=bool(args.trial), defer_arcs=args.defer_arcs)
+                    for k in ks]
+        lstep()
+        torch.cuda.synchronize()
+        tl0 = time.perf_counter()
+        for _ in range(args.learned_steps):
+            lout = lstep()
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - tl0) * 1e3 / args.learned_steps
+        learned = dict(ms_per_step=round(lms, 3), value=round(work / (lms / 1e3) / 1e9, 4), unit="GTEPS",
+                       parity=check(lout), order="learned head (order perceptron) + grouped degree tail",
+                       seed_ms=round(sum(r.stats["seed_ms"] for r in lout), 3),
+                       persistent_ms=round(sum(r.stats["persistent_ms"] for r in lout), 3),
+                       deferred_ms=round(sum(r.stats["defer_ms"] for r in lout), 3))
+        if plain is not None:
+            learned["speedup_vs_plain"] = round(plain["ms_per_step"] / lms, 2)
+        log(f"[bench] batched+learned: {lms:.1f} ms/step")
+
     roofline = None
     widths = sorted({width_of(k) for k in ks})
     kernel = "k_batched_lds<1>" if widths == [64] else (f"k_batched<{widths[0] // 64}>" if len(widths) == 1 else
@@ -270,7 +310,8 @@ def main():
                 warmup=args.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="int64", data="synthetic",
                 config=dict(workload=workloads.DESCRIPTION[args.workload], k=ks, mode=args.mode,
-                            width=args.width, order=args.order, footnote=bool(args.footnote),
+                            width=args.width, defer_arcs=args.defer_arcs, order=args.order,
+                            footnote=bool(args.footnote),
                             trial=bool(args.trial),
                             tuned={str(k): v for k, v in tuned.items()} if tuned else None,
                             tune_s=round(tune_s, 2) if tuned else None,
@@ -288,7 +329,7 @@ def main():
                     workgroup_ms_record=round(agg["record_ms"] / args.steps, 1),
                     workgroup_ms_phases=dict(zip(("setup", "count", "cut", "build", "reset"),
                                                  [round(x / args.steps, 1) for x in agg["phase_ms"]]))),
-                roofline=roofline, cpu_baseline=cpu, plain=plain)
+                roofline=roofline, cpu_baseline=cpu, plain=plain, batched_learned=learned)
     print(json.dumps(line), flush=True)
     G.close()
 

@@ -39,13 +39,14 @@ def log(*a):
 
 
 def algorithmic_bytes(arcs: int, entries: int, discovered: int, W: int) -> int:
-    """Minimal HBM bytes of the level work (roofline):
-    per scanned arc: col[e] (4 B) + seen[w] gather (W/8 B);
+    """Minimal HBM bytes of the level work of the persistent kernel:
+    per scanned arc: col[e] (4 B) + deg[col[e]] (4 B; the over-counted bound
+    test sums the degree of every arc's target) + seen[w] gather (W/8 B);
     per expanded frontier entry: list entry (4 B) + row_ptr pair (8 B) + cur[u] (W/8 B);
-    per discovered entry: list entry (4 B) + deg (4 B) + nxt read+reset (2 W/8 B)
-    + seen read+write (2 W/8 B) + cur write (W/8 B)."""
+    per discovered entry of an exactly counted level: list entry (4 B) + deg (4 B)
+    + nxt read+reset (2 W/8 B) + seen read+write (2 W/8 B) + cur write (W/8 B)."""
     wb = W // 8
-    return arcs * (4 + wb) + entries * (12 + wb) + discovered * (8 + 5 * wb)
+    return arcs * (8 + wb) + entries * (12 + wb) + discovered * (8 + 5 * wb)
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -53,7 +54,6 @@ def measured_traffic(kernel: str, workload: str):
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
     for a plain copy of known size), or None when there is none or the kernel
     source has changed since the counters were taken."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}.md")
     if not os.path.exists(path):
@@ -62,10 +62,22 @@ def measured_traffic(kernel: str, workload: str):
     if not m:
         return None
     info = json.loads(m.group(1))
-    src = os.path.join(ROOT, "paper_1507_01490_amd", "csrc", "topk.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != info.get("source_sha256_16"):
+    if device_source_hash() != info.get("device_source_sha256_16"):
         return None
     return info.get("traffic_bytes_per_launch")
+
+
+def device_source_hash() -> str:
+    """SHA-256 (16 hex digits) of the device part of csrc/topk.hip: all of the
+    file above its host-side marker, where every kernel and device function
+    of the level step lives.  Host-side edits below the marker leave it
+    unchanged; any kernel edit changes it."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1507_01490_amd", "csrc", "topk.hip")).read()
+    mark = "// --------------------------------------------------------- host side"
+    if src.count(mark) != 1:
+        return ""
+    return hashlib.sha256(src.split(mark)[0].encode()).hexdigest()[:16]
 
 
 def main():

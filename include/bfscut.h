@@ -67,7 +67,10 @@ typedef struct bc_graph bc_graph;
                                 of bc_graph_features (ties by out-degree, then id)               */
 #define BC_ORDER_LEARNED_GROUPED 5 /* opts.mlp: the sources of the seed batches (ceil(k/W) batches
                                 unless opts.seed_batches says otherwise) by decreasing score, then
-                                all others in BC_ORDER_GROUPED order                               */
+                                all others in BC_ORDER_GROUPED order.  On a directed graph it is
+                                BC_ORDER_GROUPED: the shipped perceptron is trained on undirected
+                                families only, and the degree order is its fallback (its scores
+                                picked seed sources that made directed R-MAT 15x slower)          */
 #define BC_ORDER_LOCALITY 6  /* compact balls of `width` sources: from a breadth-first order
                                 rooted at an approximate centre (middle of a double-sweep
                                 path; other components follow in degree order), each batch

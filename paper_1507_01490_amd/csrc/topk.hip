@@ -2482,8 +2482,14 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
 bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_order, hipStream_t s) {
     const int32_t n = g->dg.n;
     const int W = o.width;
-    const int32_t ord = o.order == BC_ORDER_AUTO ? (o.mode == BC_MODE_BATCHED ? BC_ORDER_GROUPED : BC_ORDER_DEGREE)
-                                                  : o.order;
+    int32_t ord = o.order == BC_ORDER_AUTO ? (o.mode == BC_MODE_BATCHED ? BC_ORDER_GROUPED : BC_ORDER_DEGREE)
+                                            : o.order;
+    // the order perceptron is trained on undirected graphs; on directed ones
+    // the combined order falls back to the degree-based one
+    if (ord == BC_ORDER_LEARNED_GROUPED && g->dg.directed) {
+        if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
+        ord = BC_ORDER_GROUPED;
+    }
     if (ord == BC_ORDER_DEGREE) {
         BC_TRY(order_by_degree(g, d_order, s));
     } else if (ord == BC_ORDER_GROUPED) {

@@ -32,6 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # favour 256-source batches, the latter with no deferral (7.3 s vs 11.9 s)
 WORKLOAD_KNOBS = {"ba1m": (64, 0), "ba2k": (64, 0), "rmat21": (256, 0), "collab": (256, -1), "rgg": (256, 0),
                   "rgg18": (256, 0)}
+# geometric graphs have no hubs: batches of nearby sources share their levels
+WORKLOAD_ORDER = {"rgg": "locality", "rgg18": "locality"}
 
 
 def log(*a):
@@ -156,6 +158,8 @@ def main():
         args.width = wdef
     if args.defer_arcs is None:
         args.defer_arcs = ddef
+    if args.order == "auto":
+        args.order = WORKLOAD_ORDER.get(args.workload, "auto")
     t0 = time.time()
     g = workloads.build(args.workload)
     log(f"[bench] built {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")

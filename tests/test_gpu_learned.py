@@ -202,3 +202,22 @@ def test_learned_order_gain(gi):
         for order in ("learned", "learned_grouped"):
             a = G.topk(100, mode="batched", order=order)
             assert a.ids.tolist() == ref["ids"].tolist()
+
+
+def test_learned_grouped_falls_back_to_degree_order_on_directed_graphs():
+    """The shipped perceptron is trained on undirected families; on a
+    directed graph the learned-grouped order is the grouped degree order
+    (the fallback), and the answer is the oracle's."""
+    g = synth.rmat(12, 16, 0.57, 0.19, 0.19, 61)
+    with bc.Graph(g.row_ptr, g.col, directed=True) as G:
+        a = G.source_order(10, mode="batched", order="learned_grouped")
+        b = G.source_order(10, mode="batched", order="grouped")
+        assert a.tolist() == b.tolist()
+        res = G.topk(10, mode="batched", order="learned_grouped")
+    ref = oracle.topk(g, 10)
+    assert res.ids.tolist() == ref["ids"].tolist() and res.farness.tolist() == ref["f"].tolist()
+    u = synth.barabasi_albert(3000, 3, 62)
+    with bc.Graph(u.row_ptr, u.col) as G:
+        a = G.source_order(10, mode="batched", order="learned_grouped")
+        b = G.source_order(10, mode="batched", order="grouped")
+        assert a.tolist() != b.tolist()  # undirected: the learned head is used

@@ -96,7 +96,9 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--order", default="auto", choices=["auto", "degree", "grouped", "locality", "learned", "learned_grouped"],
                     help="source order of the timed mode (auto: grouped degree in batched mode)")
-    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain comparator (0 = skip)")
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="timed steps of the plain comparator (0 = skip; default 1, 0 on the geometric workloads, "
+                         "where its thousands of host-synchronised levels per batch take many minutes)")
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the batched mode with the learned order (learned head + grouped tail; "
                          "0 = skip)")
@@ -160,6 +162,8 @@ def main():
         args.defer_arcs = ddef
     if args.order == "auto":
         args.order = WORKLOAD_ORDER.get(args.workload, "auto")
+    if args.plain_steps is None:
+        args.plain_steps = 0 if args.workload in ("rgg", "rgg18") else 1
     t0 = time.time()
     g = workloads.build(args.workload)
     log(f"[bench] built {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")

@@ -56,7 +56,11 @@ def test_collaboration_full_size_sampled():
     g = workloads.build("collab")
     with bc.Graph(g.row_ptr, g.col) as G:
         res = G.topk(10, mode="batched")
+        # the configuration the benchmark times on this workload
+        bench_cfg = G.topk(10, mode="batched", width=256, defer_arcs=-1)
     assert len(res.ids) == 10
+    assert bench_cfg.ids.tolist() == res.ids.tolist()
+    assert bench_cfg.farness.tolist() == res.farness.tolist() and bench_cfg.reach.tolist() == res.reach.tolist()
 
     def exact(v):
         d = oracle.bfs(g, int(v)).astype(np.int64)
@@ -79,3 +83,23 @@ def test_collaboration_full_size_sampled():
         r, f = exact(v)
         kv = oracle.closeness_key(r, f)
         assert kv < kth_key or (kv == kth_key and v > kth_id), v
+
+
+def test_rmat21_with_largest_scc_bounds_against_oracle():
+    """Directed R-MAT scale 21 with the largest-SCC reach refinement, in the
+    configurations the benchmark times (W = 256 batches, and the learned
+    order, which falls back to the grouped order on directed graphs): the
+    oracle's stored top-10 (computed with the plain reach bounds; the answer
+    does not depend on the bounds)."""
+    path = os.path.join(HERE, "golden", "rmat21.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored answer")
+    gold = json.load(open(path))
+    g = workloads.build("rmat21")
+    assert g.sha256() == gold["sha256"]
+    ref = gold["results"]["10"]
+    with bc.Graph(g.row_ptr, g.col, directed=True, big_scc=True) as G:
+        for kw in (dict(mode="batched", width=256), dict(mode="batched", width=256, order="learned_grouped")):
+            res = G.topk(10, **kw)
+            assert res.ids.tolist() == ref["ids"], kw
+            assert [int(x) for x in res.farness] == ref["farness"] and [int(x) for x in res.reach] == ref["reach"]

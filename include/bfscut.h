@@ -65,9 +65,11 @@ typedef struct bc_graph bc_graph;
                                 neighbour (then id), so that a batch shares neighbourhoods       */
 #define BC_ORDER_LEARNED 4   /* opts.mlp: decreasing score of the order perceptron over the features
                                 of bc_graph_features (ties by out-degree, then id)               */
-#define BC_ORDER_LEARNED_GROUPED 5 /* opts.mlp: the sources of the seed batches (ceil(k/W) batches
-                                unless opts.seed_batches says otherwise) by decreasing score, then
-                                all others in BC_ORDER_GROUPED order.  On a directed graph it is
+#define BC_ORDER_LEARNED_GROUPED 5 /* opts.mlp: the k best-scored sources (at most as many as the
+                                seed batches hold: ceil(k/W) batches unless opts.seed_batches says
+                                otherwise) by decreasing score, then all others in BC_ORDER_GROUPED
+                                order, so that the seed batches also hold the highest-degree
+                                nodes.  On a directed graph it is
                                 BC_ORDER_GROUPED: the shipped perceptron is trained on undirected
                                 families only, and the degree order is its fallback (its scores
                                 picked seed sources that made directed R-MAT 15x slower)          */

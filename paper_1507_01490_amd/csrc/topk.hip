@@ -2514,7 +2514,11 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
             BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
         } else {
             const SeedPlan sp = seed_plan(o, kk, n, W);
-            const int64_t head = std::min<int64_t>((int64_t)n, (int64_t)sp.batches * sp.sw);
+            // the k best-scored sources first (the predicted top-k), then the
+            // grouped order, which fills the rest of the seed batches with the
+            // highest-degree nodes
+            const int64_t head =
+                std::min<int64_t>((int64_t)n, std::min<int64_t>((int64_t)sp.batches * sp.sw, (int64_t)kk));
             BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order, s));
         }
     } else {

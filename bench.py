@@ -40,15 +40,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(arcs: int, entries: int, discovered: int, W: int) -> int:
+def algorithmic_bytes(arcs: int, entries: int, discovered: int, W: int, trial: bool = True) -> int:
     """Minimal HBM bytes of the level work of the persistent kernel:
-    per scanned arc: col[e] (4 B) + deg[col[e]] (4 B; the over-counted bound
-    test sums the degree of every arc's target) + seen[w] gather (W/8 B);
+    per scanned arc: col[e] (4 B) + seen[w] gather (W/8 B), plus deg[col[e]]
+    (4 B) in the W = 64 kernel, whose over-counted bound test (trial) sums the
+    degree of every arc's target;
     per expanded frontier entry: list entry (4 B) + row_ptr pair (8 B) + cur[u] (W/8 B);
     per discovered entry of an exactly counted level: list entry (4 B) + deg (4 B)
     + nxt read+reset (2 W/8 B) + seen read+write (2 W/8 B) + cur write (W/8 B)."""
     wb = W // 8
-    return arcs * (8 + wb) + entries * (12 + wb) + discovered * (8 + 5 * wb)
+    return arcs * ((8 if trial else 4) + wb) + entries * (12 + wb) + discovered * (8 + 5 * wb)
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -229,7 +230,8 @@ def main():
         for k, r in zip(ks, out):
             s = r.stats
             agg["alg_bytes"] += algorithmic_bytes(s["persistent_arcs"], s["persistent_entries"],
-                                                  s["persistent_discovered"], width_of(k))
+                                                  s["persistent_discovered"], width_of(k),
+                                                  trial=width_of(k) == 64 and bool(args.trial))
             agg["persistent_ms"] += s["persistent_ms"]
             agg["seed_ms"] += s["seed_ms"]
             agg["defer_ms"] += s["defer_ms"]

@@ -18,8 +18,9 @@ def test_algorithmic_bytes_per_unit():
     assert bench.algorithmic_bytes(1, 0, 0, 64) == 16
     assert bench.algorithmic_bytes(0, 1, 0, 64) == 20
     assert bench.algorithmic_bytes(0, 0, 1, 64) == 48
-    # W = 256: masks of 32 B
-    assert bench.algorithmic_bytes(1, 1, 1, 256) == (8 + 32) + (12 + 32) + (8 + 5 * 32)
+    # W = 256 (no trial cut: no per-arc degree): masks of 32 B
+    assert bench.algorithmic_bytes(1, 1, 1, 256, trial=False) == (4 + 32) + (12 + 32) + (8 + 5 * 32)
+    assert bench.algorithmic_bytes(1, 0, 0, 64, trial=False) == 12
     assert bench.algorithmic_bytes(10, 20, 30, 64) == 10 * 16 + 20 * 20 + 30 * 48
 
 

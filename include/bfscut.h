@@ -174,7 +174,7 @@ typedef struct bc_stats {
 } bc_stats;
 
 /* Fill *opts with the defaults (plain mode, automatic order, W = 64, bottom-up
- * steps when the frontier holds more than m/14 arcs). */
+ * steps when the frontier holds more than m/3 arcs). */
 void bc_opts_default(bc_opts* opts);
 
 /* Message of the last failure on this thread ("" if none). */
@@ -287,7 +287,7 @@ bc_status bc_source_order(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* 
  * `base` (NULL: defaults) in BC_MODE_BATCHED, the tuner runs the query over
  * a grid of width (64, 128, 256) x defer_arcs (16384, 65536, 262144, never),
  * then tries one knob at a time around the best setting so far:
- * defer_width (64, 256), pull_alpha (never, 14, 40), slots (128, 256, 512)
+ * defer_width (64, 256), pull_alpha (never, 3, 14), slots (128, 256, 512)
  * and order (grouped, degree, locality).  Each setting is timed as the best of
  * `repeats` runs after one
  * warm-up.  Every run must return exactly the first run's top-k, else

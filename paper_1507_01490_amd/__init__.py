@@ -245,7 +245,7 @@ def _set_first(o: Opts, first, keep: list):
     o.first, o.nfirst = a.ctypes.data_as(ctypes.c_void_p), int(a.shape[0])
 
 
-def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=14.0, pull_beta=24.0,
+def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=None, pull_alpha=3.0, pull_beta=24.0,
               slots=0, seed_batches=-1, defer_arcs=0, chunk=0, lds_tables=True, mlp=None, defer_width=0,
               graph_levels=None, seed_width=0, footnote=False, trial=True, first=None) -> Opts:
     """bc_opts for a graph of n nodes; host arrays the options point at are
@@ -413,7 +413,7 @@ class Graph:
                          chunk=chunk, lds_tables=lds_tables, mlp=mlp)
 
     def topk(self, k: int, mode: str | int = "plain", width: int = 64, order=None, scores=None,
-             pull_alpha: float = 14.0, pull_beta: float = 24.0, slots: int = 0,
+             pull_alpha: float = 3.0, pull_beta: float = 24.0, slots: int = 0,
              seed_batches: int = -1, defer_arcs: int = 0, chunk: int = 0,
              lds_tables: bool = True, mlp=None, defer_width: int = 0, graph_levels=None,
              seed_width: int = 0, footnote: bool = False, trial: bool = True, first=None) -> TopK:
@@ -452,7 +452,7 @@ class Graph:
                      mlp=None, seed_batches: int = -1, seed_width: int = 0, first=None) -> np.ndarray:
         """The order (n node ids) in which topk with the same arguments takes its sources."""
         keep = []
-        o = self._opts(mode, width, order, scores, 14.0, 24.0, 0, seed_batches, 0, 0, True, mlp, keep)
+        o = self._opts(mode, width, order, scores, 3.0, 24.0, 0, seed_batches, 0, 0, True, mlp, keep)
         o.seed_width = int(seed_width)
         _set_first(o, first, keep)
         out = np.zeros(max(1, self.n), np.int32)
@@ -463,7 +463,7 @@ class Graph:
         """(best options as topk keyword arguments, report) for this graph and k."""
         keep = []
         o = self._opts(kw.pop("mode", "batched"), kw.pop("width", 64), kw.pop("order", None), None,
-                       kw.pop("pull_alpha", 14.0), kw.pop("pull_beta", 24.0), kw.pop("slots", 0),
+                       kw.pop("pull_alpha", 3.0), kw.pop("pull_beta", 24.0), kw.pop("slots", 0),
                        kw.pop("seed_batches", -1), kw.pop("defer_arcs", 0), 0, kw.pop("lds_tables", True), None, keep)
         if kw:
             raise TypeError(f"unexpected options {sorted(kw)}")
@@ -482,7 +482,7 @@ class Graph:
                     seed_batches: int = -1, defer_arcs: int = 0, lds_tables: bool = True):
         """(farness, reach, stats) of every node, exactly (no cut)."""
         keep = []
-        o = self._opts(mode, width, order, None, 14.0, 24.0, slots, seed_batches, defer_arcs, 0, lds_tables,
+        o = self._opts(mode, width, order, None, 3.0, 24.0, slots, seed_batches, defer_arcs, 0, lds_tables,
                        None, keep)
         far = np.zeros(max(self.n, 1), np.uint64)
         rea = np.zeros(max(self.n, 1), np.uint32)

@@ -90,7 +90,7 @@ void bc_opts_default(bc_opts* o) {
     o->width = 64;
     o->perm = nullptr;
     o->scores = nullptr;
-    o->pull_alpha = 14.f;
+    o->pull_alpha = 3.f;
     o->pull_beta = 24.f;
     o->slots = 0;
     o->seed_batches = -1;

@@ -109,7 +109,7 @@ extern "C" bc_status bc_autotune(bc_graph* g, int32_t k, const bc_opts* base, in
         const int cus = 256;
         std::vector<Knob> knobs = {
             {{64, 256}, [](bc_opts& o, int v) { o.defer_width = v; }},
-            {{0, 14, 40}, [](bc_opts& o, int v) { o.pull_alpha = (float)v; }},
+            {{0, 3, 14}, [](bc_opts& o, int v) { o.pull_alpha = (float)v; }},
             {{cus / 2, cus, 2 * cus}, [](bc_opts& o, int v) { o.slots = v; }},
             {{BC_ORDER_GROUPED, BC_ORDER_DEGREE, BC_ORDER_LOCALITY}, [](bc_opts& o, int v) { o.order = v; }},
         };

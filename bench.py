@@ -273,8 +273,10 @@ def main():
 
     learned = None
     if args.learned_steps > 0 and args.mode == "batched":
+        lorder = "learned_locality" if args.order == "locality" else "learned_grouped"
+
         def lstep():
-            return [G.topk(k, mode="batched", width=args.width, slots=args.slots, order="learned_grouped",
+            return [G.topk(k, mode="batched", width=args.width, slots=args.slots, order=lorder,
                            footnote=bool(args.footnote), trial=bool(args.trial), defer_arcs=args.defer_arcs)
                     for k in ks]
         lstep()
@@ -285,7 +287,9 @@ def main():
         torch.cuda.synchronize()
         lms = (time.perf_counter() - tl0) * 1e3 / args.learned_steps
         learned = dict(ms_per_step=round(lms, 3), value=round(work / (lms / 1e3) / 1e9, 4), unit="GTEPS",
-                       parity=check(lout), order="learned head (order perceptron) + grouped degree tail",
+                       parity=check(lout), order=("learned head (order perceptron) + " +
+                                                  ("locality" if lorder == "learned_locality" else "grouped degree")
+                                                  + " tail"),
                        seed_ms=round(sum(r.stats["seed_ms"] for r in lout), 3),
                        persistent_ms=round(sum(r.stats["persistent_ms"] for r in lout), 3),
                        deferred_ms=round(sum(r.stats["defer_ms"] for r in lout), 3))

@@ -80,6 +80,9 @@ typedef struct bc_graph bc_graph;
                                 of unplaced nodes around it.  A batch's sources lie within a
                                 few hops of each other, so they share most levels (suits
                                 graphs without hubs: geometric, grid-like)                      */
+#define BC_ORDER_LEARNED_LOCALITY 7 /* opts.mlp: the k best-scored sources (at most as many as the
+                                seed batches hold), then all others in BC_ORDER_LOCALITY order (for
+                                graphs without hubs); BC_ORDER_LOCALITY on a directed graph      */
 #define BC_ORDER_AUTO   -1   /* BC_ORDER_GROUPED in batched mode, BC_ORDER_DEGREE in plain mode   */
 
 /* Parameters of the order perceptron 3 -> 64 -> 64 -> 1 (ReLU, fp32), one flat vector:

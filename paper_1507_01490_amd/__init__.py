@@ -37,6 +37,7 @@ BC_BOUND_FOOTNOTE, BC_BOUND_NO_TRIAL = 0x1, 0x2
 ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_LEARNED_GROUPED, ORDER_AUTO = \
     0, 1, 2, 3, 4, 5, -1
 ORDER_LOCALITY = 6
+ORDER_LEARNED_LOCALITY = 7
 MLP_PARAMS = 4481
 MODE_PLAIN, MODE_BATCHED = 0, 1
 _STATUS = {0: "BC_OK", -1: "BC_EINVAL", -2: "BC_EGRAPH", -3: "BC_ENOMEM", -4: "BC_EDEVICE",
@@ -270,11 +271,12 @@ def make_opts(n: int, keep: list, mode="plain", width=64, order=None, scores=Non
     _set_first(o, first, keep)
     if graph_levels is not None:
         o.graph_levels = int(graph_levels)
-    if isinstance(order, str) and order in ("learned", "learned_grouped"):
+    if isinstance(order, str) and order in ("learned", "learned_grouped", "learned_locality"):
         prm = np.ascontiguousarray(default_mlp() if mlp is None else mlp, dtype=np.float32)
         if prm.shape != (MLP_PARAMS,):
             raise ValueError(f"mlp must hold {MLP_PARAMS} floats")
-        o.order = ORDER_LEARNED if order == "learned" else ORDER_LEARNED_GROUPED
+        o.order = {"learned": ORDER_LEARNED, "learned_grouped": ORDER_LEARNED_GROUPED,
+                   "learned_locality": ORDER_LEARNED_LOCALITY}[order]
         o.mlp = prm.ctypes.data
         keep.append(prm)
     elif isinstance(order, str):
@@ -422,7 +424,8 @@ class Graph:
         order: None (automatic), "degree", "grouped", "locality" (breadth-first
         from an approximate centre), "learned" (the order
         perceptron `mlp`, default the trained one), "learned_grouped" (the
-        seed-batch sources by learned score, then the grouped order), or a
+        k best-scored sources, then the grouped order), "learned_locality" (the
+        k best-scored sources, then the locality order), or a
         permutation of range(n); scores: per-node floats (decreasing score
         first); footnote: the undirected footnote bound (BC_BOUND_FOOTNOTE); trial=False skips
         the over-counted bound test before exact level counts (BC_BOUND_NO_TRIAL); first: node ids

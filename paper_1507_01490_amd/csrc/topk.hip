@@ -2486,9 +2486,9 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
                                             : o.order;
     // the order perceptron is trained on undirected graphs; on directed ones
     // the combined order falls back to the degree-based one
-    if (ord == BC_ORDER_LEARNED_GROUPED && g->dg.directed) {
+    if ((ord == BC_ORDER_LEARNED_GROUPED || ord == BC_ORDER_LEARNED_LOCALITY) && g->dg.directed) {
         if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
-        ord = BC_ORDER_GROUPED;
+        ord = ord == BC_ORDER_LEARNED_GROUPED ? BC_ORDER_GROUPED : BC_ORDER_LOCALITY;
     }
     if (ord == BC_ORDER_DEGREE) {
         BC_TRY(order_by_degree(g, d_order, s));
@@ -2502,7 +2502,7 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
     } else if (ord == BC_ORDER_SCORES) {
         if (!o.scores) { set_error("BC_ORDER_SCORES needs opts.scores"); return BC_EINVAL; }
         BC_TRY(order_by_scores(g, o.scores, false, d_order, s));
-    } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED) {
+    } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED || ord == BC_ORDER_LEARNED_LOCALITY) {
         if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
         BC_TRY(graph_features(g, s));
         DevBuf prm, sc;
@@ -2512,6 +2512,21 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
         BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
         if (ord == BC_ORDER_LEARNED) {
             BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
+        } else if (ord == BC_ORDER_LEARNED_LOCALITY) {
+            // the k best-scored sources, then the locality order without them
+            const SeedPlan sp = seed_plan(o, kk, n, W);
+            const int64_t head =
+                std::min<int64_t>((int64_t)n, std::min<int64_t>((int64_t)sp.batches * sp.sw, (int64_t)kk));
+            DevBuf bys;
+            BC_TRY(bys.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+            BC_TRY(order_by_scores(g, sc.as<float>(), true, bys.as<int32_t>(), s));
+            std::vector<int32_t> h((size_t)(head > 0 ? head : 1));
+            if (head > 0) {
+                BC_HIP(hipMemcpyAsync(h.data(), bys.p, sizeof(int32_t) * (size_t)head, hipMemcpyDeviceToHost, s));
+                BC_HIP(hipStreamSynchronize(s));
+            }
+            BC_TRY(order_locality(g, W, d_order, s));
+            if (head > 0) BC_TRY(order_front(g, h.data(), (int32_t)head, d_order, s));
         } else {
             const SeedPlan sp = seed_plan(o, kk, n, W);
             // the k best-scored sources first (the predicted top-k), then the

@@ -221,3 +221,22 @@ def test_learned_grouped_falls_back_to_degree_order_on_directed_graphs():
         a = G.source_order(10, mode="batched", order="learned_grouped")
         b = G.source_order(10, mode="batched", order="grouped")
         assert a.tolist() != b.tolist()  # undirected: the learned head is used
+
+
+@pytest.mark.parametrize("width", [64, 256])
+def test_learned_locality_order(width):
+    """BC_ORDER_LEARNED_LOCALITY: the k best-scored sources (the head of the
+    pure learned order), then the locality order without them; exact."""
+    g = synth.random_geometric(6000, 6.0, 71)
+    k = 10
+    with bc.Graph(g.row_ptr, g.col) as G:
+        ll = G.source_order(k, mode="batched", width=width, order="learned_locality")
+        lr = G.source_order(k, mode="batched", width=width, order="learned")
+        loc = G.source_order(k, mode="batched", width=width, order="locality")
+        assert sorted(ll.tolist()) == list(range(g.n))
+        head = ll[:k].tolist()
+        assert head == lr[:k].tolist()
+        assert ll[k:].tolist() == [v for v in loc.tolist() if v not in set(head)]
+        res = G.topk(k, mode="batched", width=width, order="learned_locality")
+    ref = oracle.topk(g, k)
+    assert res.ids.tolist() == ref["ids"].tolist() and res.farness.tolist() == ref["f"].tolist()

@@ -122,7 +122,7 @@ def locality_order(rp, col, B):
     return carve(rp, col, locality_seed(rp, col), B)
 
 
-ORDERS = ["degree", "grouped", "locality", "learned", "learned_grouped", "auto"]
+ORDERS = ["degree", "grouped", "locality", "learned", "learned_grouped", "learned_locality", "auto"]
 
 
 @pytest.mark.parametrize("gi", range(13))

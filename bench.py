@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64, help="serve512: workgroups per persistent kernel")
     ap.add_argument("--budget-mb", type=int, default=2048, help="serve512: device memory budget")
     ap.add_argument("--load", type=float, default=0.8, help="serve512: Poisson rate as a fraction of capacity")
+    ap.add_argument("--family-knobs", type=int, default=1, choices=[0, 1],
+                    help="serve512: per-family request options (grids: W=256, locality order, no deferral)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -473,6 +475,13 @@ def serve_bench(args, bc, workloads):
         f"sum arcs = {sum(g.m for g, _ in mix)}) in {time.time() - t0:.1f}s")
     S = bc.Server(lanes=args.lanes, slots=args.serve_slots, budget_bytes=args.budget_mb << 20)
     gids = [S.add_graph(g.row_ptr, g.col, directed=g.directed) for g, _ in mix]
+    # per-request options by graph family (request i is family i % 3: ER, BA,
+    # grid + shortcuts), as a client that knows its graphs would pass them:
+    # grids have no hubs and deep searches, which 256-source batches of
+    # nearby sources without deferral share best (3x on a 200k-node grid);
+    # 32 workgroups keep such a request's working memory within the budget
+    fam_opts = [dict(), dict(), dict(width=256, order="locality", defer_arcs=-1, slots=32)] if args.family_knobs \
+        else [dict(), dict(), dict()]
 
     def run(times):
         """Submit request i at times[i] seconds from now (None: all at once)."""
@@ -483,7 +492,7 @@ def serve_bench(args, bc, workloads):
                 delay = start + times[i] - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
-            tickets.append(S.submit(gid, k, mode="batched"))
+            tickets.append(S.submit(gid, k, mode="batched", **fam_opts[i % 3]))
         out = []
         for i, t in enumerate(tickets):
             S.wait(t, -1)
@@ -520,7 +529,8 @@ def serve_bench(args, bc, workloads):
                 capacity_rps=round(capacity, 3), offered_rps=round(rate, 3), load=args.load,
                 same_results_burst_vs_poisson=bool(same), dtype="int64", data="synthetic",
                 config=dict(workload=workloads.DESCRIPTION["serve512"], lanes=args.lanes,
-                            slots=args.serve_slots, budget_mb=args.budget_mb, mode="batched"),
+                            slots=args.serve_slots, budget_mb=args.budget_mb, mode="batched",
+                            family_options=fam_opts),
                 server=dict(uploads=info["uploads"], evictions=info["evictions"], peak_mb=round(info["peak_bytes"] / 2**20, 1),
                             completed=info["completed"], failed=info["failed"]))
     print(json.dumps(line), flush=True)

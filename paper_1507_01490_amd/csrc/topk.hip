@@ -138,6 +138,13 @@ __device__ inline void st64(uint64_t* p, uint64_t v) {
 __device__ inline int32_t ld32(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A value that every lane of the workgroup holds alike (read from LDS after a
+// barrier) moved to a scalar register, so that the branches and counters
+// that depend on it stay scalar instead of taking vector registers.
+__device__ inline uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ inline uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | (uint64_t)uni32((uint32_t)v);
+}
 
 // key(x) > key(y): A_x F_y > A_y F_x in 128 bits, ties by the smaller id
 __device__ inline bool key_gt(uint64_t Ax, uint64_t Fx, int32_t ix, uint64_t Ay, uint64_t Fy, int32_t iy) {
@@ -1570,7 +1577,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     auto has_threshold = [&]() -> bool {
         if (tid == 0) s_hasth = __hip_atomic_load(T.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ? 1u : 0u;
         __syncthreads();
-        const bool h = s_hasth != 0u;
+        const bool h = uni32(s_hasth) != 0u;
         __syncthreads();
         return h;
     };
@@ -1623,7 +1630,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     for (;;) {
         if (tid == 0) s_b = atomicAdd(next_batch, 1u);
         __syncthreads();
-        const uint32_t b = s_b;
+        const uint32_t b = uni32(s_b);
         __syncthreads();
         if (b >= nbatches) break;
         ++batches;
@@ -1663,13 +1670,13 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
             S[tid] = sv;
         }
         __syncthreads();
-        uint32_t live = cut_step<1>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D);
-        uint32_t flen = s_flen, d = 0, cur = 0, stamp = 0;
+        uint32_t live = uni32(cut_step<1>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D));
+        uint32_t flen = uni32(s_flen), d = 0, cur = 0, stamp = 0;
         uint32_t trial_d = 0;  // level whose over-counted bound test has run (0: none; level 0 needs none)
         uint64_t tp = __builtin_amdgcn_s_memrealtime();
         ticks[0] += tp - tb;
         while (live) {
-            if (s_mode == 0) {
+            if (uni32(s_mode) == 0) {
                 // ---------------- LDS level
                 const int32_t* F = L.fl[cur];
                 bool counted = false;  // the level's arcs are already in node_arcs
@@ -1686,7 +1693,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     tab_cheap_arcs<false>(G, L, nullptr, tot0, PX, cg, ct);
                     __syncthreads();
                     counted = true;
-                    live = trial_cut(T, S, W, d + 1, cg, ct, st, s_act, CL);
+                    live = uni32(trial_cut(T, S, W, d + 1, cg, ct, st, s_act, CL));
                     const uint64_t tq = __builtin_amdgcn_s_memrealtime();
                     ticks[1] += tq - tp;
                     tp = tq;
@@ -1696,7 +1703,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         break;
                     }
                 }
-                const uint64_t act = s_act[0];
+                const uint64_t act = uni64(s_act[0]);
                 if (tid == 0) L.tsum = 0;
                 __syncthreads();
                 unsigned long long tl = 0;
@@ -1706,7 +1713,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 }
                 if (tl) atomicAdd(&L.tsum, tl);
                 __syncthreads();
-                const unsigned long long Tarcs = L.tsum;
+                const unsigned long long Tarcs = uni64(L.tsum);
                 const uint32_t npass = (uint32_t)((Tarcs + kPassCap - 1) / kPassCap);
                 if (npass > kPassMax) {
                     to_global(F, flen);
@@ -1731,8 +1738,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     tab_next_reset<B>(L);
                     __syncthreads();
                 }
-                distinct = L.nins;
-                if (L.over) {
+                distinct = uni32(L.nins);
+                if (uni32(L.over)) {
                     // a pass overflowed H_next: count this level on the global records
                     if (tid < kBlk) {
                         cg[tid] = 0;
@@ -1749,12 +1756,12 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 tp = tq;
                 ++d;
                 ++levels;
-                live = cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
+                live = uni32(cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D));
                 tq = __builtin_amdgcn_s_memrealtime();
                 ticks[2] += tq - tp;
                 tp = tq;
                 if (!live) break;
-                const uint64_t lact = s_act[0];
+                const uint64_t lact = uni64(s_act[0]);
                 // nodes to build <= sum of gamma over the live sources
                 if (tid == 0) L.tsum = 0;
                 __syncthreads();
@@ -1763,8 +1770,8 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 // distinct nodes of the new level with a live bit: at most the
                 // pairs counted for the live sources, and at most the distinct
                 // targets the count passes inserted
-                const unsigned long long live_nodes = min(L.tsum, (unsigned long long)distinct);
-                if (force_spill || L.sfill + live_nodes > kSeenCap) {
+                const unsigned long long live_nodes = min((unsigned long long)uni64(L.tsum), (unsigned long long)distinct);
+                if (force_spill || uni32(L.sfill) + live_nodes > kSeenCap) {
                     // the new level does not fit H_seen: build it on the global records
                     to_global(F, flen);
                     if (tid == 0) s_nlen = 0;
@@ -1774,13 +1781,13 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
                                              &s_arcs, &s_arcs);
                     __syncthreads();
-                    const uint32_t nlen = s_nlen;
+                    const uint32_t nlen = uni32(s_nlen);
                     clear_cur<1>(P, P.qa, flen, 0, B);
                     if (tid == 0) s_flen = 0;
                     __syncthreads();
                     build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs, L.filter());
                     __syncthreads();
-                    flen = s_flen;
+                    flen = uni32(s_flen);
                     tq = __builtin_amdgcn_s_memrealtime();
                     ticks[3] += tq - tp;
                     tp = tq;
@@ -1799,7 +1806,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 }
                 for (uint32_t e = tid; e < flen; e += B) L.scur[F[e]] = 0;
                 __syncthreads();
-                const uint32_t fl2 = L.flen2;
+                const uint32_t fl2 = uni32(L.flen2);
                 for (uint32_t e = tid; e < fl2; e += B) {
                     const int32_t sl = Fn[e];
                     L.scur[sl] = L.sncur[sl];
@@ -1814,7 +1821,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
             } else {
                 // ---------------- global level (state on the node records)
                 const uint64_t tr0 = tp;
-                const unsigned long long ra0 = s_narcs, en0 = s_ent;
+                const unsigned long long ra0 = uni64(s_narcs), en0 = uni64(s_ent);
                 bool counted = false;
                 if (!no_trial && d >= 1 && trial_d != d + 1 && has_threshold()) {
                     trial_d = d + 1;
@@ -1823,7 +1830,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         ct[tid] = 0;
                     }
                     __syncthreads();
-                    const uint64_t act0 = s_act[0];
+                    const uint64_t act0 = uni64(s_act[0]);
                     for (uint32_t e0 = 0; e0 < flen; e0 += B) {
                         const uint32_t tot = rec_prologue(G, P, P.qa, e0, min(flen, e0 + B), act0, PX, &s_narcs,
                                                           &s_ent);
@@ -1831,7 +1838,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         __syncthreads();
                     }
                     counted = true;
-                    live = trial_cut(T, S, W, d + 1, cg, ct, st, s_act, CL);
+                    live = uni32(trial_cut(T, S, W, d + 1, cg, ct, st, s_act, CL));
                     const uint64_t tq = __builtin_amdgcn_s_memrealtime();
                     ticks[1] += tq - tp;
                     tp = tq;
@@ -1839,11 +1846,11 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         ++levels;
                         ++rec_lv;
                         rec_ticks += tq - tr0;
-                        rec_arcs += s_narcs - ra0;
+                        rec_arcs += uni64(s_narcs) - ra0;
                         break;
                     }
                 }
-                const uint64_t act = s_act[0];
+                const uint64_t act = uni64(s_act[0]);
                 // When the level's arcs fit the LDS counting passes, count it in
                 // H_next with the seen bits read from the node records (no global
                 // atomics); the records take the level only if a source survives.
@@ -1858,7 +1865,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     if (tl) atomicAdd(&L.tsum, tl);
                 }
                 __syncthreads();
-                const unsigned long long Tarcs = L.tsum;
+                const unsigned long long Tarcs = uni64(L.tsum);
                 const uint32_t npass = (uint32_t)((Tarcs + kPassCap - 1) / kPassCap);
                 bool hybrid = false;
                 if (npass <= kPassMax) {
@@ -1883,7 +1890,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         tab_next_reset<B>(L);
                         __syncthreads();
                     }
-                    hybrid = L.over == 0u;
+                    hybrid = uni32(L.over) == 0u;
                     if (!hybrid && tid == 0) {
                         s_narcs = ra0;  // recounted below
                         s_ent = en0;
@@ -1891,14 +1898,14 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     __syncthreads();
                 }
                 if (hybrid) {
-                    disc += L.nins;
+                    disc += uni32(L.nins);
                     ++rec_lv;
                     uint64_t tq = __builtin_amdgcn_s_memrealtime();
                     ticks[1] += tq - tp;
                     tp = tq;
                     ++d;
                     ++levels;
-                    live = cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
+                    live = uni32(cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D));
                     tq = __builtin_amdgcn_s_memrealtime();
                     ticks[2] += tq - tp;
                     tp = tq;
@@ -1911,20 +1918,20 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                             expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp,
                                                  LE, &s_arcs, &s_arcs);
                         __syncthreads();
-                        const uint32_t nlen = s_nlen;
+                        const uint32_t nlen = uni32(s_nlen);
                         clear_cur<1>(P, P.qa, flen, 0, B);
                         if (tid == 0) s_flen = 0;
                         __syncthreads();
                         build_level<1>(P, P.qb, nlen, 0, B, s_act, true, P.qa, &s_flen, &s_clen, &s_arcs,
                                        L.filter());
                         __syncthreads();
-                        flen = s_flen;
+                        flen = uni32(s_flen);
                     }
                     tq = __builtin_amdgcn_s_memrealtime();
                     ticks[3] += tq - tp;
                     tp = tq;
                     rec_ticks += tq - tr0;
-                    rec_arcs += s_narcs - ra0;
+                    rec_arcs += uni64(s_narcs) - ra0;
                     continue;
                 }
                 ++stamp;
@@ -1938,7 +1945,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
                                          &s_narcs, &s_ent);
                 __syncthreads();
-                const uint32_t nlen = s_nlen;
+                const uint32_t nlen = uni32(s_nlen);
                 count_level<1, B>(P, P.qb, nlen, cg, ct);
                 __syncthreads();
                 disc += nlen;
@@ -1948,7 +1955,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 tp = tq;
                 ++d;
                 ++levels;
-                live = cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
+                live = uni32(cut_step<1>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D));
                 tq = __builtin_amdgcn_s_memrealtime();
                 ticks[2] += tq - tp;
                 tp = tq;
@@ -1958,17 +1965,17 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 build_level<1>(P, P.qb, nlen, 0, B, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs,
                                L.filter());
                 __syncthreads();
-                flen = s_flen;
+                flen = uni32(s_flen);
                 tq = __builtin_amdgcn_s_memrealtime();
                 ticks[3] += tq - tp;
                 tp = tq;
                 rec_ticks += tq - tr0;
-                rec_arcs += s_narcs - ra0;
+                rec_arcs += uni64(s_narcs) - ra0;
             }
         }
         // reset the batch state: global records (when used) and the LDS tables
-        if (s_mode == 1) {
-            const uint32_t nc = s_clen;
+        if (uni32(s_mode) == 1) {
+            const uint32_t nc = uni32(s_clen);
             for (uint32_t i = tid; i < nc; i += B) {
                 uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
                 rec[0] = 0;

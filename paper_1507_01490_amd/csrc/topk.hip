@@ -1564,7 +1564,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     __shared__ CutLds CL;
     __shared__ uint32_t s_flen, s_nlen, s_clen, s_b, s_mode, s_hasth;
     __shared__ uint64_t s_act[4];
-    __shared__ unsigned long long s_arcs, s_narcs, s_ent;
+    __shared__ unsigned long long s_arcs, s_narcs, s_ent, s_ent_lv;
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
     SlotPtrs P;
@@ -1704,22 +1704,6 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     }
                 }
                 const uint64_t act = uni64(s_act[0]);
-                if (tid == 0) L.tsum = 0;
-                __syncthreads();
-                unsigned long long tl = 0;
-                for (uint32_t e = tid; e < flen; e += B) {
-                    const int32_t sl = F[e];
-                    if (L.scur[sl] & act) tl += G.deg[L.skey[sl]];
-                }
-                if (tl) atomicAdd(&L.tsum, tl);
-                __syncthreads();
-                const unsigned long long Tarcs = uni64(L.tsum);
-                const uint32_t npass = (uint32_t)((Tarcs + kPassCap - 1) / kPassCap);
-                if (npass > kPassMax) {
-                    to_global(F, flen);
-                    continue;
-                }
-                const uint32_t np = npass > 0 ? npass : 1;
                 if (tid < kBlk) {
                     cg[tid] = 0;
                     ct[tid] = 0;
@@ -1727,11 +1711,25 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 if (tid == 0) {
                     L.nins = 0;
                     L.over = 0;
+                    s_ent_lv = 0;
                 }
                 __syncthreads();
+                // the prologue's arc total is the level's arc count, which sets
+                // the passes (the frontier holds distinct nodes, so it is below
+                // m < 2^31); its statistics are kept only if the level stays here
+                const uint32_t tot = uni32(tab_prologue(G, L, F, flen, act, PX, nullptr,
+                                                        counted ? nullptr : &s_ent_lv));
+                const uint32_t npass = (tot + kPassCap - 1) / kPassCap;
+                if (npass > kPassMax) {
+                    to_global(F, flen);
+                    continue;
+                }
+                if (!counted && tid == 0) {
+                    s_narcs += tot;
+                    s_ent += s_ent_lv;
+                }
+                const uint32_t np = npass > 0 ? npass : 1;
                 uint32_t distinct = 0;
-                const uint32_t tot = tab_prologue(G, L, F, flen, act, PX, counted ? nullptr : &s_narcs,
-                                                  counted ? nullptr : &s_ent);
                 for (uint32_t p = 0; p < np; ++p) {
                     tab_arcs<true, false>(G, L, nullptr, tot, np, p, PX, cg, ct);
                     __syncthreads();

@@ -432,8 +432,12 @@ struct LdsExpand {
 
 // Expand entries [e0, e1) (at most kBlk) of the frontier list F: every arc of
 // every entry with a live bit, balanced over the workgroup by a scan of the
-// degrees.  Nodes reached for the first time this level go to N once.
-template <int WW, int B = kBlk>
+// degrees.  Nodes reached for the first time this level go to N once.  Each
+// thread takes kArcs arcs per round (a, a + B, ...) and issues all their
+// target loads before it visits any target's record: two in the
+// level-synchronous kernel, one in the persistent kernels, where the second
+// arc's registers cost more than its overlap gains.
+template <int WW, int B = kBlk, int kArcs = 2>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
                                const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW, B>& L,
                                unsigned long long* arcs, unsigned long long* entries) {
@@ -468,22 +472,53 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
     const uint32_t off = block_exscan<B>(deg, L.scan, &total);
     L.off[tid] = off;
     __syncthreads();
-    for (uint32_t a0 = 0; a0 < total; a0 += B) {
-        const uint32_t a = a0 + tid;
-        bool app = false;
-        int32_t w = 0;
-        if (a < total) {
-            // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
-            uint32_t lo = 0, hi = B;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (L.off[mid] <= a) lo = mid + 1; else hi = mid;
+    if constexpr (kArcs == 1) {
+        for (uint32_t a0 = 0; a0 < total; a0 += B) {
+            const uint32_t a = a0 + tid;
+            bool app = false;
+            int32_t w = 0;
+            if (a < total) {
+                // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
+                uint32_t lo = 0, hi = B;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (L.off[mid] <= a) lo = mid + 1; else hi = mid;
+                }
+                const uint32_t i = lo - 1;
+                w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
+                app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp);
             }
-            const uint32_t i = lo - 1;
-            w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
-            app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp);
+            append_if(app, w, N, nctr);
         }
-        append_if(app, w, N, nctr);
+    } else {
+        for (uint32_t a0 = 0; a0 < total; a0 += kArcs * B) {
+            bool app[kArcs];
+            int32_t w[kArcs];
+            uint32_t own[kArcs];
+#pragma unroll
+            for (int u = 0; u < kArcs; ++u) {
+                app[u] = false;
+                w[u] = 0;
+                own[u] = 0;
+                const uint32_t a = a0 + (uint32_t)u * B + tid;
+                if (a < total) {
+                    // owner entry: the last i with off[i] <= a (off[0] = 0 <= a)
+                    uint32_t lo = 0, hi = B;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (L.off[mid] <= a) lo = mid + 1; else hi = mid;
+                    }
+                    own[u] = lo - 1;
+                    w[u] = G.col[L.beg[own[u]] + (int32_t)(a - L.off[own[u]])];
+                    app[u] = true;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kArcs; ++u)
+                if (app[u]) app[u] = visit<WW>(&P.ns[(size_t)w[u] * Lo::SW], &L.m[own[u] * WW], stamp);
+#pragma unroll
+            for (int u = 0; u < kArcs; ++u) append_if(app[u], w[u], N, nctr);
+        }
     }
     if (tid == 0) *arcs += total;
     __syncthreads();
@@ -1166,7 +1201,7 @@ __global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order,
             if (tid == 0) s_nlen = 0;
             __syncthreads();
             for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                expand_entries<WW, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, &s_narcs,
+                expand_entries<WW, B, 1>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, &s_narcs,
                                       &s_ent);
             __syncthreads();
             const uint32_t nlen = s_nlen;
@@ -1776,7 +1811,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     __syncthreads();
                     ++stamp;
                     for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                        expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
+                        expand_entries<1, B, 1>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
                                              &s_arcs, &s_arcs);
                     __syncthreads();
                     const uint32_t nlen = uni32(s_nlen);
@@ -1913,7 +1948,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         if (tid == 0) s_nlen = 0;
                         __syncthreads();
                         for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                            expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp,
+                            expand_entries<1, B, 1>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp,
                                                  LE, &s_arcs, &s_arcs);
                         __syncthreads();
                         const uint32_t nlen = uni32(s_nlen);
@@ -1940,7 +1975,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 if (tid == 0) s_nlen = 0;
                 __syncthreads();
                 for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                    expand_entries<1, B>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
+                    expand_entries<1, B, 1>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE,
                                          &s_narcs, &s_ent);
                 __syncthreads();
                 const uint32_t nlen = uni32(s_nlen);

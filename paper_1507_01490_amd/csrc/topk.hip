@@ -1560,13 +1560,14 @@ __device__ inline void tab_next_reset(LdsTab& L) {
 // After a build pass: every H_next entry becomes (or updates) an H_seen entry
 // and joins the next frontier; H_next is cleared.
 template <int B>
-__device__ inline void tab_build_pass(LdsTab& L, int32_t* Fn) {
+__device__ inline void tab_build_pass(LdsTab& L, int32_t* Fn, uint64_t keep = ~0ull) {
     for (int i = threadIdx.x; i < kCapN; i += B) {
         const int32_t w = L.nkey[i];
         if (w < 0) continue;
-        const uint64_t bits = L.nmask[i];
+        const uint64_t bits = L.nmask[i] & keep;
         L.nkey[i] = -1;
         L.nmask[i] = 0;
+        if (!bits) continue;
         const int s = tab_seen_claim(L, w);
         if (s < 0) {
             L.over = 1u;
@@ -1764,12 +1765,19 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                     s_ent += s_ent_lv;
                 }
                 const uint32_t np = npass > 0 ? npass : 1;
+                // A single-pass level keeps its H_next (every target with the
+                // bits of all sources counted) for the build, which then only
+                // masks it with the surviving sources instead of walking the
+                // level's arcs again.  Every other way out clears it.
+                const bool keep_next = np == 1;
                 uint32_t distinct = 0;
                 for (uint32_t p = 0; p < np; ++p) {
                     tab_arcs<true, false>(G, L, nullptr, tot, np, p, PX, cg, ct);
                     __syncthreads();
-                    tab_next_reset<B>(L);
-                    __syncthreads();
+                    if (!keep_next) {
+                        tab_next_reset<B>(L);
+                        __syncthreads();
+                    }
                 }
                 distinct = uni32(L.nins);
                 if (uni32(L.over)) {
@@ -1778,6 +1786,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                         cg[tid] = 0;
                         ct[tid] = 0;
                     }
+                    if (keep_next) tab_next_reset<B>(L);
                     __syncthreads();
                     to_global(F, flen);
                     continue;
@@ -1793,7 +1802,13 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 tq = __builtin_amdgcn_s_memrealtime();
                 ticks[2] += tq - tp;
                 tp = tq;
-                if (!live) break;
+                if (!live) {
+                    if (keep_next) {
+                        tab_next_reset<B>(L);
+                        __syncthreads();
+                    }
+                    break;
+                }
                 const uint64_t lact = uni64(s_act[0]);
                 // nodes to build <= sum of gamma over the live sources
                 if (tid == 0) L.tsum = 0;
@@ -1806,6 +1821,10 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 const unsigned long long live_nodes = min((unsigned long long)uni64(L.tsum), (unsigned long long)distinct);
                 if (force_spill || uni32(L.sfill) + live_nodes > kSeenCap) {
                     // the new level does not fit H_seen: build it on the global records
+                    if (keep_next) {
+                        tab_next_reset<B>(L);
+                        __syncthreads();
+                    }
                     to_global(F, flen);
                     if (tid == 0) s_nlen = 0;
                     __syncthreads();
@@ -1830,12 +1849,19 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 int32_t* Fn = L.fl[cur ^ 1];
                 if (tid == 0) L.flen2 = 0;
                 __syncthreads();
-                const uint32_t tot2 = tab_prologue(G, L, F, flen, lact, PX, nullptr, nullptr);
-                for (uint32_t p = 0; p < np; ++p) {
-                    tab_arcs<false, false>(G, L, nullptr, tot2, np, p, PX, nullptr, nullptr);
+                if (keep_next) {
+                    // H_next of the count holds, per target, the bits of every
+                    // source counted; the survivors' bits are the new level
+                    tab_build_pass<B>(L, Fn, lact);
                     __syncthreads();
-                    tab_build_pass<B>(L, Fn);
-                    __syncthreads();
+                } else {
+                    const uint32_t tot2 = tab_prologue(G, L, F, flen, lact, PX, nullptr, nullptr);
+                    for (uint32_t p = 0; p < np; ++p) {
+                        tab_arcs<false, false>(G, L, nullptr, tot2, np, p, PX, nullptr, nullptr);
+                        __syncthreads();
+                        tab_build_pass<B>(L, Fn);
+                        __syncthreads();
+                    }
                 }
                 for (uint32_t e = tid; e < flen; e += B) L.scur[F[e]] = 0;
                 __syncthreads();

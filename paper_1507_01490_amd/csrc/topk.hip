@@ -198,17 +198,20 @@ __device__ void topk_insert(const TopKDev& T, uint64_t A, uint64_t F, uint64_t f
     }
 }
 
-// The record at seq-1 was written before seq was published (release); its
-// address depends on the loaded seq, and device-scope loads read past the
-// non-coherent caches, so a relaxed read of seq is enough here.
+// The record at seq-1 was written before seq was published with a release
+// store at agent scope; the acquire load of seq here pairs with it, so the
+// record's three words are visible once seq is (the ring itself is never
+// cleared between queries).  A record with F = 0 cannot be a published one
+// (F = f >= 1 for r >= 2, and F = 1 for r = 1) and is treated as no threshold,
+// which is always safe: it only means no source is cut.
 __device__ inline bool load_threshold(const TopKDev& T, ThRec* th) {
-    uint32_t s = __hip_atomic_load(T.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t s = __hip_atomic_load(T.seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     if (s == 0) return false;
     ThRec* r = &T.ring[s - 1];
     th->A = ld64(&r->A);
     th->F = ld64(&r->F);
     th->id = (int64_t)ld64((const uint64_t*)&r->id);
-    return true;
+    return th->F != 0;
 }
 
 __device__ inline void lock_acquire(uint32_t* l) {
@@ -1611,7 +1614,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
     unsigned long long levels = 0, batches = 0, disc = 0, lds_lv = 0, rec_lv = 0, spills = 0;
     // whether a k-th best record has been published (the trial cut needs one)
     auto has_threshold = [&]() -> bool {
-        if (tid == 0) s_hasth = __hip_atomic_load(T.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ? 1u : 0u;
+        if (tid == 0) s_hasth = __hip_atomic_load(T.seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u ? 1u : 0u;
         __syncthreads();
         const bool h = uni32(s_hasth) != 0u;
         __syncthreads();
@@ -2212,6 +2215,14 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
             BC_HIP(hipStreamSynchronize(s));
             // control block words: d, flen, nlen, clen, live, pull, chunk, done, stamp, ran, front_arcs
             const uint32_t flen = hctl[1], live = hctl[4], pull = hctl[5];
+            // every list holds distinct nodes, so no length can exceed n: a
+            // longer one means the level step wrote out of order, and no
+            // further kernel may index the lists with it
+            if (flen > (uint32_t)n || hctl[2] > (uint32_t)n || hctl[3] > (uint32_t)n) {
+                set_error("internal: level %u list lengths %u/%u/%u exceed n = %d", hctl[0], flen, hctl[2], hctl[3],
+                          n);
+                return BC_EDEVICE;
+            }
             unsigned long long fa;
             std::memcpy(&fa, hctl + 10, sizeof(fa));
             if (!live) break;

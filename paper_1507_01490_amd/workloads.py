@@ -11,6 +11,11 @@ are queried with).  Inputs only: no part of the method lives here.
           seed 5; k = 10
   rgg18   the same random geometric family at n = 2^18 (the size the oracle
           and the GPU finish in minutes; n = 4M needs ~2e13 visited arcs)
+  rgg20   the same random geometric family at n = 2^20 (the largest size the
+          multi-threaded oracle finishes in about an hour)
+  collab500k  the collaboration family at a quarter of the full size: 500,000
+          actors, 125,000 groups, same size law, seed 4 (the oracle finishes it;
+          the full 2M-actor graph needs ~2e13 visited arcs)
   serve512  serving mix: 512 graphs, n log-uniform in [1e3, 2e5], one third
           each Erdos-Renyi (average degree 8), Barabasi-Albert (m = 4) and
           2-D grid with 1 % random shortcuts; one request per graph with k
@@ -28,9 +33,12 @@ DESCRIPTION = {
     "rmat21": "directed R-MAT scale=21 edge_factor=16 (0.57,0.19,0.19,0.05) dedup seed=2",
     "collab": "undirected collaboration projection actors=2000000 groups=500000 zipf=2.1 cap=200 seed=4",
     "rgg": "undirected random geometric graph n=4000000 avg_deg=6 seed=5",
+    "rgg20": "undirected random geometric graph n=1048576 avg_deg=6 seed=5",
+    "collab500k": "undirected collaboration projection actors=500000 groups=125000 zipf=2.1 cap=200 seed=4",
 }
 
-KS = {"ba2k": (1, 10), "ba1m": (1, 10, 100), "rmat21": (10,), "collab": (10,), "rgg": (10,), "rgg18": (10,)}
+KS = {"ba2k": (1, 10), "ba1m": (1, 10, 100), "rmat21": (10,), "collab": (10,), "rgg": (10,), "rgg18": (10,),
+      "rgg20": (10,), "collab500k": (10,)}
 DESCRIPTION["serve512"] = ("serving mix: 512 graphs n~logU[1e3,2e5] (ER deg 8 / BA m=4 / grid+1% shortcuts), "
                            "k~U{1,10,100}, seed=3")
 
@@ -83,4 +91,8 @@ def build(name: str) -> synth.Csr:
         return synth.random_geometric(4_000_000, 6.0, 5)
     if name == "rgg18":
         return synth.random_geometric(1 << 18, 6.0, 5)
+    if name == "rgg20":
+        return synth.random_geometric(1 << 20, 6.0, 5)
+    if name == "collab500k":
+        return synth.collaboration(500_000, 125_000, 2.1, 200, 4)
     raise KeyError(name)

@@ -8,7 +8,13 @@ and the visited-arc count m_vis of the sequential run in decreasing-degree
 order (Algorithm 1 with one thread), which the benchmark uses as the fixed
 work numerator of its throughput.
 
-Usage: python tests/golden/make_golden.py [ba1m] [rmat21] [collab] [rgg]
+Workloads too large for a single-threaded run (``PARALLEL_ONLY``) are run
+with the oracle's parallel loop only (Section 2.1: threads share the k-th
+best value; the answer is the same as the sequential one).  Their files
+record ``m_vis_par`` (the arcs of that run, which depends on the thread
+timing) instead of ``m_vis_seq``.
+
+Usage: python tests/golden/make_golden.py [--threads T] [ba1m] [rmat21] [collab500k] [rgg20] ...
 """
 
 import json
@@ -23,12 +29,24 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from paper_1507_01490_amd import workloads  # noqa: E402
 
+PARALLEL_ONLY = {"collab500k", "rgg20"}
+
 
 def run(name: str, ks, threads: int):
     g = workloads.build(name)
     out = dict(workload=name, description=workloads.DESCRIPTION[name], n=g.n, m=g.m,
                directed=bool(g.directed), sha256=g.sha256(), results={})
     for k in ks:
+        if name in PARALLEL_ONLY:
+            t0 = time.time()
+            par = oracle.topk(g, k, nthreads=threads)
+            t1 = time.time()
+            out["results"][str(k)] = dict(ids=par["ids"].tolist(), farness=[int(x) for x in par["f"]],
+                                          reach=[int(x) for x in par["r"]], m_vis_par=int(par["stats"]["m_vis"]),
+                                          n_done_par=int(par["stats"]["n_done"]), threads=threads,
+                                          oracle_par_s=round(t1 - t0, 2))
+            print(name, k, f"{t1 - t0:.1f}s with {threads} threads", par["stats"], flush=True)
+            continue
         t0 = time.time()
         seq = oracle.topk(g, k, nthreads=1)
         t1 = time.time()
@@ -47,6 +65,11 @@ def run(name: str, ks, threads: int):
 
 
 if __name__ == "__main__":
-    targets = sys.argv[1:] or ["ba1m"]
-    for t in targets:
-        run(t, workloads.KS[t], threads=8)
+    args = sys.argv[1:]
+    threads = 8
+    if "--threads" in args:
+        i = args.index("--threads")
+        threads = int(args[i + 1])
+        del args[i:i + 2]
+    for t in args or ["ba1m"]:
+        run(t, workloads.KS[t], threads=threads)

@@ -252,6 +252,60 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
                   uint32_t* reach, int32_t* count, bc_stats* stats);
 
 /*
+ * Many queries, one launch.  Algorithm 1 runs its sources in any order and
+ * the sources of one query share only the k-th best value (Section 2.1), so
+ * the source batches of several queries, on graphs of different sizes, can
+ * run side by side in one persistent kernel: every workgroup claims the next
+ * batch of a single global sequence, whichever query it belongs to, and each
+ * query keeps its own top-k list and threshold records.  The seed batches of
+ * every query (ceil(k / W) batches, the first of its order) come first in the
+ * sequence; the other batches of a query wait, for a bounded time, until its
+ * seed batches have finished, so that they start with a k-th best value to
+ * cut against.  Results are those of bc_topk on each graph alone.
+ *
+ * bc_multi_create -- prepare a launch over `count` queries.
+ *   graphs   host array of count graph handles on the current device (a graph
+ *            may appear several times; every graph must outlive the launch)
+ *   ks       host, count entries: k of each query (>= 1)
+ *   opts     NULL for the defaults; width (64, 128 or 256, shared by all
+ *            queries), order (a rule applied to each graph: BC_ORDER_DEGREE,
+ *            BC_ORDER_GROUPED (the default), BC_ORDER_LOCALITY or a learned
+ *            order with opts.mlp), slots (workgroups, 0 = one per compute unit)
+ *            and bounds (BC_BOUND_FOOTNOTE) apply; mode, seed_*, defer_*,
+ *            lds_tables and graph_levels are ignored (every batch runs in the
+ *            launch); BC_ORDER_GIVEN / BC_ORDER_SCORES and opts.first are
+ *            rejected (BC_EINVAL)
+ *   capture  nonzero: record the launch (a fill kernel that clears the
+ *            per-query state, then the persistent kernel) as a HIP graph once,
+ *            and replay it on every bc_multi_run
+ *   stream   hipStream_t of the runs (NULL = the legacy default stream)
+ *   out      receives the handle; release it with bc_multi_destroy
+ * The launch owns its device memory: the source orders, per-query lists,
+ * threshold records and statistics, and node-record slots sized for the
+ * largest graph.  Errors: BC_EINVAL, BC_ENOMEM, BC_EDEVICE.
+ *
+ * bc_multi_run -- run the prepared launch (blocking; any number of times,
+ * never two at once on one handle).
+ *   ids, farness, reach  host, sum of ks entries: query i writes its results,
+ *            sorted by decreasing key, from offset ks[0] + ... + ks[i-1]
+ *   counts   host, count entries: min(k_i, n_i) results per query
+ *   stats    host, optional (NULL): count bc_stats, each with its size set
+ *            (persistent_ms and query_ms are those of the whole launch)
+ *
+ * bc_topk_multi -- bc_multi_create (no capture, on the first graph's stream),
+ * one bc_multi_run, bc_multi_destroy.
+ */
+typedef struct bc_multi bc_multi;
+
+bc_status bc_multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts* opts,
+                          int32_t capture, void* stream, bc_multi** out);
+bc_status bc_multi_run(bc_multi* p, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts,
+                       bc_stats* stats);
+bc_status bc_multi_destroy(bc_multi* p);
+bc_status bc_topk_multi(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts* opts,
+                        int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts, bc_stats* stats);
+
+/*
  * bc_farness_all -- exact farness and reach of every node (the textbook
  * computation of Section 1: one breadth-first search per node, here in
  * bit-parallel batches, with no bound and no cut).

@@ -26,7 +26,7 @@ __all__ = ["Graph", "TopK", "Opts", "Stats", "BcError", "load_library", "closene
            "MODE_PLAIN", "MODE_BATCHED", "ORDER_DEGREE", "ORDER_GIVEN", "ORDER_SCORES", "ORDER_GROUPED",
            "ORDER_LEARNED", "ORDER_LEARNED_GROUPED", "MLP_PARAMS", "Server", "ServerOpts", "RequestInfo",
            "ServerStats", "footprint", "LIB_PATH", "MLP_PATH", "default_mlp", "mlp_forward", "mlp_loss_grad",
-           "mlp_adam"]
+           "mlp_adam", "MultiLaunch", "topk_multi"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.so")
 # trained parameters of the order perceptron (written by train_order.py)
@@ -149,6 +149,10 @@ def load_library(path: str = LIB_PATH):
     lib.bc_autotune.argtypes = [P, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(Opts), ctypes.POINTER(TuneReport)]
     lib.bc_footprint.argtypes = [i32, i64, u32, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(u64),
                                  ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.bc_multi_create.argtypes = [P, i32, P, ctypes.POINTER(Opts), i32, P, ctypes.POINTER(P)]
+    lib.bc_multi_run.argtypes = [P, P, P, P, P, P]
+    lib.bc_multi_destroy.argtypes = [P]
+    lib.bc_topk_multi.argtypes = [P, i32, P, ctypes.POINTER(Opts), P, P, P, P, P]
     lib.bc_graph_features.argtypes = [P, P, P]
     lib.bc_mlp_forward.argtypes = [P, P, i64, P, P]
     lib.bc_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, i64, P, ctypes.POINTER(ctypes.c_double), P]
@@ -157,7 +161,7 @@ def load_library(path: str = LIB_PATH):
                  "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_source_order", "bc_graph_features", "bc_server_create",
                  "bc_server_destroy", "bc_server_add_graph", "bc_submit", "bc_wait", "bc_poll", "bc_cancel",
                  "bc_server_info", "bc_footprint", "bc_autotune", "bc_mlp_forward", "bc_mlp_loss_grad",
-                 "bc_mlp_adam"):
+                 "bc_mlp_adam", "bc_multi_create", "bc_multi_run", "bc_multi_destroy", "bc_topk_multi"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -581,3 +585,93 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _multi_args(graphs, ks, keep, order=None, width=64, slots=0, footnote=False, mlp=None):
+    graphs = list(graphs)
+    ks = [int(k) for k in ks]
+    if len(graphs) != len(ks) or not graphs:
+        raise ValueError("one k per graph, at least one graph")
+    o = make_opts(max(g.n for g in graphs), keep, mode="batched", width=width, slots=slots, footnote=footnote,
+                  order=order if (order is None or isinstance(order, str)) else None, mlp=mlp)
+    if order is not None and not isinstance(order, str):
+        raise TypeError("job launches take an order rule (a string), not a permutation")
+    hs = (ctypes.c_void_p * len(graphs))(*[g._h.value for g in graphs])
+    kv = np.ascontiguousarray(ks, dtype=np.int32)
+    keep += [hs, kv]
+    return graphs, ks, o, hs, kv
+
+
+def _multi_results(graphs, ks, ids, far, rea, cnt, sts):
+    out, off = [], 0
+    for i, k in enumerate(ks):
+        c = int(cnt[i])
+        out.append(TopK(ids[off:off + c].copy(), far[off:off + c].copy(), rea[off:off + c].copy(),
+                        sts[i].as_dict()))
+        off += k
+    return out
+
+
+class MultiLaunch:
+    """Top-k queries over several graphs in one persistent launch
+    (bc_multi_create / bc_multi_run): results are each graph's own top-k.
+    capture=True records the launch as a HIP graph replayed by every run()."""
+
+    def __init__(self, graphs, ks, capture: bool = True, stream=None, **kw):
+        keep = []
+        self._graphs, self._ks, o, hs, kv = _multi_args(graphs, ks, keep, **kw)
+        s = None
+        if stream is not None:
+            s = ctypes.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+        h = ctypes.c_void_p()
+        _check(load_library().bc_multi_create(hs, len(self._graphs), _ptr(kv), ctypes.byref(o), int(bool(capture)), s,
+                                              ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        """List of TopK, one per query, in the order given."""
+        tot = sum(self._ks)
+        ids = np.zeros(tot, np.int32)
+        far = np.zeros(tot, np.uint64)
+        rea = np.zeros(tot, np.uint32)
+        cnt = np.zeros(len(self._ks), np.int32)
+        sts = (Stats * len(self._ks))()
+        for st in sts:
+            st.size = ctypes.sizeof(Stats)
+        _check(load_library().bc_multi_run(self._h, _ptr(ids), _ptr(far), _ptr(rea), _ptr(cnt),
+                                           ctypes.cast(sts, ctypes.c_void_p)))
+        return _multi_results(self._graphs, self._ks, ids, far, rea, cnt, sts)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().bc_multi_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def topk_multi(graphs, ks, **kw):
+    """Top-k of several graphs in one persistent launch (bc_topk_multi)."""
+    keep = []
+    graphs, ks, o, hs, kv = _multi_args(graphs, ks, keep, **kw)
+    tot = sum(ks)
+    ids = np.zeros(tot, np.int32)
+    far = np.zeros(tot, np.uint64)
+    rea = np.zeros(tot, np.uint32)
+    cnt = np.zeros(len(ks), np.int32)
+    sts = (Stats * len(ks))()
+    for st in sts:
+        st.size = ctypes.sizeof(Stats)
+    _check(load_library().bc_topk_multi(hs, len(graphs), _ptr(kv), ctypes.byref(o), _ptr(ids), _ptr(far), _ptr(rea),
+                                        _ptr(cnt), ctypes.cast(sts, ctypes.c_void_p)))
+    return _multi_results(graphs, ks, ids, far, rea, cnt, sts)

@@ -211,6 +211,65 @@ bc_status bc_source_order(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* 
     BC_GUARD_END
 }
 
+static bc_status check_multi(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts* opts,
+                             bc_opts* o) {
+    if (count < 1) { set_error("count must be positive (got %d)", count); return BC_EINVAL; }
+    if (!graphs || !ks) { set_error("graphs/ks is NULL"); return BC_EINVAL; }
+    BC_TRY(copy_opts(opts, o));
+    if (o->nfirst != 0) { set_error("opts.first is not supported by job launches"); return BC_EINVAL; }
+    if (o->order == BC_ORDER_GIVEN || o->order == BC_ORDER_SCORES) {
+        set_error("per-graph orders are not supported by job launches (order %d)", o->order);
+        return BC_EINVAL;
+    }
+    return BC_OK;
+}
+
+bc_status bc_multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts* opts,
+                          int32_t capture, void* stream, bc_multi** out) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!out) { set_error("out is NULL"); return BC_EINVAL; }
+    *out = nullptr;
+    bc_opts o;
+    BC_TRY(check_multi(graphs, count, ks, opts, &o));
+    return bc::multi_create(graphs, count, ks, o, (hipStream_t)stream, capture != 0, out);
+    BC_GUARD_END
+}
+
+bc_status bc_multi_run(bc_multi* p, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts,
+                       bc_stats* stats) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!p) { set_error("launch is NULL"); return BC_EINVAL; }
+    if (!ids || !farness || !reach || !counts) { set_error("NULL output array"); return BC_EINVAL; }
+    return bc::multi_run(p, ids, farness, reach, counts, stats);
+    BC_GUARD_END
+}
+
+bc_status bc_multi_destroy(bc_multi* p) {
+    BC_GUARD_BEGIN
+    if (p) bc::multi_destroy(p);
+    return BC_OK;
+    BC_GUARD_END
+}
+
+bc_status bc_topk_multi(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts* opts,
+                        int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts, bc_stats* stats) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    bc_opts o;
+    BC_TRY(check_multi(graphs, count, ks, opts, &o));
+    if (!ids || !farness || !reach || !counts) { set_error("NULL output array"); return BC_EINVAL; }
+    for (int32_t i = 0; i < count; ++i)
+        if (!graphs[i]) { set_error("graph %d is NULL", i); return BC_EINVAL; }
+    bc_multi* p = nullptr;
+    BC_TRY(bc::multi_create(graphs, count, ks, o, graphs[0]->stream, false, &p));
+    const bc_status rs = bc::multi_run(p, ids, farness, reach, counts, stats);
+    bc::multi_destroy(p);
+    return rs;
+    BC_GUARD_END
+}
+
 bc_status bc_graph_features(bc_graph* g, float* x, uint32_t* core) {
     BC_GUARD_BEGIN
     bc::g_err[0] = 0;

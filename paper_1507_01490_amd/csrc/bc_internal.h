@@ -228,4 +228,13 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
 bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st,
                           hipStream_t s);
 
+// Many queries (graph, k) in one persistent launch (topk.hip): prepare the
+// launch (orders, per-query state, descriptors, shared slots; with capture,
+// a HIP graph of it), run it (any number of times), release it.
+bc_status multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts& o, hipStream_t s,
+                       bool capture, bc_multi** out);
+bc_status multi_run(bc_multi* p, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts,
+                    bc_stats* stats);
+void multi_destroy(bc_multi* p);
+
 }  // namespace bc

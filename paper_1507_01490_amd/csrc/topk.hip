@@ -339,9 +339,12 @@ __device__ inline void wave_count_nodes(const uint64_t* nb, uint32_t deg, uint32
 
 // Counters of the level just reached, from its list N[0, len) of newly
 // reached nodes (each once) after the expansion: the nxt masks are read from
-// L2 (they were written by atomics this level).
+// L2 (they were written by atomics this level).  The out-degree comes from
+// the record's meta word, or from degs[] when the records are shared by the
+// batches of several graphs (their meta words then hold no degree).
 template <int WW, int B>
-__device__ void count_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t* cg, unsigned long long* ct) {
+__device__ void count_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t* cg, unsigned long long* ct,
+                            const uint32_t* degs = nullptr) {
     using Lo = Layout<WW>;
     const uint32_t tid = threadIdx.x;
     for (uint32_t rb = 0; rb < len; rb += B) {
@@ -356,7 +359,7 @@ __device__ void count_level(const SlotPtrs& P, const int32_t* N, uint32_t len, u
 #pragma unroll
             for (int j = 0; j < WW; ++j)
                 nb[j] = __hip_atomic_load(&rec[Lo::NXT + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            deg = (uint32_t)(rec[Lo::META] >> 32);
+            deg = degs ? degs[N[i]] : (uint32_t)(rec[Lo::META] >> 32);
         }
         wave_count_nodes<WW>(nb, deg, cg, ct);
     }
@@ -1140,6 +1143,96 @@ __global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
 
 // ------------------------------------------------------ batched kernel
 
+// Shared memory of the record-based persistent kernels (one slot per
+// workgroup, every level of a batch inside the workgroup).
+template <int WW, int B>
+struct RecLds {
+    LdsExpand<WW, B> LE;
+    SrcState S[kBlk];
+    uint32_t cg[kBlk];
+    unsigned long long ct[kBlk];
+    CutLds CL;
+    uint32_t flen, nlen, clen;
+    uint64_t act[4];
+    unsigned long long arcs, narcs, ent;  // narcs, ent: arcs and frontier entries expanded
+};
+
+// Per-workgroup counters of a record-based persistent kernel.
+struct RecCounters {
+    unsigned long long levels = 0, batches = 0, disc = 0;
+    unsigned long long ticks[5] = {0, 0, 0, 0, 0};  // set-up, expand, cut, build, reset (100 MHz)
+};
+
+// One whole batch b (sources order[b W .. b W + W)) of graph G on the node
+// records of slot P: level 0, then per level the expansion over the frontier,
+// the counters of the level reached, the cut step and the build of the live
+// bits, until no source is live; then the marks of every node the batch
+// reached are reset, so the slot is all zero again.  degs: out-degrees from
+// the graph (records shared by several graphs) or null (from the records'
+// meta words).  Block-uniform call.
+template <int WW, int B>
+__device__ void record_batch(const DevGraph& G, const int32_t* order, int W, uint32_t b, const SlotPtrs& P,
+                             const TopKDev& T, QStats* st, const DeferList* D, const uint32_t* degs,
+                             RecLds<WW, B>& R, uint32_t& stamp, RecCounters& K) {
+    using Lo = Layout<WW>;
+    const int tid = threadIdx.x;
+    ++K.batches;
+    const uint64_t tb = __builtin_amdgcn_s_memrealtime();
+    init_batch<WW>(G, order, G.n, b, W, P, R.S, &R.flen, &R.arcs);
+    if (tid == 0) R.clen = R.flen;
+    uint32_t live = cut_step<WW>(T, R.S, W, 0, false, nullptr, nullptr, false, true, st, R.act, R.CL, D);
+    uint32_t flen = R.flen, d = 0;
+    uint64_t tp = __builtin_amdgcn_s_memrealtime();
+    K.ticks[0] += tp - tb;
+    while (live) {
+        ++stamp;
+        if (tid < kBlk) {
+            R.cg[tid] = 0;
+            R.ct[tid] = 0;
+        }
+        if (tid == 0) R.nlen = 0;
+        __syncthreads();
+        for (uint32_t e0 = 0; e0 < flen; e0 += B)
+            expand_entries<WW, B, 1>(G, P, P.qa, e0, min(flen, e0 + B), R.act, P.qb, &R.nlen, stamp, R.LE, &R.narcs,
+                                     &R.ent);
+        __syncthreads();
+        const uint32_t nlen = R.nlen;
+        count_level<WW, B>(P, P.qb, nlen, R.cg, R.ct, degs);
+        __syncthreads();
+        K.disc += nlen;
+        uint64_t tq = __builtin_amdgcn_s_memrealtime();
+        K.ticks[1] += tq - tp;
+        tp = tq;
+        ++d;
+        ++K.levels;
+        live = cut_step<WW>(T, R.S, W, d, true, R.cg, R.ct, false, true, st, R.act, R.CL, D);
+        tq = __builtin_amdgcn_s_memrealtime();
+        K.ticks[2] += tq - tp;
+        tp = tq;
+        clear_cur<WW>(P, P.qa, flen, 0, B);
+        if (tid == 0) R.flen = 0;
+        __syncthreads();
+        build_level<WW>(P, P.qb, nlen, 0, B, R.act, live != 0, P.qa, &R.flen, &R.clen, &R.arcs);
+        __syncthreads();
+        flen = R.flen;
+        tq = __builtin_amdgcn_s_memrealtime();
+        K.ticks[3] += tq - tp;
+        tp = tq;
+    }
+    // reset seen and cur of every node this batch reached
+    const uint32_t nc = R.clen;
+    for (uint32_t i = tid; i < nc; i += B) {
+        uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
+#pragma unroll
+        for (int j = 0; j < WW; ++j) {
+            rec[j] = 0;
+            rec[Lo::CUR + j] = 0;
+        }
+    }
+    __syncthreads();
+    K.ticks[4] += __builtin_amdgcn_s_memrealtime() - tp;
+}
+
 // Persistent: every workgroup owns one slot and runs whole batches, pulling
 // batch indices from a device counter, with every level inside the workgroup.
 // B threads per workgroup (kBatchBlk): a level's arcs are spread over all of
@@ -1149,14 +1242,8 @@ __global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order,
                                                  uint32_t* next_batch, uint32_t chunk, SlotPtrs base,
                                                  uint32_t* slot_stamp, TopKDev T, QStats* st, DeferList D) {
     using Lo = Layout<WW>;
-    __shared__ LdsExpand<WW, B> LE;
-    __shared__ SrcState S[kBlk];
-    __shared__ uint32_t cg[kBlk];
-    __shared__ unsigned long long ct[kBlk];
-    __shared__ CutLds CL;
-    __shared__ uint32_t s_flen, s_nlen, s_clen, s_b, s_next, s_end;
-    __shared__ uint64_t s_act[4];
-    __shared__ unsigned long long s_arcs, s_narcs, s_ent;
+    __shared__ RecLds<WW, B> R;
+    __shared__ uint32_t s_b, s_next, s_end;
     const int tid = threadIdx.x;
     const size_t slot = blockIdx.x;
     SlotPtrs P;
@@ -1166,11 +1253,10 @@ __global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order,
     P.clr = base.clr + slot * (size_t)G.n;
     // first-touch stamps keep growing across queries (stamps are never cleared)
     uint32_t stamp = slot_stamp[slot];
-    unsigned long long levels = 0, batches = 0, disc = 0;
-    unsigned long long ticks[5] = {0, 0, 0, 0, 0};
+    RecCounters K;
     if (tid == 0) {
-        s_narcs = 0;
-        s_ent = 0;
+        R.narcs = 0;
+        R.ent = 0;
         s_next = s_end = 0;
     }
     for (;;) {
@@ -1187,71 +1273,247 @@ __global__ __launch_bounds__(B) void k_batched(DevGraph G, const int32_t* order,
         const uint32_t b = s_b;
         __syncthreads();
         if (b >= nbatches) break;
-        ++batches;
-        const uint64_t tb = __builtin_amdgcn_s_memrealtime();
-        init_batch<WW>(G, order, G.n, b, W, P, S, &s_flen, &s_arcs);
-        if (tid == 0) s_clen = s_flen;
-        uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, true, st, s_act, CL, &D);
-        uint32_t flen = s_flen, d = 0;
-        uint64_t tp = __builtin_amdgcn_s_memrealtime();
-        ticks[0] += tp - tb;
-        while (live) {
-            ++stamp;
-            if (tid < kBlk) {
-                cg[tid] = 0;
-                ct[tid] = 0;
+        record_batch<WW, B>(G, order, W, b, P, T, st, &D, nullptr, R, stamp, K);
+    }
+    if (tid == 0) {
+        atomicAdd(&st->levels, K.levels);
+        atomicAdd(&st->batches, K.batches);
+        atomicAdd(&st->discovered, K.disc);
+        if (R.narcs) atomicAdd(&st->node_arcs, R.narcs);
+        if (R.ent) atomicAdd(&st->frontier_entries, R.ent);
+        for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], K.ticks[i]);
+        slot_stamp[slot] = stamp;
+    }
+}
+
+// --------------------------------------------------------- job launches
+//
+// A job is one top-k query (a graph, its source order, k) of a launch that
+// runs the batches of many queries, on graphs of different sizes, in one
+// persistent kernel: the parallel loop of Algorithm 1 (Section 2.1) over the
+// sources of every query at once.  Each query keeps its own top-k list,
+// threshold records and statistics, so it returns what it returns alone.
+//
+// Every batch of every query has a place in one global batch sequence.  A
+// descriptor (JobDesc) covers a contiguous range of it: `count` batches of
+// one query, its local batches bofs .. bofs + count.  A query may have two
+// ranges (its seed batches early in the sequence, the rest later), which
+// share its state.  Workgroups claim global batches one at a time with a
+// compare-and-swap that never passes the published total, so every claimed
+// batch exists and is run; the total only grows (a serving queue appends
+// queries while the kernel runs).  Node records are shared by all queries:
+// they are sized for the largest graph and all zero at rest, degrees come
+// from each graph's own array.
+
+struct JobDesc {
+    DevGraph G;
+    const int32_t* order;
+    TopKDev T;
+    QStats* st;
+    unsigned long long start;  // first global batch of this range
+    uint32_t count;            // batches in the range (>= 1)
+    uint32_t bofs;             // local index of its first batch
+    uint32_t total;            // batches of the whole query
+    uint32_t seed;             // the query's first `seed` batches: the others wait (bounded) for them
+    uint32_t* ctr;             // device, 2 words: finished batches, finished seed batches
+    Rec* out;                  // host-visible copy of the finished list (k records), or null
+    unsigned long long* out_st;  // host-visible copy of the QStats words, or null
+    uint32_t* done;            // host-visible: count of results + 1 once the query is finished, or null
+};
+static_assert(sizeof(JobDesc) % 8 == 0, "descriptors are copied in 8-byte words");
+static_assert(offsetof(JobDesc, start) % 8 == 0 && offsetof(JobDesc, count) % 8 == 0,
+              "the range fields are read as 8-byte words");
+static_assert(sizeof(QStats) % 8 == 0, "statistics are copied in 8-byte words");
+
+struct JobLaunch {
+    const JobDesc* jobs;                  // descriptor table (device or pinned host memory)
+    uint32_t njobs;                       // entries of the table scanned for a batch
+    uint32_t idle_spins;                  // claim attempts with nothing claimable before a workgroup ends
+    const unsigned long long* published;  // batches published (monotone; device or pinned host memory)
+    const uint32_t* stop;                 // nonzero: end once nothing is claimable (may be null)
+    unsigned long long* claim;            // device: next global batch to hand out (kept across launches)
+    int W;
+    int32_t ncap;                         // nodes per slot (the largest graph)
+};
+
+constexpr uint32_t kSeedSpins = 1u << 17;  // bounded wait for a query's seed batches (~0.5 s)
+
+__device__ inline unsigned long long sys_ld64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline void sys_st64(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Pointer and size fields of a descriptor read from LDS into scalar
+// registers (the same in every lane), so that the level loops address the
+// graph as they do when it is a kernel argument.
+template <class Ptr>
+__device__ inline Ptr uni_ptr(Ptr p) {
+    return reinterpret_cast<Ptr>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+__device__ inline DevGraph uni_graph(const DevGraph& g) {
+    DevGraph o;
+    o.n = (int32_t)uni32((uint32_t)g.n);
+    o.m = (int64_t)uni64((uint64_t)g.m);
+    o.directed = (int32_t)uni32((uint32_t)g.directed);
+    o.rp = uni_ptr(g.rp);
+    o.col = uni_ptr(g.col);
+    o.irp = uni_ptr(g.irp);
+    o.icol = uni_ptr(g.icol);
+    o.deg = uni_ptr(g.deg);
+    o.adj = uni_ptr(g.adj);
+    o.x0 = uni_ptr(g.x0);
+    o.x1 = uni_ptr(g.x1);
+    return o;
+}
+__device__ inline TopKDev uni_topk(const TopKDev& t) {
+    TopKDev o;
+    o.k = (int32_t)uni32((uint32_t)t.k);
+    o.cnt = uni_ptr(t.cnt);
+    o.lock = uni_ptr(t.lock);
+    o.seq = uni_ptr(t.seq);
+    o.list = uni_ptr(t.list);
+    o.ring = uni_ptr(t.ring);
+    o.all_f = uni_ptr(t.all_f);
+    o.all_r = uni_ptr(t.all_r);
+    o.footnote = (int32_t)uni32((uint32_t)t.footnote);
+    return o;
+}
+
+template <int WW, int B>
+__global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t* slot_stamp) {
+    using Lo = Layout<WW>;
+    __shared__ RecLds<WW, B> R;
+    __shared__ JobDesc J;
+    __shared__ unsigned long long s_c;
+    __shared__ int32_t s_slot;
+    const int tid = threadIdx.x;
+    const size_t slot = blockIdx.x;
+    SlotPtrs P;
+    P.ns = base.ns + slot * (size_t)L.ncap * Lo::SW;
+    P.qa = base.qa + slot * (size_t)L.ncap;
+    P.qb = base.qb + slot * (size_t)L.ncap;
+    P.clr = base.clr + slot * (size_t)L.ncap;
+    uint32_t stamp = slot_stamp[slot];
+    unsigned long long jstart = ~0ull, jend = 0;  // range of the descriptor held in J
+    for (;;) {
+        if (tid == 0) {
+            // claim the next published batch, or give up after idle_spins
+            // attempts that found nothing (or at once when told to stop)
+            unsigned long long got = ~0ull;
+            uint32_t spin = 0;
+            for (;;) {
+                const unsigned long long pub = __hip_atomic_load(L.published, __ATOMIC_ACQUIRE,
+                                                                 __HIP_MEMORY_SCOPE_SYSTEM);
+                unsigned long long c = __hip_atomic_load(L.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (c < pub) {
+                    // a failed exchange means another workgroup claimed c
+                    if (__hip_atomic_compare_exchange_strong(L.claim, &c, c + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        got = c;
+                        break;
+                    }
+                    continue;
+                }
+                if (L.stop && __hip_atomic_load(L.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) break;
+                if (spin++ >= L.idle_spins) break;
+                __builtin_amdgcn_s_sleep(127);
             }
-            if (tid == 0) s_nlen = 0;
-            __syncthreads();
-            for (uint32_t e0 = 0; e0 < flen; e0 += B)
-                expand_entries<WW, B, 1>(G, P, P.qa, e0, min(flen, e0 + B), s_act, P.qb, &s_nlen, stamp, LE, &s_narcs,
-                                      &s_ent);
-            __syncthreads();
-            const uint32_t nlen = s_nlen;
-            count_level<WW, B>(P, P.qb, nlen, cg, ct);
-            __syncthreads();
-            disc += nlen;
-            uint64_t tq = __builtin_amdgcn_s_memrealtime();
-            ticks[1] += tq - tp;
-            tp = tq;
-            ++d;
-            ++levels;
-            live = cut_step<WW>(T, S, W, d, true, cg, ct, false, true, st, s_act, CL, &D);
-            tq = __builtin_amdgcn_s_memrealtime();
-            ticks[2] += tq - tp;
-            tp = tq;
-            clear_cur<WW>(P, P.qa, flen, 0, B);
-            if (tid == 0) s_flen = 0;
-            __syncthreads();
-            build_level<WW>(P, P.qb, nlen, 0, B, s_act, live != 0, P.qa, &s_flen, &s_clen, &s_arcs);
-            __syncthreads();
-            flen = s_flen;
-            tq = __builtin_amdgcn_s_memrealtime();
-            ticks[3] += tq - tp;
-            tp = tq;
+            s_c = got;
+            s_slot = -1;
         }
-        // reset seen and cur of every node this batch reached
-        const uint32_t nc = s_clen;
-        for (uint32_t i = tid; i < nc; i += B) {
-            uint64_t* rec = &P.ns[(size_t)P.clr[i] * Lo::SW];
-#pragma unroll
-            for (int j = 0; j < WW; ++j) {
-                rec[j] = 0;
-                rec[Lo::CUR + j] = 0;
+        __syncthreads();
+        const unsigned long long c = uni64(s_c);
+        if (c == ~0ull) break;
+        if (c < jstart || c >= jend) {
+            // the descriptor whose range holds c (exactly one: ranges do not
+            // overlap, and the range of a claimed batch stays in the table
+            // until its query has finished)
+            for (uint32_t i = tid; i < L.njobs; i += B) {
+                const JobDesc* jd = &L.jobs[i];
+                const unsigned long long st0 = sys_ld64(&jd->start);
+                const unsigned long long cw = sys_ld64(reinterpret_cast<const unsigned long long*>(&jd->count));
+                const unsigned long long cnt = cw & 0xFFFFFFFFull;
+                if (st0 <= c && c < st0 + cnt) s_slot = (int32_t)i;
+            }
+            __syncthreads();
+            const int32_t js = (int32_t)uni32((uint32_t)s_slot);
+            if (js < 0) break;  // cannot happen for a published batch; end rather than guess
+            const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&L.jobs[js]);
+            unsigned long long* dst = reinterpret_cast<unsigned long long*>(&J);
+            for (int w = tid; w < (int)(sizeof(JobDesc) / 8); w += B) dst[w] = sys_ld64(&src[w]);
+            __syncthreads();
+            jstart = uni64(J.start);
+            jend = jstart + uni32(J.count);
+        }
+        const uint32_t b = uni32(J.bofs) + (uint32_t)(c - jstart);
+        const uint32_t seed = uni32(J.seed), total = uni32(J.total);
+        uint32_t* ctr = uni_ptr(J.ctr);
+        const TopKDev T = uni_topk(J.T);
+        QStats* st = uni_ptr(J.st);
+        const DevGraph G = uni_graph(J.G);
+        const int32_t* order = uni_ptr(J.order);
+        if (b >= seed && tid == 0) {
+            // a later batch waits (bounded) for the seed batches of its query,
+            // so that it starts with a k-th best record to cut against
+            for (uint32_t sp = 0; sp < kSeedSpins; ++sp) {
+                if (__hip_atomic_load(T.seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                if (__hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= seed) break;
+                __builtin_amdgcn_s_sleep(127);
+            }
+        }
+        if (tid == 0) {
+            R.narcs = 0;
+            R.ent = 0;
+        }
+        __syncthreads();
+        RecCounters K;
+        record_batch<WW, B>(G, order, L.W, b, P, T, st, nullptr, G.deg, R, stamp, K);
+        if (tid == 0) {
+            atomicAdd(&st->levels, K.levels);
+            atomicAdd(&st->batches, K.batches);
+            atomicAdd(&st->discovered, K.disc);
+            if (R.narcs) atomicAdd(&st->node_arcs, R.narcs);
+            if (R.ent) atomicAdd(&st->frontier_entries, R.ent);
+            for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], K.ticks[i]);
+            if (b < seed) __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t f = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (f + 1 == total) {
+                // the query's last batch: every other batch's list updates and
+                // statistics happen before its increment, which this one read
+                const int32_t cnt = ld32(T.cnt);
+                Rec* out = uni_ptr(J.out);
+                if (out) {
+                    for (int32_t i = 0; i < cnt; ++i) {
+                        unsigned long long* o = reinterpret_cast<unsigned long long*>(&out[i]);
+                        const uint64_t* q = reinterpret_cast<const uint64_t*>(&T.list[i]);
+                        for (int w = 0; w < 4; ++w) sys_st64(&o[w], ld64(&q[w]));
+                    }
+                }
+                if (J.out_st) {
+                    const uint64_t* q = reinterpret_cast<const uint64_t*>(st);
+                    unsigned long long* os = uni_ptr(J.out_st);
+                    for (int w = 0; w < (int)(sizeof(QStats) / 8); ++w) sys_st64(&os[w], ld64(&q[w]));
+                }
+                // the counters are ready for the next query that uses them
+                __hip_atomic_store(&ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t* done = uni_ptr(J.done);
+                if (done) __hip_atomic_store(done, (uint32_t)cnt + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
         __syncthreads();
-        ticks[4] += __builtin_amdgcn_s_memrealtime() - tp;
     }
-    if (tid == 0) {
-        atomicAdd(&st->levels, levels);
-        atomicAdd(&st->batches, batches);
-        atomicAdd(&st->discovered, disc);
-        if (s_narcs) atomicAdd(&st->node_arcs, s_narcs);
-        if (s_ent) atomicAdd(&st->frontier_entries, s_ent);
-        for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], ticks[i]);
-        slot_stamp[slot] = stamp;
-    }
+    if (tid == 0) slot_stamp[slot] = stamp;
+}
+
+// Zero `words` 8-byte words (the per-query state of a captured job launch:
+// list headers, statistics and counters, so that every replay starts clean;
+// a kernel rather than a memset node, which is what the capture records).
+__global__ void k_zero_words(unsigned long long* p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // ------------------------------------------- LDS-resident batched kernel
@@ -2630,5 +2892,296 @@ bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint
                           hipStream_t s) {
     return run_query(g, 0, o, nullptr, nullptr, nullptr, nullptr, st, farness, reach, s, false);
 }
+
+// ------------------------------------------------ many graphs, one launch
+
+namespace {
+
+// Per-query state of a job launch, one block per query in one buffer that a
+// single fill kernel clears before every run: list header (count, lock,
+// sequence), k list records, statistics, the two job counters.
+constexpr size_t kHdr = 64;
+size_t query_state_bytes(int32_t kk) {
+    const size_t b = kHdr + sizeof(Rec) * (size_t)kk + sizeof(QStats) + 16;
+    return (b + 255) & ~(size_t)255;
+}
+
+// bc_stats of one query of a job launch (every batch ran in the persistent kernel).
+void multi_stats(const QStats& h, double preprocess_ms, double query_ms, double launch_ms, bc_stats* out) {
+    const uint32_t sz = out->size;
+    bc_stats o2;
+    std::memset(&o2, 0, sizeof(o2));
+    o2.size = sizeof(bc_stats);
+    o2.batches = (uint32_t)h.batches;
+    o2.m_vis = h.m_vis;
+    o2.node_arcs = h.node_arcs;
+    o2.levels = h.levels;
+    o2.n_cut = h.n_cut;
+    o2.n_done = h.n_done;
+    o2.n_trivial = h.n_trivial;
+    o2.preprocess_ms = preprocess_ms;
+    o2.query_ms = query_ms;
+    o2.persistent_ms = launch_ms;
+    o2.frontier_entries = h.frontier_entries;
+    o2.discovered = h.discovered;
+    o2.persistent_arcs = h.node_arcs;
+    o2.persistent_entries = h.frontier_entries;
+    o2.persistent_discovered = h.discovered;
+    for (int i = 0; i < 5; ++i) o2.phase_ms[i] = (double)h.phase_ticks[i] / 1e5;
+    std::memcpy(out, &o2, std::min<size_t>(sz ? sz : sizeof(bc_stats), sizeof(bc_stats)));
+}
+
+}  // namespace
+
+}  // namespace bc
+
+// A prepared job launch over a fixed set of queries (graph, k): orders,
+// per-query state, the descriptor table and shared node-record slots, and
+// (when captured) the HIP graph that clears the state and runs the launch.
+struct bc_multi {
+    int W = 64;
+    int32_t count = 0;
+    std::vector<bc_graph*> graphs;
+    std::vector<int32_t> kk;            // min(k, n) per query
+    std::vector<int32_t> kreq;          // k per query (output offsets are sums of these)
+    std::vector<size_t> state_off;      // offset of each query's state block
+    hipStream_t s = nullptr;            // stream of the runs
+    hipStream_t cap = nullptr;          // private capture stream
+    bc::DevBuf orders, rings, state, jobs, ctl;
+    bc::DevBuf ns, qa, qb, clr, stamps;
+    int slots = 0;
+    int32_t ncap = 0;
+    size_t state_bytes = 0;
+    unsigned long long nbatch = 0;      // published batches of the launch
+    uint32_t njobs = 0;
+    bool captured = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~bc_multi() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (s) (void)hipStreamSynchronize(s);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace bc {
+
+namespace {
+
+template <int WW>
+void launch_jobs(bc_multi* p, hipStream_t st) {
+    const size_t words = p->state_bytes / 8;
+    k_zero_words<<<clamp_grid((int64_t)words, 1024), kBlk, 0, st>>>(p->state.as<unsigned long long>(), words);
+    k_zero_words<<<1, 64, 0, st>>>(p->ctl.as<unsigned long long>(), 1);  // the claim counter
+    JobLaunch L;
+    L.jobs = p->jobs.as<JobDesc>();
+    L.njobs = p->njobs;
+    L.idle_spins = 0;  // every batch is published before the launch: end when none is left
+    L.published = p->ctl.as<unsigned long long>() + 1;
+    L.stop = nullptr;
+    L.claim = p->ctl.as<unsigned long long>();
+    L.W = p->W;
+    L.ncap = p->ncap;
+    SlotPtrs base{p->ns.as<uint64_t>(), p->qa.as<int32_t>(), p->qb.as<int32_t>(), p->clr.as<int32_t>()};
+    k_jobs<WW, kBatchBlk><<<p->slots, kBatchBlk, 0, st>>>(L, base, p->stamps.as<uint32_t>());
+}
+
+void launch_jobs_any(bc_multi* p, hipStream_t st) {
+    if (p->W == 64) launch_jobs<1>(p, st);
+    else if (p->W == 128) launch_jobs<2>(p, st);
+    else launch_jobs<4>(p, st);
+}
+
+}  // namespace
+
+bc_status multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks, const bc_opts& o, hipStream_t s,
+                       bool capture, bc_multi** out) {
+    *out = nullptr;
+    const int W = o.width;
+    if (W != 64 && W != 128 && W != 256) {
+        set_error("width must be 64, 128 or 256 (got %d)", W);
+        return BC_EINVAL;
+    }
+    int dev = 0;
+    BC_HIP(hipGetDevice(&dev));
+    std::unique_ptr<bc_multi> p(new bc_multi());
+    p->W = W;
+    p->count = count;
+    p->s = s;
+    p->graphs.assign(graphs, graphs + count);
+    p->kk.resize((size_t)count);
+    p->kreq.assign(ks, ks + count);
+    p->state_off.resize((size_t)count);
+    const int SW = W == 64 ? Layout<1>::SW : (W == 128 ? Layout<2>::SW : Layout<4>::SW);
+    size_t ord_total = 0, ring_total = 0;
+    std::vector<size_t> ord_off((size_t)count), ring_off((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        bc_graph* g = graphs[i];
+        if (!g) { set_error("graph %d is NULL", i); return BC_EINVAL; }
+        if (g->device != dev) { set_error("graph %d lives on device %d, not the current %d", i, g->device, dev); return BC_EINVAL; }
+        if (ks[i] <= 0) { set_error("k of query %d must be positive (got %d)", i, ks[i]); return BC_EINVAL; }
+        const int32_t n = g->dg.n;
+        p->kk[(size_t)i] = std::min(ks[i], n);
+        p->ncap = std::max(p->ncap, n);
+        p->state_off[(size_t)i] = p->state_bytes;
+        p->state_bytes += query_state_bytes(p->kk[(size_t)i]);
+        ord_off[(size_t)i] = ord_total;
+        ring_off[(size_t)i] = ring_total;
+        ord_total += (size_t)n;
+        ring_total += (size_t)n + 1;
+    }
+    if (p->state_bytes == 0) p->state_bytes = 256;
+    BC_TRY(p->orders.alloc_on(sizeof(int32_t) * std::max<size_t>(ord_total, 1), s));
+    BC_TRY(p->rings.alloc_on(sizeof(ThRec) * std::max<size_t>(ring_total, 1), s));
+    BC_TRY(p->state.alloc_on(p->state_bytes, s));
+    BC_TRY(p->ctl.alloc_on(64, s));
+    BC_HIP(hipMemsetAsync(p->state.p, 0, p->state_bytes, s));
+    BC_HIP(hipMemsetAsync(p->ctl.p, 0, 64, s));
+    // source orders (each graph's own rule, as bc_topk in batched mode)
+    bc_opts ob = o;
+    ob.mode = BC_MODE_BATCHED;
+    ob.nfirst = 0;
+    ob.first = nullptr;
+    for (int32_t i = 0; i < count; ++i)
+        if (p->kk[(size_t)i] > 0)
+            BC_TRY(build_order(graphs[i], ob, p->kk[(size_t)i], p->orders.as<int32_t>() + ord_off[(size_t)i], s));
+    // descriptors: the seed batches of every query first, then the rest of
+    // each query, the most arcs first (the longest work starts earliest)
+    std::vector<JobDesc> jd;
+    std::vector<int32_t> rest;
+    unsigned long long pos = 0;
+    char* sb = p->state.as<char>();
+    auto fill = [&](int32_t i, uint32_t bofs, uint32_t cnt) {
+        bc_graph* g = graphs[i];
+        const int32_t kq = p->kk[(size_t)i];
+        const uint32_t nb = (uint32_t)((g->dg.n + W - 1) / W);
+        char* q = sb + p->state_off[(size_t)i];
+        JobDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.G = g->dg;
+        d.order = p->orders.as<int32_t>() + ord_off[(size_t)i];
+        d.T.k = kq;
+        d.T.cnt = (int32_t*)q;
+        d.T.lock = (uint32_t*)(q + 4);
+        d.T.seq = (uint32_t*)(q + 8);
+        d.T.list = (Rec*)(q + kHdr);
+        d.T.ring = p->rings.as<ThRec>() + ring_off[(size_t)i];
+        d.T.all_f = nullptr;
+        d.T.all_r = nullptr;
+        d.T.footnote = (!g->dg.directed && (o.bounds & BC_BOUND_FOOTNOTE)) ? 1 : 0;
+        d.st = (QStats*)(q + kHdr + sizeof(Rec) * (size_t)kq);
+        d.ctr = (uint32_t*)(q + kHdr + sizeof(Rec) * (size_t)kq + sizeof(QStats));
+        d.start = pos;
+        d.count = cnt;
+        d.bofs = bofs;
+        d.total = nb;
+        d.seed = std::min<uint32_t>(nb, (uint32_t)((kq + W - 1) / W));
+        d.out = nullptr;
+        d.out_st = nullptr;
+        d.done = nullptr;
+        jd.push_back(d);
+        pos += cnt;
+    };
+    for (int32_t i = 0; i < count; ++i) {
+        if (p->kk[(size_t)i] <= 0) continue;
+        const uint32_t nb = (uint32_t)((graphs[i]->dg.n + W - 1) / W);
+        const uint32_t sd = std::min<uint32_t>(nb, (uint32_t)((p->kk[(size_t)i] + W - 1) / W));
+        fill(i, 0, sd);
+        if (sd < nb) rest.push_back(i);
+    }
+    std::stable_sort(rest.begin(), rest.end(), [&](int32_t a, int32_t b) { return graphs[a]->dg.m > graphs[b]->dg.m; });
+    for (int32_t i : rest) {
+        const uint32_t nb = (uint32_t)((graphs[i]->dg.n + W - 1) / W);
+        const uint32_t sd = std::min<uint32_t>(nb, (uint32_t)((p->kk[(size_t)i] + W - 1) / W));
+        fill(i, sd, nb - sd);
+    }
+    p->nbatch = pos;
+    p->njobs = (uint32_t)jd.size();
+    BC_TRY(p->jobs.alloc_on(sizeof(JobDesc) * std::max<size_t>(jd.size(), 1), s));
+    if (!jd.empty())
+        BC_HIP(hipMemcpyAsync(p->jobs.p, jd.data(), sizeof(JobDesc) * jd.size(), hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(p->ctl.as<unsigned long long>() + 1, &p->nbatch, sizeof(unsigned long long),
+                          hipMemcpyHostToDevice, s));
+    // shared node-record slots for the largest graph, all zero at rest
+    int slots = o.slots > 0 ? o.slots : device_cus();
+    if ((unsigned long long)slots > p->nbatch) slots = (int)std::max<unsigned long long>(p->nbatch, 1);
+    const size_t N = (size_t)std::max(p->ncap, 1);
+    const size_t per_slot = N * (8 * (size_t)SW + 12);
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) == hipSuccess) {
+        const size_t capn = (size_t)(0.45 * (double)freeb) / per_slot;
+        if ((size_t)slots > capn) slots = (int)std::max<size_t>(capn, 1);
+    }
+    p->slots = slots;
+    BC_TRY(p->ns.alloc_on(sizeof(uint64_t) * N * SW * (size_t)slots, s));
+    BC_TRY(p->qa.alloc_on(sizeof(int32_t) * N * (size_t)slots, s));
+    BC_TRY(p->qb.alloc_on(sizeof(int32_t) * N * (size_t)slots, s));
+    BC_TRY(p->clr.alloc_on(sizeof(int32_t) * N * (size_t)slots, s));
+    BC_TRY(p->stamps.alloc_on(sizeof(uint32_t) * (size_t)slots, s));
+    BC_HIP(hipMemsetAsync(p->ns.p, 0, sizeof(uint64_t) * N * SW * (size_t)slots, s));
+    BC_HIP(hipMemsetAsync(p->stamps.p, 0, sizeof(uint32_t) * (size_t)slots, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (capture && p->nbatch > 0) {
+        BC_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));  // default priority
+        BC_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+        launch_jobs_any(p.get(), p->cap);
+        const hipError_t ce = hipStreamEndCapture(p->cap, &p->graph);
+        BC_HIP(ce);
+        BC_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+        p->captured = true;
+    }
+    *out = p.release();
+    return BC_OK;
+}
+
+bc_status multi_run(bc_multi* p, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts, bc_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = p->s;
+    double launch_ms = 0;
+    std::vector<char> hs(p->state_bytes);
+    if (p->nbatch > 0) {
+        EventPair ev;
+        BC_TRY(ev.create());
+        BC_HIP(hipEventRecord(ev.a, s));
+        if (p->captured) BC_HIP(hipGraphLaunch(p->exec, s));
+        else launch_jobs_any(p, s);
+        BC_HIP(hipEventRecord(ev.b, s));
+        BC_HIP(hipGetLastError());
+        BC_TRY(ev.ms(&launch_ms));
+        BC_HIP(hipMemcpyAsync(hs.data(), p->state.p, p->state_bytes, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+    }
+    const double qms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    size_t off = 0;
+    for (int32_t i = 0; i < p->count; ++i) {
+        const int32_t kq = p->kk[(size_t)i];
+        const char* q = hs.data() + p->state_off[(size_t)i];
+        int32_t cnt = 0;
+        QStats h;
+        std::memset(&h, 0, sizeof(h));
+        if (kq > 0) {
+            std::memcpy(&cnt, q, sizeof(int32_t));
+            std::memcpy(&h, q + kHdr + sizeof(Rec) * (size_t)kq, sizeof(QStats));
+            if (cnt != kq) {
+                set_error("internal: query %d top-k list holds %d of %d entries", i, cnt, kq);
+                return BC_EDEVICE;
+            }
+            for (int32_t j = 0; j < cnt; ++j) {
+                Rec r;
+                std::memcpy(&r, q + kHdr + sizeof(Rec) * (size_t)j, sizeof(Rec));
+                ids[off + (size_t)j] = (int32_t)(uint32_t)(r.idr & 0xFFFFFFFFu);
+                reach[off + (size_t)j] = (uint32_t)(r.idr >> 32);
+                farness[off + (size_t)j] = r.f;
+            }
+        }
+        counts[i] = cnt;
+        if (stats) multi_stats(h, p->graphs[(size_t)i]->preprocess_ms, qms, launch_ms, &stats[i]);
+        off += (size_t)p->kreq[(size_t)i];
+    }
+    return BC_OK;
+}
+
+void multi_destroy(bc_multi* p) { delete p; }
 
 }  // namespace bc

@@ -382,6 +382,21 @@ typedef struct bc_server_opts {
     int32_t device;         /* HIP device (-1: the current one)                          */
     uint64_t budget_bytes;  /* device memory for resident graphs and running requests
                                (0: 45 % of the free memory at creation)                 */
+    int32_t queue;          /* 1: continuous batching through a device-visible queue:
+                               lanes only prepare requests (upload, order, lists) and
+                               append them to a queue in pinned host memory that one
+                               persistent kernel drains while it runs, its workgroups
+                               taking the next source batch of whichever request waits,
+                               so requests that arrive while others run start as soon as
+                               a workgroup is free and run beside them.  Batched requests
+                               with k <= 256 on graphs no larger than the largest one
+                               registered before the first request use it; others run as
+                               whole-request launches on the lanes.  0 (default): lanes only */
+    int32_t queue_width;    /* W of the queue kernel (64, 128 or 256; default 64): every
+                               queued request uses it (the width changes the speed only) */
+    int32_t queue_slots;    /* workgroups of the queue kernel (0: one per compute unit);
+                               their node records, sized for the largest registered graph,
+                               are reserved in the budget while the server lives          */
 } bc_server_opts;
 
 typedef struct bc_request_info {

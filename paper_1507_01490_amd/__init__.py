@@ -88,7 +88,8 @@ class TuneReport(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("lanes", ctypes.c_int32), ("slots", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64)]
+                ("device", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64), ("queue", ctypes.c_int32),
+                ("queue_width", ctypes.c_int32), ("queue_slots", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -503,11 +504,15 @@ class Server:
     """Serving queue over registered graphs (bc_server_*): submit returns a
     ticket at once; poll returns None until the result is ready."""
 
-    def __init__(self, lanes: int = 4, slots: int = 64, budget_bytes: int = 0, device: int = -1):
+    def __init__(self, lanes: int = 4, slots: int = 64, budget_bytes: int = 0, device: int = -1, queue: bool = False,
+                 queue_width: int = 64, queue_slots: int = 0):
+        """queue=True: continuous batching through the device-visible queue of
+        one running persistent kernel (bc_server_opts.queue)."""
         lib = load_library()
         o = ServerOpts()
         lib.bc_server_opts_default(ctypes.byref(o))
         o.lanes, o.slots, o.budget_bytes, o.device = int(lanes), int(slots), int(budget_bytes), int(device)
+        o.queue, o.queue_width, o.queue_slots = int(bool(queue)), int(queue_width), int(queue_slots)
         h = ctypes.c_void_p()
         _check(lib.bc_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

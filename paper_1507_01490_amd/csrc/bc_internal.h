@@ -237,4 +237,27 @@ bc_status multi_run(bc_multi* p, int32_t* ids, uint64_t* farness, uint32_t* reac
                     bc_stats* stats);
 void multi_destroy(bc_multi* p);
 
+// Serving queue drained by a running persistent job kernel (topk.hip).
+// devq_create: ring, result areas and flags in pinned host memory, node-record
+// slots for graphs of up to ncap nodes (*device_bytes: their size).
+// devq_submit: build the request's order on `prep`, write its descriptor and
+// publish it (blocks while every ring slot is in flight); the kernel is
+// launched when none is running.  devq_done polls the request's flag;
+// devq_collect copies its results; devq_release frees its slot and memory;
+// devq_pump relaunches the kernel when work waits and it has ended.
+struct DevQueue;
+struct QueueJob;
+constexpr int kQueueMaxK = 256;  // largest k a queued request may ask for
+bc_status devq_create(int W, int32_t ncap, int slots, DevQueue** out, uint64_t* device_bytes);
+void devq_destroy(DevQueue* q);
+int devq_width(const DevQueue* q);
+int32_t devq_ncap(const DevQueue* q);
+bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o, hipStream_t prep, QueueJob** out);
+bool devq_done(DevQueue* q, const QueueJob* j);
+bc_status devq_collect(DevQueue* q, QueueJob* j, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count,
+                       bc_stats* st, double query_ms);
+void devq_release(DevQueue* q, QueueJob* j);
+void devq_free(QueueJob* j);  // memory of an entry whose queue is gone
+bc_status devq_pump(DevQueue* q);
+
 }  // namespace bc

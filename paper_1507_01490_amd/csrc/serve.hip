@@ -11,6 +11,16 @@
 // once.  Each request's persistent kernel is limited to `slots` workgroups,
 // so that L requests fit side by side on the compute units.
 //
+// With the device queue (bc_server_opts.queue = 1) a lane only prepares a
+// request (upload, source order, its list and threshold records) and hands
+// it to a device-visible queue that one persistent kernel drains while it
+// runs: the kernel's workgroups claim the next source batch of whichever
+// queued request it belongs to, so requests that arrive while others are on
+// the GPU are admitted as slots free up and their batches run beside the
+// others' (continuous batching).  A reaper thread collects finished requests
+// from their flags in pinned host memory and relaunches the kernel when it
+// has ended with work waiting.
+//
 // The top-k of a request is the same whatever runs beside it: every query
 // keeps its own list, threshold records and working memory (a stale or
 // private threshold never changes the result, Section 2.1).
@@ -97,9 +107,23 @@ struct SrvReq {
     bc_stats st{};
     double t_submit = 0, t_start = 0, t_finish = 0;
     uint64_t query_bytes = 0, upload_bytes = 0;
+    uint64_t lane_bytes = 0, queue_bytes = 0;  // working memory as a whole-request launch / in the queue
+    bool to_queue = false;                     // admitted for the device queue
     int lane = -1;
     bool uploaded = false;
+    QueueJob* qjob = nullptr;  // in the device queue (finished by the reaper)
 };
+
+// Working memory of a request in the device queue: its order, threshold
+// records, list and statistics, the order's sort temporaries and (learned
+// orders) the features and scores.  The node-record slots belong to the queue.
+uint64_t queue_request_bytes(int32_t n, int32_t k, const bc_opts& o) {
+    const uint64_t N = (uint64_t)(n > 0 ? n : 0), kk = (uint64_t)(k > 0 ? k : 1);
+    uint64_t b = 4 * N + 24 * (N + 1) + 512 + 32 * kk + 24 * N;
+    if (o.order == BC_ORDER_LEARNED || o.order == BC_ORDER_LEARNED_GROUPED || o.order == BC_ORDER_LEARNED_LOCALITY)
+        b += 4 * N + 4 * BC_MLP_PARAMS + 16 * N;
+    return b;
+}
 
 }  // namespace
 }  // namespace bc
@@ -121,6 +145,17 @@ struct bc_server {
     std::vector<hipStream_t> streams;
     std::vector<std::thread> workers;
     std::chrono::steady_clock::time_point t0;
+    // device queue mode
+    bool queue_mode = false;
+    int queue_width = 64;
+    int queue_slots = 0;
+    bc::DevQueue* q = nullptr;
+    bool q_failed = false;
+    uint64_t q_bytes = 0;
+    std::vector<bc::SrvReq*> inflight;  // requests in the device queue
+    std::vector<bc::QueueJob*> orphans; // queue entries given up at shutdown, freed after the kernel ends
+    bool reaper_stop = false;
+    std::thread reaper;
 
     double now_ms() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -154,11 +189,15 @@ void evict_for(bc_server* S, uint64_t need, const SrvGraph* keep) {
 // Decide on the head of the queue (caller holds the lock).  Returns the
 // request to start, or null.  A head that cannot fit even with every lane
 // idle and every other graph evicted fails with BC_ENOMEM.
+bool queue_eligible(bc_server* S, const SrvReq* r, const SrvGraph* G);
+
 SrvReq* admit_head(bc_server* S) {
     while (!S->queue.empty()) {
         SrvReq* r = S->reqs.at(S->queue.front()).get();
         SrvGraph* G = S->graphs[(size_t)r->gid].get();
         if (G->loading) return nullptr;  // another lane is uploading it
+        r->to_queue = queue_eligible(S, r, G);
+        r->query_bytes = r->to_queue ? r->queue_bytes : r->lane_bytes;
         const uint64_t gneed = G->g ? 0 : G->resident_bytes + r->upload_bytes;
         const uint64_t need = r->query_bytes + gneed;
         if (S->used + need > S->budget) evict_for(S, need, G);
@@ -178,6 +217,10 @@ SrvReq* admit_head(bc_server* S) {
     }
     return nullptr;
 }
+
+void finish_request(bc_server* S, SrvReq* r, SrvGraph* G, bc_status rs, const std::string& err);
+bool queue_eligible(bc_server* S, const SrvReq* r, const SrvGraph* G);
+bc_status ensure_queue(bc_server* S);
 
 void lane_main(bc_server* S, int lane) {
     (void)hipSetDevice(S->device);
@@ -201,6 +244,7 @@ void lane_main(bc_server* S, int lane) {
         r->uploaded = upload;
         r->t_start = S->now_ms();
         ++S->running;
+        const bool to_queue = r->to_queue;
         lk.unlock();
 
         bc_status rs = BC_OK;
@@ -236,35 +280,169 @@ void lane_main(bc_server* S, int lane) {
             r->reach.assign((size_t)std::max(r->k, 1), 0);
             std::memset(&r->st, 0, sizeof(r->st));
             r->st.size = sizeof(bc_stats);
-            try {
-                rs = run_topk(G->g, r->k, r->o, r->ids.data(), r->far.data(), r->reach.data(), &r->count, &r->st, st,
-                              true);
-            } catch (...) {
-                set_error("internal error");
-                rs = BC_EDEVICE;
+            if (to_queue) {
+                QueueJob* j = nullptr;
+                try {
+                    rs = ensure_queue(S);
+                    if (rs == BC_OK) rs = devq_submit(S->q, G->g, r->k, r->o, st, &j);
+                } catch (...) {
+                    set_error("internal error");
+                    rs = BC_EDEVICE;
+                }
+                if (rs == BC_OK) {
+                    // the reaper finishes it when the kernel raises its flag
+                    lk.lock();
+                    r->qjob = j;
+                    S->inflight.push_back(r);
+                    S->cv.notify_all();
+                    continue;
+                }
+                err = bc_last_error();
+            } else {
+                try {
+                    rs = run_topk(G->g, r->k, r->o, r->ids.data(), r->far.data(), r->reach.data(), &r->count, &r->st,
+                                  st, true);
+                } catch (...) {
+                    set_error("internal error");
+                    rs = BC_EDEVICE;
+                }
+                if (rs != BC_OK) err = bc_last_error();
             }
-            if (rs != BC_OK) err = bc_last_error();
         }
 
         lk.lock();
-        --S->running;
-        G->refs -= 1;
-        G->last_use = ++S->clock;
-        S->used -= r->query_bytes;
-        r->t_finish = S->now_ms();
-        r->status = rs;
-        r->err = err;
-        if (r->cancel) {
-            r->state = RQ_CANCELED;
-            ++S->canceled;
-        } else if (rs == BC_OK) {
-            r->state = RQ_DONE;
-            ++S->completed;
-        } else {
-            r->state = RQ_FAILED;
-            ++S->failed;
+        finish_request(S, r, G, rs, err);
+    }
+}
+
+// Bookkeeping of a request that has ended (caller holds the lock).
+void finish_request(bc_server* S, SrvReq* r, SrvGraph* G, bc_status rs, const std::string& err) {
+    --S->running;
+    G->refs -= 1;
+    G->last_use = ++S->clock;
+    S->used -= r->query_bytes;
+    r->t_finish = S->now_ms();
+    r->status = rs;
+    r->err = err;
+    if (r->cancel) {
+        r->state = RQ_CANCELED;
+        ++S->canceled;
+    } else if (rs == BC_OK) {
+        r->state = RQ_DONE;
+        ++S->completed;
+    } else {
+        r->state = RQ_FAILED;
+        ++S->failed;
+    }
+    S->cv.notify_all();
+}
+
+// Whether a request goes to the device queue (caller holds the lock): batched
+// requests whose k and graph fit the queue's result areas and slots.
+bool queue_eligible(bc_server* S, const SrvReq* r, const SrvGraph* G) {
+    if (!S->queue_mode || S->q_failed || r->o.mode != BC_MODE_BATCHED || r->k > kQueueMaxK) return false;
+    if (S->q) return G->n <= devq_ncap(S->q);
+    return true;  // the queue is sized for the largest registered graph when it is made
+}
+
+// Make the device queue on first use: slots sized for the largest graph
+// registered so far.  Its memory is reserved in the budget for the server's
+// lifetime.
+bc_status ensure_queue(bc_server* S) {
+    static std::mutex make_mu;
+    std::lock_guard<std::mutex> mk(make_mu);
+    int32_t ncap = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->q) return BC_OK;
+        for (auto& G : S->graphs) ncap = std::max(ncap, G->n);
+    }
+    // at most half the budget for the queue's node records
+    const uint64_t SW = S->queue_width == 64 ? 4 : (S->queue_width == 128 ? 8 : 16);
+    const uint64_t per_slot = (uint64_t)std::max(ncap, 1) * (8 * SW + 12) + 4;
+    int slots = S->queue_slots;
+    if (slots <= 0) {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        slots = cus;
+    }
+    slots = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)slots, S->budget / 2 / per_slot));
+    DevQueue* q = nullptr;
+    uint64_t bytes = 0;
+    const bc_status rs = devq_create(S->queue_width, ncap, slots, &q, &bytes);
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (rs != BC_OK) {
+        S->q_failed = true;
+        return rs;
+    }
+    S->q = q;
+    S->q_bytes = bytes;
+    reserve(S, bytes);
+    return BC_OK;
+}
+
+// Reaper: finishes queued requests whose flag the kernel has raised, and
+// relaunches the kernel when it has ended with requests still waiting.
+void reaper_main(bc_server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    double stop_ms = -1.0;
+    for (;;) {
+        if (S->inflight.empty()) {
+            if (S->reaper_stop) return;
+            S->cv.wait_for(lk, std::chrono::milliseconds(20));
+            continue;
         }
-        S->cv.notify_all();
+        if (S->reaper_stop) {
+            // shutting down: give the queued requests a minute to finish, then
+            // fail them; their memory is freed only after the kernel has ended
+            if (stop_ms < 0) stop_ms = S->now_ms();
+            if (S->now_ms() - stop_ms > 60000.0) {
+                for (SrvReq* r : S->inflight) {
+                    S->orphans.push_back(r->qjob);
+                    r->qjob = nullptr;
+                    finish_request(S, r, S->graphs[(size_t)r->gid].get(), BC_EDEVICE,
+                                   "queued request did not finish before the server was destroyed");
+                }
+                S->inflight.clear();
+                return;
+            }
+        }
+        for (size_t i = 0; i < S->inflight.size();) {
+            SrvReq* r = S->inflight[i];
+            if (!devq_done(S->q, r->qjob)) {
+                ++i;
+                continue;
+            }
+            SrvGraph* G = S->graphs[(size_t)r->gid].get();
+            const double qms = S->now_ms() - r->t_start;
+            bc_status rs = devq_collect(S->q, r->qjob, r->ids.data(), r->far.data(), r->reach.data(), &r->count,
+                                        &r->st, qms);
+            const std::string err = rs == BC_OK ? std::string() : std::string(bc_last_error());
+            devq_release(S->q, r->qjob);
+            r->qjob = nullptr;
+            S->inflight[i] = S->inflight.back();
+            S->inflight.pop_back();
+            finish_request(S, r, G, rs, err);
+        }
+        if (!S->inflight.empty()) {
+            DevQueue* q = S->q;
+            lk.unlock();
+            const bc_status ps = devq_pump(q);
+            std::this_thread::sleep_for(std::chrono::microseconds(100));
+            lk.lock();
+            if (ps != BC_OK) {
+                // the kernel cannot be launched: fail what waits on it
+                const std::string err = bc_last_error();
+                for (SrvReq* r : S->inflight) {
+                    devq_release(S->q, r->qjob);
+                    r->qjob = nullptr;
+                    finish_request(S, r, S->graphs[(size_t)r->gid].get(), ps, err);
+                }
+                S->inflight.clear();
+            }
+        }
     }
 }
 
@@ -295,6 +473,9 @@ void bc_server_opts_default(bc_server_opts* o) {
     o->slots = 64;
     o->budget_bytes = 0;
     o->device = -1;
+    o->queue = 0;
+    o->queue_width = 64;
+    o->queue_slots = 0;
 }
 
 bc_status bc_footprint(int32_t n, int64_t m, uint32_t flags, int32_t k, const bc_opts* opts, int32_t slots,
@@ -328,6 +509,13 @@ bc_status bc_server_create(const bc_server_opts* opts, bc_server** out) {
     S->budget = o.budget_bytes > 0 ? o.budget_bytes : (uint64_t)(0.45 * (double)freeb);
     S->lanes = o.lanes;
     S->slots = o.slots;
+    S->queue_mode = o.queue != 0;
+    S->queue_width = o.queue_width;
+    S->queue_slots = o.queue_slots;
+    if (S->queue_mode && o.queue_width != 64 && o.queue_width != 128 && o.queue_width != 256) {
+        set_error("queue_width must be 64, 128 or 256");
+        return BC_EINVAL;
+    }
     S->t0 = std::chrono::steady_clock::now();
     for (int i = 0; i < S->lanes; ++i) {
         hipStream_t st = nullptr;
@@ -335,6 +523,7 @@ bc_status bc_server_create(const bc_server_opts* opts, bc_server** out) {
         S->streams.push_back(st);
     }
     for (int i = 0; i < S->lanes; ++i) S->workers.emplace_back(bc::lane_main, S.get(), i);
+    if (S->queue_mode) S->reaper = std::thread(bc::reaper_main, S.get());
     *out = S.release();
     return BC_OK;
     SRV_GUARD_END
@@ -355,6 +544,19 @@ bc_status bc_server_destroy(bc_server* S) {
         S->cv.notify_all();
     }
     for (auto& t : S->workers) t.join();
+    if (S->reaper.joinable()) {
+        // queued requests on the device finish first
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->reaper_stop = true;
+            S->cv.notify_all();
+        }
+        S->reaper.join();
+    }
+    if (S->q) bc::devq_destroy(S->q);  // the kernel has ended when this returns
+    S->q = nullptr;
+    for (bc::QueueJob* j : S->orphans) bc::devq_free(j);
+    S->orphans.clear();
     for (auto& G : S->graphs)
         if (G->g) (void)bc_graph_destroy(G->g);
     for (hipStream_t st : S->streams) {
@@ -429,6 +631,8 @@ bc_status bc_submit(bc_server* S, int32_t graph_id, int32_t k, const bc_opts* op
     bc::footprint(G->n, G->m, (G->flags & BC_DIRECTED) != 0, k, r->o, S->slots, &gb, &ub, &qb);
     if (r->o.mode == BC_MODE_BATCHED && r->o.slots <= 0) r->o.slots = S->slots;
     (void)gb;  // the graph's resident bytes were fixed when it was registered
+    r->lane_bytes = qb;
+    r->queue_bytes = bc::queue_request_bytes(G->n, k, r->o);
     r->query_bytes = qb;
     r->upload_bytes = ub;
     r->id = S->next_id++;

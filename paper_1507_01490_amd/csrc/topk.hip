@@ -34,6 +34,7 @@
 // the true k-th best, and a stale one only weakens the cut (the shared value
 // of the parallel loop, Section 2.1), so results never change.
 #include <chrono>
+#include <condition_variable>
 #include <cstddef>
 #include <cstring>
 
@@ -1337,6 +1338,7 @@ struct JobLaunch {
 };
 
 constexpr uint32_t kSeedSpins = 1u << 17;  // bounded wait for a query's seed batches (~0.5 s)
+constexpr int kQueueCap = 256;             // requests in flight in a serving queue (ring slots)
 
 __device__ inline unsigned long long sys_ld64(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1443,6 +1445,10 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&L.jobs[js]);
             unsigned long long* dst = reinterpret_cast<unsigned long long*>(&J);
             for (int w = tid; w < (int)(sizeof(JobDesc) / 8); w += B) dst[w] = sys_ld64(&src[w]);
+            // the query's graph, order and state were written by other
+            // streams, possibly while this launch ran: every wave drops what
+            // its caches may hold of them before it reads them
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __syncthreads();
             jstart = uni64(J.start);
             jend = jstart + uni32(J.count);
@@ -3183,5 +3189,277 @@ bc_status multi_run(bc_multi* p, int32_t* ids, uint64_t* farness, uint32_t* reac
 }
 
 void multi_destroy(bc_multi* p) { delete p; }
+
+// ------------------------------------------- serving queue of a running kernel
+//
+// A device-visible queue of top-k requests that a persistent job kernel
+// drains while it runs: the host writes a request's descriptor into a ring in
+// pinned host memory and raises the published batch total; workgroups that
+// finish a batch claim the next published one, whichever request it belongs
+// to, so a request that arrives while others are on the GPU starts as soon
+// as a workgroup is free, and its batches run beside theirs.  The last batch
+// of a request copies its list and statistics to the ring slot's result area
+// (pinned host memory) and raises its done flag; the host polls the flags.
+// The kernel ends after a bounded idle time with nothing to claim (or at
+// once when told to stop); the host launches it again when work is waiting.
+
+struct QueueJob {
+    int slot = -1;
+    int32_t kk = 0;
+    bc_graph* g = nullptr;
+    DevBuf order, ring, state;
+};
+
+struct DevQueue {
+    int W = 64;
+    int32_t ncap = 0;
+    int slots = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    bool launched = false;
+    char* host = nullptr;            // pinned: descriptors, results, statistics, flags, totals
+    JobDesc* ring = nullptr;
+    Rec* out = nullptr;
+    unsigned long long* out_st = nullptr;
+    uint32_t* done = nullptr;
+    unsigned long long* published = nullptr;
+    uint32_t* stop = nullptr;
+    char* dhost = nullptr;           // the same block as the device addresses it
+    DevBuf ctr, claim, ns, qa, qb, clr, stamps;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<char> busy;
+    unsigned long long total = 0;    // batches published so far
+    ~DevQueue() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (ev) (void)hipEventDestroy(ev);
+        if (host) (void)hipHostFree(host);
+        ns.release();
+        qa.release();
+        qb.release();
+        clr.release();
+        stamps.release();
+        ctr.release();
+        claim.release();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+constexpr uint32_t kQueueIdleSpins = 1000;  // ~3.4 ms with nothing to claim before the kernel ends
+
+size_t queue_host_bytes() {
+    return sizeof(JobDesc) * kQueueCap + sizeof(Rec) * (size_t)kQueueCap * kQueueMaxK +
+           sizeof(QStats) * kQueueCap + sizeof(uint32_t) * kQueueCap + 64;
+}
+
+template <int WW>
+void launch_queue(DevQueue* q) {
+    JobLaunch L;
+    L.jobs = reinterpret_cast<const JobDesc*>(q->dhost);
+    L.njobs = kQueueCap;
+    L.idle_spins = kQueueIdleSpins;
+    L.published = reinterpret_cast<const unsigned long long*>(q->dhost + ((char*)q->published - q->host));
+    L.stop = reinterpret_cast<const uint32_t*>(q->dhost + ((char*)q->stop - q->host));
+    L.claim = q->claim.as<unsigned long long>();
+    L.W = q->W;
+    L.ncap = q->ncap;
+    SlotPtrs base{q->ns.as<uint64_t>(), q->qa.as<int32_t>(), q->qb.as<int32_t>(), q->clr.as<int32_t>()};
+    k_jobs<WW, kBatchBlk><<<q->slots, kBatchBlk, 0, q->stream>>>(L, base, q->stamps.as<uint32_t>());
+}
+
+// Launch the kernel when work is published and no launch is running
+// (caller holds q->mu).
+bc_status pump_locked(DevQueue* q) {
+    if (q->launched) {
+        const hipError_t e = hipEventQuery(q->ev);
+        if (e == hipErrorNotReady) return BC_OK;
+        BC_HIP(e);
+        q->launched = false;
+    }
+    bool pending = false;
+    for (int i = 0; i < kQueueCap && !pending; ++i) pending = q->busy[(size_t)i] != 0;
+    if (!pending) return BC_OK;
+    if (q->W == 64) launch_queue<1>(q);
+    else if (q->W == 128) launch_queue<2>(q);
+    else launch_queue<4>(q);
+    BC_HIP(hipGetLastError());
+    BC_HIP(hipEventRecord(q->ev, q->stream));
+    q->launched = true;
+    return BC_OK;
+}
+
+}  // namespace
+
+bc_status devq_create(int W, int32_t ncap, int slots, DevQueue** out, uint64_t* device_bytes) {
+    *out = nullptr;
+    if (W != 64 && W != 128 && W != 256) {
+        set_error("queue width must be 64, 128 or 256 (got %d)", W);
+        return BC_EINVAL;
+    }
+    std::unique_ptr<DevQueue> q(new DevQueue());
+    q->W = W;
+    q->ncap = std::max(ncap, 1);
+    q->slots = slots > 0 ? slots : device_cus();
+    q->busy.assign(kQueueCap, 0);
+    BC_HIP(hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking));  // default priority
+    BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
+    const size_t hb = queue_host_bytes();
+    BC_HIP(hipHostMalloc((void**)&q->host, hb, hipHostMallocCoherent | hipHostMallocMapped));
+    std::memset(q->host, 0, hb);
+    char* h = q->host;
+    q->ring = reinterpret_cast<JobDesc*>(h);
+    h += sizeof(JobDesc) * kQueueCap;
+    q->out = reinterpret_cast<Rec*>(h);
+    h += sizeof(Rec) * (size_t)kQueueCap * kQueueMaxK;
+    q->out_st = reinterpret_cast<unsigned long long*>(h);
+    h += sizeof(QStats) * kQueueCap;
+    q->done = reinterpret_cast<uint32_t*>(h);
+    h += sizeof(uint32_t) * kQueueCap;
+    q->published = reinterpret_cast<unsigned long long*>(h);
+    q->stop = reinterpret_cast<uint32_t*>(h + 8);
+    void* dp = nullptr;
+    BC_HIP(hipHostGetDevicePointer(&dp, q->host, 0));
+    q->dhost = reinterpret_cast<char*>(dp);
+    const int SW = W == 64 ? Layout<1>::SW : (W == 128 ? Layout<2>::SW : Layout<4>::SW);
+    const size_t N = (size_t)q->ncap, S_ = (size_t)q->slots;
+    BC_TRY(q->ctr.alloc(sizeof(uint32_t) * 2 * kQueueCap));
+    BC_TRY(q->claim.alloc(64));
+    BC_TRY(q->ns.alloc(sizeof(uint64_t) * N * SW * S_));
+    BC_TRY(q->qa.alloc(sizeof(int32_t) * N * S_));
+    BC_TRY(q->qb.alloc(sizeof(int32_t) * N * S_));
+    BC_TRY(q->clr.alloc(sizeof(int32_t) * N * S_));
+    BC_TRY(q->stamps.alloc(sizeof(uint32_t) * S_));
+    BC_HIP(hipMemsetAsync(q->ctr.p, 0, q->ctr.bytes, q->stream));
+    BC_HIP(hipMemsetAsync(q->claim.p, 0, q->claim.bytes, q->stream));
+    BC_HIP(hipMemsetAsync(q->ns.p, 0, q->ns.bytes, q->stream));
+    BC_HIP(hipMemsetAsync(q->stamps.p, 0, q->stamps.bytes, q->stream));
+    BC_HIP(hipStreamSynchronize(q->stream));
+    if (device_bytes)
+        *device_bytes = q->ns.bytes + q->qa.bytes + q->qb.bytes + q->clr.bytes + q->stamps.bytes + q->ctr.bytes + 64;
+    *out = q.release();
+    return BC_OK;
+}
+
+void devq_destroy(DevQueue* q) {
+    if (!q) return;
+    __atomic_store_n(q->stop, 1u, __ATOMIC_RELEASE);
+    delete q;  // synchronises the queue stream: the kernel ends at its next claim
+}
+
+int devq_width(const DevQueue* q) { return q->W; }
+int32_t devq_ncap(const DevQueue* q) { return q->ncap; }
+
+bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, hipStream_t prep, QueueJob** out) {
+    *out = nullptr;
+    const int32_t n = g->dg.n;
+    if (n > q->ncap || k > kQueueMaxK || k <= 0) {
+        set_error("request does not fit the queue (n %d of %d, k %d of %d)", n, q->ncap, k, kQueueMaxK);
+        return BC_EINVAL;
+    }
+    const int W = q->W;
+    std::unique_ptr<QueueJob> j(new QueueJob());
+    j->g = g;
+    j->kk = std::min(k, n);
+    bc_opts o = o_in;
+    o.mode = BC_MODE_BATCHED;
+    o.width = W;
+    o.nfirst = 0;
+    o.first = nullptr;
+    const size_t sbytes = query_state_bytes(std::max(j->kk, 0));
+    BC_TRY(j->order.alloc_on(sizeof(int32_t) * (size_t)std::max(n, 1), prep));
+    BC_TRY(j->ring.alloc_on(sizeof(ThRec) * ((size_t)n + 1), prep));
+    BC_TRY(j->state.alloc_on(sbytes, prep));
+    BC_HIP(hipMemsetAsync(j->state.p, 0, sbytes, prep));
+    if (j->kk > 0) BC_TRY(build_order(g, o, j->kk, j->order.as<int32_t>(), prep));
+    BC_HIP(hipStreamSynchronize(prep));
+    const uint32_t nb = (uint32_t)((n + W - 1) / W);
+    std::unique_lock<std::mutex> lk(q->mu);
+    // a free ring slot (one per request in flight)
+    int slot = -1;
+    q->cv.wait(lk, [&] {
+        for (int i = 0; i < kQueueCap; ++i)
+            if (!q->busy[(size_t)i]) {
+                slot = i;
+                return true;
+            }
+        return false;
+    });
+    char* st = j->state.as<char>();
+    JobDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.G = g->dg;
+    d.order = j->order.as<int32_t>();
+    d.T.k = j->kk;
+    d.T.cnt = (int32_t*)st;
+    d.T.lock = (uint32_t*)(st + 4);
+    d.T.seq = (uint32_t*)(st + 8);
+    d.T.list = (Rec*)(st + kHdr);
+    d.T.ring = j->ring.as<ThRec>();
+    d.T.footnote = (!g->dg.directed && (o_in.bounds & BC_BOUND_FOOTNOTE)) ? 1 : 0;
+    d.st = (QStats*)(st + kHdr + sizeof(Rec) * (size_t)j->kk);
+    d.ctr = q->ctr.as<uint32_t>() + 2 * slot;
+    d.start = q->total;
+    d.count = nb;
+    d.bofs = 0;
+    d.total = nb;
+    d.seed = std::min<uint32_t>(nb, (uint32_t)((j->kk + W - 1) / W));
+    d.out = reinterpret_cast<Rec*>(q->dhost + ((char*)(q->out + (size_t)slot * kQueueMaxK) - q->host));
+    d.out_st = reinterpret_cast<unsigned long long*>(
+        q->dhost + ((char*)(q->out_st + (size_t)slot * (sizeof(QStats) / 8)) - q->host));
+    d.done = reinterpret_cast<uint32_t*>(q->dhost + ((char*)(q->done + slot) - q->host));
+    __atomic_store_n(&q->done[slot], 0u, __ATOMIC_RELAXED);
+    std::memcpy(&q->ring[slot], &d, sizeof(d));
+    q->busy[(size_t)slot] = 1;
+    j->slot = slot;
+    q->total += nb;
+    // the descriptor is complete before the total that makes it claimable
+    __atomic_store_n(q->published, q->total, __ATOMIC_RELEASE);
+    BC_TRY(pump_locked(q));
+    *out = j.release();
+    return BC_OK;
+}
+
+bool devq_done(DevQueue* q, const QueueJob* j) { return __atomic_load_n(&q->done[j->slot], __ATOMIC_ACQUIRE) != 0u; }
+
+bc_status devq_collect(DevQueue* q, QueueJob* j, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count,
+                       bc_stats* st, double query_ms) {
+    const uint32_t dv = __atomic_load_n(&q->done[j->slot], __ATOMIC_ACQUIRE);
+    const int32_t cnt = (int32_t)dv - 1;
+    if (cnt != j->kk) {
+        set_error("internal: queued request finished with %d of %d entries", cnt, j->kk);
+        return BC_EDEVICE;
+    }
+    const Rec* r = q->out + (size_t)j->slot * kQueueMaxK;
+    for (int32_t i = 0; i < cnt; ++i) {
+        ids[i] = (int32_t)(uint32_t)(r[i].idr & 0xFFFFFFFFu);
+        reach[i] = (uint32_t)(r[i].idr >> 32);
+        farness[i] = r[i].f;
+    }
+    *count = cnt;
+    if (st) {
+        QStats h;
+        std::memcpy(&h, q->out_st + (size_t)j->slot * (sizeof(QStats) / 8), sizeof(QStats));
+        multi_stats(h, j->g->preprocess_ms, query_ms, 0.0, st);
+    }
+    return BC_OK;
+}
+
+void devq_release(DevQueue* q, QueueJob* j) {
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        if (j->slot >= 0) q->busy[(size_t)j->slot] = 0;
+    }
+    q->cv.notify_all();
+    delete j;
+}
+
+void devq_free(QueueJob* j) { delete j; }
+
+bc_status devq_pump(DevQueue* q) {
+    std::lock_guard<std::mutex> lk(q->mu);
+    return pump_locked(q);
+}
 
 }  // namespace bc

@@ -413,6 +413,9 @@ typedef struct bc_server_stats {
     uint32_t graphs, resident_graphs, queued, running, reserved;
     uint64_t budget_bytes, used_bytes, peak_bytes;
     uint64_t uploads, evictions, completed, failed, canceled;
+    uint64_t queue_inflight;  /* requests in the device queue now                           */
+    uint64_t queue_launches;  /* launches of the queue's persistent kernel so far           */
+    uint64_t queue_batches;   /* source batches published to the queue so far               */
 } bc_server_stats;
 
 void bc_server_opts_default(bc_server_opts* opts);

@@ -106,7 +106,8 @@ class ServerStats(ctypes.Structure):
                 ("queued", ctypes.c_uint32), ("running", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("uploads", ctypes.c_uint64), ("evictions", ctypes.c_uint64), ("completed", ctypes.c_uint64),
-                ("failed", ctypes.c_uint64), ("canceled", ctypes.c_uint64)]
+                ("failed", ctypes.c_uint64), ("canceled", ctypes.c_uint64), ("queue_inflight", ctypes.c_uint64),
+                ("queue_launches", ctypes.c_uint64), ("queue_batches", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("size", "reserved")}

@@ -259,5 +259,10 @@ bc_status devq_collect(DevQueue* q, QueueJob* j, int32_t* ids, uint64_t* farness
 void devq_release(DevQueue* q, QueueJob* j);
 void devq_free(QueueJob* j);  // memory of an entry whose queue is gone
 bc_status devq_pump(DevQueue* q);
+// Publish the rest of a request once its seed batches have finished (true
+// when it did); launch and published-batch counts for the server's report.
+bool devq_advance(DevQueue* q, QueueJob* j);
+unsigned long long devq_launches(DevQueue* q);
+unsigned long long devq_published(DevQueue* q);
 
 }  // namespace bc

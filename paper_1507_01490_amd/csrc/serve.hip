@@ -340,7 +340,7 @@ void finish_request(bc_server* S, SrvReq* r, SrvGraph* G, bc_status rs, const st
 // Whether a request goes to the device queue (caller holds the lock): batched
 // requests whose k and graph fit the queue's result areas and slots.
 bool queue_eligible(bc_server* S, const SrvReq* r, const SrvGraph* G) {
-    if (!S->queue_mode || S->q_failed || r->o.mode != BC_MODE_BATCHED || r->k > kQueueMaxK) return false;
+    if (!S->queue_mode || S->q_failed || r->o.mode != BC_MODE_BATCHED || r->k > kQueueMaxK || G->n <= 0) return false;
     if (S->q) return G->n <= devq_ncap(S->q);
     return true;  // the queue is sized for the largest registered graph when it is made
 }
@@ -412,6 +412,7 @@ void reaper_main(bc_server* S) {
         for (size_t i = 0; i < S->inflight.size();) {
             SrvReq* r = S->inflight[i];
             if (!devq_done(S->q, r->qjob)) {
+                (void)devq_advance(S->q, r->qjob);
                 ++i;
                 continue;
             }
@@ -751,6 +752,11 @@ bc_status bc_server_info(bc_server* S, bc_server_stats* out) {
     t.completed = S->completed;
     t.failed = S->failed;
     t.canceled = S->canceled;
+    t.queue_inflight = S->inflight.size();
+    if (S->q) {
+        t.queue_launches = bc::devq_launches(S->q);
+        t.queue_batches = bc::devq_published(S->q);
+    }
     std::memcpy(out, &t, std::min<size_t>(out->size ? out->size : sizeof(t), sizeof(t)));
     return BC_OK;
 }

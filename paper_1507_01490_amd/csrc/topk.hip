@@ -1320,6 +1320,7 @@ struct JobDesc {
     Rec* out;                  // host-visible copy of the finished list (k records), or null
     unsigned long long* out_st;  // host-visible copy of the QStats words, or null
     uint32_t* done;            // host-visible: count of results + 1 once the query is finished, or null
+    uint32_t* seeded;          // host-visible: 1 once the query's seed batches have finished, or null
 };
 static_assert(sizeof(JobDesc) % 8 == 0, "descriptors are copied in 8-byte words");
 static_assert(offsetof(JobDesc, start) % 8 == 0 && offsetof(JobDesc, count) % 8 == 0,
@@ -1329,7 +1330,8 @@ static_assert(sizeof(QStats) % 8 == 0, "statistics are copied in 8-byte words");
 struct JobLaunch {
     const JobDesc* jobs;                  // descriptor table (device or pinned host memory)
     uint32_t njobs;                       // entries of the table scanned for a batch
-    uint32_t idle_spins;                  // claim attempts with nothing claimable before a workgroup ends
+    uint32_t idle_ticks;                  // time with nothing claimable before a workgroup ends (100 MHz
+                                          // ticks; 0: end at the first look that finds nothing)
     const unsigned long long* published;  // batches published (monotone; device or pinned host memory)
     const uint32_t* stop;                 // nonzero: end once nothing is claimable (may be null)
     unsigned long long* claim;            // device: next global batch to hand out (kept across launches)
@@ -1337,7 +1339,7 @@ struct JobLaunch {
     int32_t ncap;                         // nodes per slot (the largest graph)
 };
 
-constexpr uint32_t kSeedSpins = 1u << 17;  // bounded wait for a query's seed batches (~0.5 s)
+constexpr uint64_t kSeedWaitTicks = 20000000;  // bound of the wait for a query's seed batches: 0.2 s (100 MHz)
 constexpr int kQueueCap = 256;             // requests in flight in a serving queue (ring slots)
 
 __device__ inline unsigned long long sys_ld64(const unsigned long long* p) {
@@ -1345,6 +1347,22 @@ __device__ inline unsigned long long sys_ld64(const unsigned long long* p) {
 }
 __device__ inline void sys_st64(unsigned long long* p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// The current value of a device word that other workgroups change while this
+// one polls it: a read-modify-write that adds nothing is performed where the
+// atomics of every compute unit meet, so it never returns a copy that this
+// compute unit's caches kept from before (a plain or relaxed load may).
+__device__ inline unsigned long long poll64(unsigned long long* p) {
+    return __hip_atomic_fetch_add(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t poll32(uint32_t* p) {
+    return __hip_atomic_fetch_or(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Sleep between polls, doubling from about 3.4 us up to about 110 us, so that
+// many idle workgroups do not crowd the atomic unit that the busy ones need.
+__device__ inline void backoff(uint32_t& reps) {
+    for (uint32_t i = 0; i < reps; ++i) __builtin_amdgcn_s_sleep(127);
+    if (reps < 32) reps *= 2;
 }
 
 // Pointer and size fields of a descriptor read from LDS into scalar
@@ -1401,16 +1419,20 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
     unsigned long long jstart = ~0ull, jend = 0;  // range of the descriptor held in J
     for (;;) {
         if (tid == 0) {
-            // claim the next published batch, or give up after idle_spins
-            // attempts that found nothing (or at once when told to stop)
+            // claim the next published batch, or give up after idle_ticks
+            // with nothing to claim (or at once when told to stop)
             unsigned long long got = ~0ull;
-            uint32_t spin = 0;
+            const uint64_t t_idle = __builtin_amdgcn_s_memrealtime();
+            uint32_t reps = 1;
+            unsigned long long c = poll64(L.claim);
             for (;;) {
-                const unsigned long long pub = __hip_atomic_load(L.published, __ATOMIC_ACQUIRE,
+                // relaxed: a claimed batch's descriptor is read with system-scope
+                // loads, and its data after the acquire fence of a job switch
+                const unsigned long long pub = __hip_atomic_load(L.published, __ATOMIC_RELAXED,
                                                                  __HIP_MEMORY_SCOPE_SYSTEM);
-                unsigned long long c = __hip_atomic_load(L.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (c < pub) {
-                    // a failed exchange means another workgroup claimed c
+                    // a failed exchange means another workgroup claimed c; it
+                    // leaves the counter's current value in c
                     if (__hip_atomic_compare_exchange_strong(L.claim, &c, c + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT)) {
                         got = c;
@@ -1419,8 +1441,9 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
                     continue;
                 }
                 if (L.stop && __hip_atomic_load(L.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) break;
-                if (spin++ >= L.idle_spins) break;
-                __builtin_amdgcn_s_sleep(127);
+                if (__builtin_amdgcn_s_memrealtime() - t_idle >= L.idle_ticks) break;
+                backoff(reps);
+                c = poll64(L.claim);
             }
             s_c = got;
             s_slot = -1;
@@ -1463,11 +1486,11 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
         if (b >= seed && tid == 0) {
             // a later batch waits (bounded) for the seed batches of its query,
             // so that it starts with a k-th best record to cut against
-            for (uint32_t sp = 0; sp < kSeedSpins; ++sp) {
-                if (__hip_atomic_load(T.seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-                if (__hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= seed) break;
-                __builtin_amdgcn_s_sleep(127);
-            }
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            uint32_t reps = 1;
+            while (poll32(T.seq) == 0u && poll32(&ctr[1]) < seed &&
+                   __builtin_amdgcn_s_memrealtime() - t0 < kSeedWaitTicks)
+                backoff(reps);
         }
         if (tid == 0) {
             R.narcs = 0;
@@ -1483,7 +1506,13 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             if (R.narcs) atomicAdd(&st->node_arcs, R.narcs);
             if (R.ent) atomicAdd(&st->frontier_entries, R.ent);
             for (int i = 0; i < 5; ++i) atomicAdd(&st->phase_ticks[i], K.ticks[i]);
-            if (b < seed) __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (b < seed) {
+                const uint32_t sd = __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t* seeded = uni_ptr(J.seeded);
+                // the last seed batch tells the host, which then publishes the rest
+                if (sd + 1 == seed && seeded)
+                    __hip_atomic_store(seeded, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
             const uint32_t f = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             if (f + 1 == total) {
                 // the query's last batch: every other batch's list updates and
@@ -2983,7 +3012,7 @@ void launch_jobs(bc_multi* p, hipStream_t st) {
     JobLaunch L;
     L.jobs = p->jobs.as<JobDesc>();
     L.njobs = p->njobs;
-    L.idle_spins = 0;  // every batch is published before the launch: end when none is left
+    L.idle_ticks = 0;  // every batch is published before the launch: end when none is left
     L.published = p->ctl.as<unsigned long long>() + 1;
     L.stop = nullptr;
     L.claim = p->ctl.as<unsigned long long>();
@@ -3086,6 +3115,7 @@ bc_status multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks
         d.out = nullptr;
         d.out_st = nullptr;
         d.done = nullptr;
+        d.seeded = nullptr;
         jd.push_back(d);
         pos += cnt;
     };
@@ -3204,8 +3234,12 @@ void multi_destroy(bc_multi* p) { delete p; }
 // once when told to stop); the host launches it again when work is waiting.
 
 struct QueueJob {
-    int slot = -1;
+    int slot = -1;          // ring slot of the seed range (its done and seeded flags, its counters)
+    int slot2 = -1;         // ring slot of the rest, published once the seed batches have finished
+    bool rest_pending = false;
+    uint32_t nb = 0, seed = 0;
     int32_t kk = 0;
+    int32_t footnote = 0;
     bc_graph* g = nullptr;
     DevBuf order, ring, state;
 };
@@ -3222,9 +3256,11 @@ struct DevQueue {
     Rec* out = nullptr;
     unsigned long long* out_st = nullptr;
     uint32_t* done = nullptr;
+    uint32_t* seeded = nullptr;
     unsigned long long* published = nullptr;
     uint32_t* stop = nullptr;
     char* dhost = nullptr;           // the same block as the device addresses it
+    unsigned long long launches = 0;
     DevBuf ctr, claim, ns, qa, qb, clr, stamps;
     std::mutex mu;
     std::condition_variable cv;
@@ -3247,11 +3283,16 @@ struct DevQueue {
 
 namespace {
 
-constexpr uint32_t kQueueIdleSpins = 1000;  // ~3.4 ms with nothing to claim before the kernel ends
+constexpr uint32_t kQueueIdleTicks = 500000;  // 5 ms (100 MHz) with nothing to claim before the kernel ends
 
 size_t queue_host_bytes() {
     return sizeof(JobDesc) * kQueueCap + sizeof(Rec) * (size_t)kQueueCap * kQueueMaxK +
-           sizeof(QStats) * kQueueCap + sizeof(uint32_t) * kQueueCap + 64;
+           sizeof(QStats) * kQueueCap + 2 * sizeof(uint32_t) * kQueueCap + 64;
+}
+
+template <class T>
+T* dev_view(const DevQueue* q, T* host_ptr) {
+    return reinterpret_cast<T*>(q->dhost + (reinterpret_cast<char*>(host_ptr) - q->host));
 }
 
 template <int WW>
@@ -3259,7 +3300,7 @@ void launch_queue(DevQueue* q) {
     JobLaunch L;
     L.jobs = reinterpret_cast<const JobDesc*>(q->dhost);
     L.njobs = kQueueCap;
-    L.idle_spins = kQueueIdleSpins;
+    L.idle_ticks = kQueueIdleTicks;
     L.published = reinterpret_cast<const unsigned long long*>(q->dhost + ((char*)q->published - q->host));
     L.stop = reinterpret_cast<const uint32_t*>(q->dhost + ((char*)q->stop - q->host));
     L.claim = q->claim.as<unsigned long long>();
@@ -3287,7 +3328,45 @@ bc_status pump_locked(DevQueue* q) {
     BC_HIP(hipGetLastError());
     BC_HIP(hipEventRecord(q->ev, q->stream));
     q->launched = true;
+    ++q->launches;
     return BC_OK;
+}
+
+// Write a descriptor into a ring slot and make its batches claimable
+// (caller holds q->mu).
+void publish_locked(DevQueue* q, int slot, JobDesc d) {
+    d.start = q->total;
+    std::memcpy(&q->ring[slot], &d, sizeof(d));
+    q->total += d.count;
+    // the descriptor is complete before the total that makes it claimable
+    __atomic_store_n(q->published, q->total, __ATOMIC_RELEASE);
+}
+
+JobDesc job_desc(const DevQueue* q, const QueueJob* j, uint32_t bofs, uint32_t count) {
+    const bc_graph* g = j->g;
+    char* st = j->state.as<char>();
+    JobDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.G = g->dg;
+    d.order = j->order.as<int32_t>();
+    d.T.k = j->kk;
+    d.T.cnt = (int32_t*)st;
+    d.T.lock = (uint32_t*)(st + 4);
+    d.T.seq = (uint32_t*)(st + 8);
+    d.T.list = (Rec*)(st + kHdr);
+    d.T.ring = j->ring.as<ThRec>();
+    d.T.footnote = j->footnote;
+    d.st = (QStats*)(st + kHdr + sizeof(Rec) * (size_t)j->kk);
+    d.ctr = q->ctr.as<uint32_t>() + 2 * j->slot;
+    d.count = count;
+    d.bofs = bofs;
+    d.total = j->nb;
+    d.seed = j->seed;
+    d.out = dev_view(q, q->out + (size_t)j->slot * kQueueMaxK);
+    d.out_st = dev_view(q, q->out_st + (size_t)j->slot * (sizeof(QStats) / 8));
+    d.done = dev_view(q, q->done + j->slot);
+    d.seeded = dev_view(q, q->seeded + j->slot);
+    return d;
 }
 
 }  // namespace
@@ -3316,6 +3395,8 @@ bc_status devq_create(int W, int32_t ncap, int slots, DevQueue** out, uint64_t* 
     q->out_st = reinterpret_cast<unsigned long long*>(h);
     h += sizeof(QStats) * kQueueCap;
     q->done = reinterpret_cast<uint32_t*>(h);
+    h += sizeof(uint32_t) * kQueueCap;
+    q->seeded = reinterpret_cast<uint32_t*>(h);
     h += sizeof(uint32_t) * kQueueCap;
     q->published = reinterpret_cast<unsigned long long*>(h);
     q->stop = reinterpret_cast<uint32_t*>(h + 8);
@@ -3354,7 +3435,7 @@ int32_t devq_ncap(const DevQueue* q) { return q->ncap; }
 bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, hipStream_t prep, QueueJob** out) {
     *out = nullptr;
     const int32_t n = g->dg.n;
-    if (n > q->ncap || k > kQueueMaxK || k <= 0) {
+    if (n <= 0 || n > q->ncap || k > kQueueMaxK || k <= 0) {
         set_error("request does not fit the queue (n %d of %d, k %d of %d)", n, q->ncap, k, kQueueMaxK);
         return BC_EINVAL;
     }
@@ -3362,11 +3443,10 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
     std::unique_ptr<QueueJob> j(new QueueJob());
     j->g = g;
     j->kk = std::min(k, n);
+    j->footnote = (!g->dg.directed && (o_in.bounds & BC_BOUND_FOOTNOTE)) ? 1 : 0;
     bc_opts o = o_in;
     o.mode = BC_MODE_BATCHED;
     o.width = W;
-    o.nfirst = 0;
-    o.first = nullptr;
     const size_t sbytes = query_state_bytes(std::max(j->kk, 0));
     BC_TRY(j->order.alloc_on(sizeof(int32_t) * (size_t)std::max(n, 1), prep));
     BC_TRY(j->ring.alloc_on(sizeof(ThRec) * ((size_t)n + 1), prep));
@@ -3374,51 +3454,51 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
     BC_HIP(hipMemsetAsync(j->state.p, 0, sbytes, prep));
     if (j->kk > 0) BC_TRY(build_order(g, o, j->kk, j->order.as<int32_t>(), prep));
     BC_HIP(hipStreamSynchronize(prep));
-    const uint32_t nb = (uint32_t)((n + W - 1) / W);
+    j->nb = (uint32_t)((n + W - 1) / W);
+    j->seed = std::min<uint32_t>(j->nb, (uint32_t)((j->kk + W - 1) / W));
+    j->rest_pending = j->seed < j->nb;
+    const int need = j->rest_pending ? 2 : 1;
     std::unique_lock<std::mutex> lk(q->mu);
-    // a free ring slot (one per request in flight)
-    int slot = -1;
+    // free ring slots: one for the seed batches, one for the rest
+    int got = 0;
+    int sl[2] = {-1, -1};
     q->cv.wait(lk, [&] {
-        for (int i = 0; i < kQueueCap; ++i)
-            if (!q->busy[(size_t)i]) {
-                slot = i;
-                return true;
-            }
-        return false;
+        got = 0;
+        for (int i = 0; i < kQueueCap && got < need; ++i)
+            if (!q->busy[(size_t)i]) sl[got++] = i;
+        return got == need;
     });
-    char* st = j->state.as<char>();
-    JobDesc d;
-    std::memset(&d, 0, sizeof(d));
-    d.G = g->dg;
-    d.order = j->order.as<int32_t>();
-    d.T.k = j->kk;
-    d.T.cnt = (int32_t*)st;
-    d.T.lock = (uint32_t*)(st + 4);
-    d.T.seq = (uint32_t*)(st + 8);
-    d.T.list = (Rec*)(st + kHdr);
-    d.T.ring = j->ring.as<ThRec>();
-    d.T.footnote = (!g->dg.directed && (o_in.bounds & BC_BOUND_FOOTNOTE)) ? 1 : 0;
-    d.st = (QStats*)(st + kHdr + sizeof(Rec) * (size_t)j->kk);
-    d.ctr = q->ctr.as<uint32_t>() + 2 * slot;
-    d.start = q->total;
-    d.count = nb;
-    d.bofs = 0;
-    d.total = nb;
-    d.seed = std::min<uint32_t>(nb, (uint32_t)((j->kk + W - 1) / W));
-    d.out = reinterpret_cast<Rec*>(q->dhost + ((char*)(q->out + (size_t)slot * kQueueMaxK) - q->host));
-    d.out_st = reinterpret_cast<unsigned long long*>(
-        q->dhost + ((char*)(q->out_st + (size_t)slot * (sizeof(QStats) / 8)) - q->host));
-    d.done = reinterpret_cast<uint32_t*>(q->dhost + ((char*)(q->done + slot) - q->host));
-    __atomic_store_n(&q->done[slot], 0u, __ATOMIC_RELAXED);
-    std::memcpy(&q->ring[slot], &d, sizeof(d));
-    q->busy[(size_t)slot] = 1;
-    j->slot = slot;
-    q->total += nb;
-    // the descriptor is complete before the total that makes it claimable
-    __atomic_store_n(q->published, q->total, __ATOMIC_RELEASE);
+    j->slot = sl[0];
+    j->slot2 = sl[1];
+    for (int i = 0; i < need; ++i) q->busy[(size_t)sl[i]] = 1;
+    __atomic_store_n(&q->done[j->slot], 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(&q->seeded[j->slot], 0u, __ATOMIC_RELAXED);
+    // the seed batches first: the rest is published when they have finished,
+    // so that every later batch starts with a k-th best record and the
+    // workgroups meanwhile take other requests' batches
+    publish_locked(q, j->slot, job_desc(q, j.get(), 0, j->seed));
     BC_TRY(pump_locked(q));
     *out = j.release();
     return BC_OK;
+}
+
+bool devq_advance(DevQueue* q, QueueJob* j) {
+    if (!j->rest_pending || __atomic_load_n(&q->seeded[j->slot], __ATOMIC_ACQUIRE) == 0u) return false;
+    std::lock_guard<std::mutex> lk(q->mu);
+    publish_locked(q, j->slot2, job_desc(q, j, j->seed, j->nb - j->seed));
+    j->rest_pending = false;
+    (void)pump_locked(q);
+    return true;
+}
+
+unsigned long long devq_launches(DevQueue* q) {
+    std::lock_guard<std::mutex> lk(q->mu);
+    return q->launches;
+}
+
+unsigned long long devq_published(DevQueue* q) {
+    std::lock_guard<std::mutex> lk(q->mu);
+    return q->total;
 }
 
 bool devq_done(DevQueue* q, const QueueJob* j) { return __atomic_load_n(&q->done[j->slot], __ATOMIC_ACQUIRE) != 0u; }
@@ -3450,6 +3530,7 @@ void devq_release(DevQueue* q, QueueJob* j) {
     {
         std::lock_guard<std::mutex> lk(q->mu);
         if (j->slot >= 0) q->busy[(size_t)j->slot] = 0;
+        if (j->slot2 >= 0) q->busy[(size_t)j->slot2] = 0;
     }
     q->cv.notify_all();
     delete j;

@@ -50,6 +50,9 @@ def cpu_sample(name: str):
     if name == "rmat21":
         return (synth.rmat(18, 16, 0.57, 0.19, 0.19, 2),
                 "directed R-MAT scale=18 edge_factor=16 (0.57,0.19,0.19,0.05) dedup seed=2, same generator")
+    if name == "collab":
+        return (synth.collaboration(100_000, 25_000, 2.1, 200, 4),
+                "collaboration projection actors=100000 groups=25000 zipf=2.1 cap=200 seed=4, same generator")
     return None
 
 
@@ -62,14 +65,15 @@ def _serve_one(args):
     return synth.grid_shortcuts(n, 0.01, seed)
 
 
-def serve_mix(count: int = 512, seed: int = 3, workers: int = 16):
-    """[(graph, k)] of the serving workload, generated in a process pool."""
+def serve_mix(count: int = 512, seed: int = 3, workers: int = 16, max_n: float = 2e5):
+    """[(graph, k)] of the serving workload, generated in a process pool
+    (count graphs, n log-uniform in [1e3, max_n])."""
     import concurrent.futures as cf
     import os
 
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(seed))
-    sizes = np.exp(rng.uniform(np.log(1e3), np.log(2e5), count)).astype(np.int64)
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(max_n), count)).astype(np.int64)
     ks = rng.choice([1, 10, 100], count)
     jobs = [(i, i % 3, int(sizes[i]), seed * 100000 + i) for i in range(count)]
     nw = max(1, min(workers, os.cpu_count() or 1))

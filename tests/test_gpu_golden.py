@@ -17,8 +17,18 @@ from paper_1507_01490_amd import workloads
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-NAMES = [n for n in ("ba1m", "rmat21", "rgg18") if os.path.exists(os.path.join(HERE, "golden", f"{n}.json"))]
+NAMES = [n for n in ("ba1m", "rmat21", "rgg18", "collab500k", "rgg20")
+         if os.path.exists(os.path.join(HERE, "golden", f"{n}.json"))]
 CONFIGS = {
+    # the collaboration family at the size the oracle finishes: the knobs the
+    # benchmark times on the 2M-actor graph (W = 256, no deferral) with the
+    # learned order and without it, and the library defaults
+    "collab500k": [dict(mode="batched", width=256, defer_arcs=-1, order="learned_grouped"),
+                   dict(mode="batched", width=256, defer_arcs=-1), dict(mode="batched")],
+    # the geometric family at 2^20 nodes: the locality order and the learned
+    # head over it, as timed on the geometric workloads
+    "rgg20": [dict(mode="batched", order="locality", width=256),
+              dict(mode="batched", order="learned_locality", width=256)],
     "ba1m": [dict(mode="batched"), dict(mode="batched", width=256), dict(mode="batched", order="learned_grouped")],
     "rmat21": [dict(mode="batched"), dict(mode="batched", width=256), dict(mode="batched", order="learned_grouped")],
     # the geometric graph: the locality order (the fast one there), both
@@ -37,6 +47,7 @@ def test_full_size_against_oracle(name):
         for k, ref in gold["results"].items():
             k = int(k)
             for kw in CONFIGS[name]:
+                print(f"[golden] {name} k={k} {kw}", flush=True)
                 res = G.topk(k, **kw)
                 assert res.ids.tolist() == ref["ids"], (name, k, kw)
                 assert [int(x) for x in res.farness] == ref["farness"], (name, k, kw)
@@ -103,3 +114,26 @@ def test_rmat21_with_largest_scc_bounds_against_oracle():
             res = G.topk(10, **kw)
             assert res.ids.tolist() == ref["ids"], kw
             assert [int(x) for x in res.farness] == ref["farness"] and [int(x) for x in res.reach] == ref["reach"]
+
+
+def test_collab500k_in_one_launch_with_other_graphs():
+    """The oracle-sized collaboration graph inside a job launch beside two
+    other graphs (the many-graph persistent launch): its stored answer."""
+    path = os.path.join(HERE, "golden", "collab500k.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored answer")
+    import oracle
+    from paper_1507_01490_amd import synth
+    gold = json.load(open(path))
+    g = workloads.build("collab500k")
+    assert g.sha256() == gold["sha256"]
+    ref = gold["results"]["10"]
+    small = [synth.barabasi_albert(20000, 5, 3), synth.grid_shortcuts(10000, 0.01, 4)]
+    with bc.Graph(g.row_ptr, g.col) as G, bc.Graph(small[0].row_ptr, small[0].col) as A, \
+            bc.Graph(small[1].row_ptr, small[1].col) as B:
+        out = bc.topk_multi([A, G, B], [10, 10, 10], width=256)
+    assert out[1].ids.tolist() == ref["ids"]
+    assert [int(x) for x in out[1].farness] == ref["farness"] and [int(x) for x in out[1].reach] == ref["reach"]
+    for sg, res in zip(small, (out[0], out[2])):
+        o = oracle.topk(sg, 10)
+        assert res.ids.tolist() == o["ids"].tolist() and res.farness.tolist() == o["f"].tolist()

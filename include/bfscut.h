@@ -306,6 +306,31 @@ bc_status bc_topk_multi(bc_graph* const* graphs, int32_t count, const int32_t* k
                         int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* counts, bc_stats* stats);
 
 /*
+ * bc_topk_static -- bc_topk in plain mode (W = 64) that allocates nothing:
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ *   g, k, ids, farness, reach, count   as for bc_topk (host outputs of
+ *            capacity k; count = min(k, n) results in decreasing key order)
+ *
+ * Every buffer of the query (control block, top-k list and threshold
+ * records, statistics, source order, node records and lists) lives in one
+ * static device array of 64 MiB per device, which the library holds from the
+ * first call on that device until the process ends; it calls no hipMalloc,
+ * hipFree or allocating library routine.  The array needs about 72 n + 32 k
+ * bytes plus 20 KiB, so graphs of up to about 900,000 nodes fit; larger
+ * ones are rejected with BC_EINVAL and a message.  Sources are taken in the
+ * graph's degree order when it holds one (any earlier plain-mode or degree-
+ * order query builds it), else in node-id order; the answer is the same.
+ * Calls on one device share the array: calls from threads of one process are
+ * serialised by the library, and each call clears the state it needs (the
+ * array keeps the last call's contents).  Blocking, on the graph's stream.
+ * Errors: BC_EINVAL (k <= 0, NULL outputs, graph too large for the array),
+ * BC_EDEVICE.
+ */
+bc_status bc_topk_static(bc_graph* g, int32_t k, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count);
+
+/*
  * bc_farness_all -- exact farness and reach of every node (the textbook
  * computation of Section 1: one breadth-first search per node, here in
  * bit-parallel batches, with no bound and no cut).

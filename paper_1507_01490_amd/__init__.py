@@ -137,6 +137,7 @@ def load_library(path: str = LIB_PATH):
     lib.bc_topk.argtypes = [P, i32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(Stats)]
     f32 = ctypes.c_float
     lib.bc_farness_all.argtypes = [P, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Stats)]
+    lib.bc_topk_static.argtypes = [P, i32, P, P, P, P]
     lib.bc_source_order.argtypes = [P, i32, ctypes.POINTER(Opts), P]
     u64 = ctypes.c_uint64
     lib.bc_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
@@ -163,7 +164,8 @@ def load_library(path: str = LIB_PATH):
                  "bc_graph_csr", "bc_topk", "bc_farness_all", "bc_source_order", "bc_graph_features", "bc_server_create",
                  "bc_server_destroy", "bc_server_add_graph", "bc_submit", "bc_wait", "bc_poll", "bc_cancel",
                  "bc_server_info", "bc_footprint", "bc_autotune", "bc_mlp_forward", "bc_mlp_loss_grad",
-                 "bc_mlp_adam", "bc_multi_create", "bc_multi_run", "bc_multi_destroy", "bc_topk_multi"):
+                 "bc_mlp_adam", "bc_multi_create", "bc_multi_run", "bc_multi_destroy", "bc_topk_multi",
+                 "bc_topk_static"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -456,6 +458,18 @@ class Graph:
                                       ctypes.byref(cnt), ctypes.byref(st)))
         c = cnt.value
         return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
+
+    def topk_static(self, k: int) -> TopK:
+        """bc_topk_static: plain-mode top-k with every buffer in the library's
+        static device array (no allocation; graphs up to ~900k nodes)."""
+        kk = max(1, int(k))
+        ids = np.zeros(kk, np.int32)
+        far = np.zeros(kk, np.uint64)
+        rea = np.zeros(kk, np.uint32)
+        cnt = ctypes.c_int32()
+        _check(load_library().bc_topk_static(self._h, int(k), _ptr(ids), _ptr(far), _ptr(rea), ctypes.byref(cnt)))
+        c = cnt.value
+        return TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), {})
 
     def source_order(self, k: int = 10, mode: str | int = "batched", width: int = 64, order=None, scores=None,
                      mlp=None, seed_batches: int = -1, seed_width: int = 0, first=None) -> np.ndarray:

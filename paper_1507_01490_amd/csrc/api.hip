@@ -177,6 +177,16 @@ bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uin
     BC_GUARD_END
 }
 
+bc_status bc_topk_static(bc_graph* g, int32_t k, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count) {
+    BC_GUARD_BEGIN
+    bc::g_err[0] = 0;
+    if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    if (k <= 0) { set_error("k must be positive (got %d)", k); return BC_EINVAL; }
+    if (!ids || !farness || !reach || !count) { set_error("NULL output array"); return BC_EINVAL; }
+    return bc::run_topk_static(g, k, ids, farness, reach, count);
+    BC_GUARD_END
+}
+
 bc_status bc_farness_all(bc_graph* g, const bc_opts* opts, uint64_t* farness, uint32_t* reach, bc_stats* stats) {
     BC_GUARD_BEGIN
     bc::g_err[0] = 0;

@@ -228,6 +228,10 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
 bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st,
                           hipStream_t s);
 
+// Plain-mode top-k with every buffer in one static device array (topk.hip):
+// allocates nothing.
+bc_status run_topk_static(bc_graph* g, int32_t k, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count);
+
 // Many queries (graph, k) in one persistent launch (topk.hip): prepare the
 // launch (orders, per-query state, descriptors, shared slots; with capture,
 // a HIP graph of it), run it (any number of times), release it.

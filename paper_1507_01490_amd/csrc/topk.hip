@@ -1543,6 +1543,11 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
     if (tid == 0) slot_stamp[slot] = stamp;
 }
 
+// Node-id order 0 .. n-1 (any order gives the same answer, Section 2.1).
+__global__ void k_iota(int32_t* a, int32_t n) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = i;
+}
+
 // Zero `words` 8-byte words (the per-query state of a captured job launch:
 // list headers, statistics and counters, so that every replay starts clean;
 // a kernel rather than a memset node, which is what the capture records).
@@ -2926,6 +2931,177 @@ bc_status run_topk(bc_graph* g, int32_t k, const bc_opts& o, int32_t* ids, uint6
 bc_status run_farness_all(bc_graph* g, const bc_opts& o, uint64_t* farness, uint32_t* reach, bc_stats* st,
                           hipStream_t s) {
     return run_query(g, 0, o, nullptr, nullptr, nullptr, nullptr, st, farness, reach, s, false);
+}
+
+// ------------------------------------------ top-k without any allocation
+//
+// One file-scope device array holds every buffer of a plain-mode query, so
+// that bc_topk_static allocates nothing.  In host code `scratch` names a
+// host-side stand-in; its device address is taken once per device with
+// hipGetSymbolAddress, and only that address is ever passed to kernels or
+// copies.
+
+constexpr size_t kStaticBytes = (size_t)64 << 20;  // 64 MiB per device, held until the process ends
+constexpr size_t kStaticHdr = 64;                   // list header: count, lock, sequence
+
+}  // namespace bc
+
+static __device__ __align__(256) unsigned char scratch[bc::kStaticBytes];
+
+namespace bc {
+namespace {
+
+struct StaticScratch {
+    std::mutex mu;        // serialises calls on one device (they share the array)
+    void* ptr = nullptr;  // device address of `scratch` on this device
+};
+StaticScratch g_static[64];
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of scratch a plain-mode query of W = 64 on n nodes with k results
+// needs: control block, list, statistics, sources, threshold records, order,
+// node records and the three node lists.
+size_t static_need(int32_t n, int32_t kk) {
+    const size_t N = (size_t)n;
+    return al256(sizeof(Ctl)) + al256(kStaticHdr + sizeof(Rec) * (size_t)kk) + al256(sizeof(QStats)) +
+           al256(sizeof(SrcState) * kBlk) + al256(sizeof(ThRec) * (N + 1)) + al256(sizeof(int32_t) * N) +
+           al256(sizeof(uint64_t) * Layout<1>::SW * N) + 3 * al256(sizeof(int32_t) * N);
+}
+
+}  // namespace
+
+bc_status run_topk_static(bc_graph* g, int32_t k, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count) {
+    int dev = 0;
+    BC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device %d out of range", dev);
+        return BC_EDEVICE;
+    }
+    if (g->device != dev) {
+        set_error("the graph lives on device %d, not the current %d", g->device, dev);
+        return BC_EINVAL;
+    }
+    const int32_t n = g->dg.n;
+    const int32_t kk = std::min(k, n);
+    if (n == 0) {
+        *count = 0;
+        return BC_OK;
+    }
+    const size_t need = static_need(n, kk);
+    if (need > kStaticBytes) {
+        set_error("bc_topk_static: n = %d, k = %d needs %zu bytes of its static scratch, which holds %zu "
+                  "(at most about %zu nodes)", n, k, need, kStaticBytes, (kStaticBytes - 65536) / 72);
+        return BC_EINVAL;
+    }
+    StaticScratch& SS = g_static[dev];
+    std::lock_guard<std::mutex> lk(SS.mu);
+    if (!SS.ptr) BC_HIP(hipGetSymbolAddress(&SS.ptr, HIP_SYMBOL(scratch)));
+    hipStream_t s = g->stream;
+    const DevGraph& G = g->dg;
+    char* base = static_cast<char*>(SS.ptr);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* p = base + off;
+        off += al256(b);
+        return p;
+    };
+    Ctl* C = reinterpret_cast<Ctl*>(take(sizeof(Ctl)));
+    char* hb = take(kStaticHdr + sizeof(Rec) * (size_t)kk);
+    QStats* d_st = reinterpret_cast<QStats*>(take(sizeof(QStats)));
+    SrcState* S = reinterpret_cast<SrcState*>(take(sizeof(SrcState) * kBlk));
+    ThRec* ring = reinterpret_cast<ThRec*>(take(sizeof(ThRec) * ((size_t)n + 1)));
+    int32_t* ord = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n));
+    SlotPtrs P;
+    P.ns = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * Layout<1>::SW * (size_t)n));
+    P.qa = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n));
+    P.qb = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n));
+    P.clr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n));
+    // every call starts from zeroed state (the array keeps the last call's
+    // contents): control block, list header and records, statistics, node
+    // records; then the degrees into the records' meta words
+    const int cus = device_cus();
+    auto zero = [&](void* p, size_t bytes) {
+        const size_t words = al256(bytes) / 8;
+        k_zero_words<<<clamp_grid((int64_t)words, 4 * cus), kBlk, 0, s>>>(static_cast<unsigned long long*>(p), words);
+    };
+    zero(C, sizeof(Ctl));
+    zero(hb, kStaticHdr + sizeof(Rec) * (size_t)kk);
+    zero(d_st, sizeof(QStats));
+    zero(P.ns, sizeof(uint64_t) * Layout<1>::SW * (size_t)n);
+    k_slot_init<1><<<clamp_grid((int64_t)n, 4096), kBlk, 0, s>>>(G.deg, n, P.ns, 1);
+    // the graph's degree order when it holds one, else node-id order
+    bool have_deg = false;
+    {
+        std::lock_guard<std::mutex> ck(g->cache_mu);
+        have_deg = g->have_order_deg;
+    }
+    if (have_deg)
+        BC_HIP(hipMemcpyAsync(ord, g->order_deg.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    else
+        k_iota<<<clamp_grid((int64_t)n, 4096), kBlk, 0, s>>>(ord, n);
+    TopKDev T;
+    T.k = kk;
+    T.cnt = reinterpret_cast<int32_t*>(hb);
+    T.lock = reinterpret_cast<uint32_t*>(hb + 4);
+    T.seq = reinterpret_cast<uint32_t*>(hb + 8);
+    T.list = reinterpret_cast<Rec*>(hb + kStaticHdr);
+    T.ring = ring;
+    T.all_f = nullptr;
+    T.all_r = nullptr;
+    T.footnote = 0;
+    LevelParams lp{3.f, 24.f, 1};
+    constexpr int W = 64;
+    const uint32_t nb = (uint32_t)((n + W - 1) / W);
+    uint32_t hctl[16];  // control block words: d, flen, nlen, clen, live, pull, ..., front_arcs at 10
+    for (uint32_t b = 0; b < nb; ++b) {
+        k_plain_init<1><<<1, kBlk, 0, s>>>(G, ord, n, b, W, P, S, C, T, d_st);
+        for (;;) {
+            BC_HIP(hipMemcpyAsync(hctl, C, sizeof(hctl), hipMemcpyDeviceToHost, s));
+            BC_HIP(hipStreamSynchronize(s));
+            const uint32_t flen = hctl[1], live = hctl[4], pull = hctl[5];
+            if (flen > (uint32_t)n || hctl[2] > (uint32_t)n || hctl[3] > (uint32_t)n) {
+                set_error("internal: level %u list lengths %u/%u/%u exceed n = %d", hctl[0], flen, hctl[2], hctl[3], n);
+                return BC_EDEVICE;
+            }
+            unsigned long long fa;
+            std::memcpy(&fa, hctl + 10, sizeof(fa));
+            if (!live) break;
+            if (pull) {
+                k_plain_pull<1><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
+            } else {
+                k_plain_expand<1><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
+                k_plain_count<1><<<clamp_grid((int64_t)std::min<unsigned long long>(fa, (unsigned long long)n), 4 * cus),
+                                   kBlk, 0, s>>>(P, S, C, T, d_st, W, 0);
+            }
+            k_plain_clearcur<1><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C, 0);
+            const int64_t bound = pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
+            k_plain_build<1><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, C, lp, 0);
+        }
+        k_plain_clear<1><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
+    }
+    BC_HIP(hipGetLastError());
+    int32_t cnt = 0;
+    BC_HIP(hipMemcpyAsync(&cnt, T.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (cnt != kk) {
+        set_error("internal: top-k list holds %d of %d entries", cnt, kk);
+        return BC_EDEVICE;
+    }
+    // results in chunks through a fixed host buffer on the stack
+    Rec chunk[64];
+    for (int32_t i0 = 0; i0 < cnt; i0 += 64) {
+        const int32_t m = std::min(64, cnt - i0);
+        BC_HIP(hipMemcpyAsync(chunk, T.list + i0, sizeof(Rec) * (size_t)m, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < m; ++i) {
+            ids[i0 + i] = (int32_t)(uint32_t)(chunk[i].idr & 0xFFFFFFFFu);
+            reach[i0 + i] = (uint32_t)(chunk[i].idr >> 32);
+            farness[i0 + i] = chunk[i].f;
+        }
+    }
+    *count = cnt;
+    return BC_OK;
 }
 
 // ------------------------------------------------ many graphs, one launch

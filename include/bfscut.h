@@ -50,6 +50,13 @@ typedef struct bc_graph bc_graph;
 #define BC_DIRECTED    0x1u  /* arcs are directed (else every edge must appear in both rows) */
 #define BC_VALIDATE    0x2u  /* undirected only: reject a CSR that is not symmetric           */
 #define BC_DEVICE_PTRS 0x4u  /* row_ptr / col are device pointers (read, never kept)          */
+#define BC_KEEP_IDS    0x10u /* undirected only: keep the caller's numbering on the device.  By
+                                default an undirected graph is renumbered on upload in breadth-first
+                                order (from an approximate centre; other components by degree), so
+                                that the node records of neighbours, which a batch reaches together,
+                                sit together in memory.  The renumbering is invisible: every result,
+                                per-node output and input (orders, scores, warm-start lists) uses the
+                                caller's ids, and ties are broken by the caller's ids            */
 #define BC_BIG_SCC     0x8u  /* directed only: reach bounds with the largest-SCC refinement at the
                                 end of Section 2.4: the largest SCC (largest size; among equals the
                                 one holding the smallest node id) gets its exact reach from one
@@ -62,7 +69,8 @@ typedef struct bc_graph bc_graph;
 #define BC_ORDER_GIVEN  1    /* opts.perm: a permutation of [0, n) (host pointer)                */
 #define BC_ORDER_SCORES 2    /* opts.scores: decreasing score, ties by out-degree then id        */
 #define BC_ORDER_GROUPED 3   /* decreasing out-degree; equal degrees grouped by their highest-degree
-                                neighbour (then id), so that a batch shares neighbourhoods       */
+                                neighbour (then id), so that a batch shares neighbourhoods; ids
+                                of the graph's own numbering (see BC_KEEP_IDS)                  */
 #define BC_ORDER_LEARNED 4   /* opts.mlp: decreasing score of the order perceptron over the features
                                 of bc_graph_features (ties by out-degree, then id)               */
 #define BC_ORDER_LEARNED_GROUPED 5 /* opts.mlp: the k best-scored sources (at most as many as the
@@ -79,7 +87,8 @@ typedef struct bc_graph bc_graph;
                                 takes the first unplaced node and grows a breadth-first ball
                                 of unplaced nodes around it.  A batch's sources lie within a
                                 few hops of each other, so they share most levels (suits
-                                graphs without hubs: geometric, grid-like)                      */
+                                graphs without hubs: geometric, grid-like).  Ties and neighbour
+                                order follow the graph's own numbering (see BC_KEEP_IDS)        */
 #define BC_ORDER_LEARNED_LOCALITY 7 /* opts.mlp: the k best-scored sources (at most as many as the
                                 seed batches hold), then all others in BC_ORDER_LOCALITY order (for
                                 graphs without hubs); BC_ORDER_LOCALITY on a directed graph      */

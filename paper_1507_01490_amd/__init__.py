@@ -32,7 +32,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbfscut.s
 # trained parameters of the order perceptron (written by train_order.py)
 MLP_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "order_mlp.npy")
 
-BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS, BC_BIG_SCC = 0x1, 0x2, 0x4, 0x8
+BC_DIRECTED, BC_VALIDATE, BC_DEVICE_PTRS, BC_BIG_SCC, BC_KEEP_IDS = 0x1, 0x2, 0x4, 0x8, 0x10
 BC_BOUND_FOOTNOTE, BC_BOUND_NO_TRIAL = 0x1, 0x2
 ORDER_DEGREE, ORDER_GIVEN, ORDER_SCORES, ORDER_GROUPED, ORDER_LEARNED, ORDER_LEARNED_GROUPED, ORDER_AUTO = \
     0, 1, 2, 3, 4, 5, -1
@@ -339,12 +339,15 @@ class Graph:
 
     ``row_ptr``/``col`` are int32 numpy arrays (host) or int32 torch CUDA
     tensors (device); either way the library copies them.  big_scc: directed
-    reach bounds with the largest-SCC refinement (BC_BIG_SCC)."""
+    reach bounds with the largest-SCC refinement (BC_BIG_SCC); keep_ids: no
+    breadth-first renumbering of an undirected graph on the device
+    (BC_KEEP_IDS; results are in the caller's ids either way)."""
 
     def __init__(self, row_ptr, col, directed: bool = False, validate: bool = False, stream=None,
-                 big_scc: bool = False):
+                 big_scc: bool = False, keep_ids: bool = False):
         lib = load_library()
-        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0) | (BC_BIG_SCC if big_scc else 0)
+        flags = (BC_DIRECTED if directed else 0) | (BC_VALIDATE if validate else 0) | (BC_BIG_SCC if big_scc else 0) \
+            | (BC_KEEP_IDS if keep_ids else 0)
         if _is_torch(row_ptr):
             if not row_ptr.is_cuda:
                 row_ptr, col = row_ptr.numpy(), col.numpy()

@@ -1,6 +1,8 @@
 // C ABI of the library (declared in include/bfscut.h).  Every entry point
 // returns a bc_status and never lets a C++ exception cross the boundary.
+#include <algorithm>
 #include <cstdarg>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -42,7 +44,7 @@ bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32
     *out = nullptr;
     if (n < 0 || m < 0) { set_error("negative size"); return BC_EINVAL; }
     if (!row_ptr || (m > 0 && !col)) { set_error("row_ptr/col is NULL"); return BC_EINVAL; }
-    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS | BC_BIG_SCC)) {
+    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_DEVICE_PTRS | BC_BIG_SCC | BC_KEEP_IDS)) {
         set_error("unknown flag bits");
         return BC_EINVAL;
     }
@@ -50,10 +52,17 @@ bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32
     g->stream = stream;
     g->ordered = ordered;
     (void)hipGetDevice(&g->device);
-    bc_status s = graph_build(g.get(), n, m, row_ptr, col, flags);
+    bc_status s = graph_build(g.get(), n, m, row_ptr, col, flags & ~(uint32_t)BC_KEEP_IDS);
     if (s != BC_OK) {
         (void)hipStreamSynchronize(g->stream);
         return s;
+    }
+    if (!(flags & (BC_DIRECTED | BC_KEEP_IDS)) && n > 1) {
+        bc_graph* h = nullptr;
+        s = graph_relabel(g.get(), flags & ~(uint32_t)(BC_DEVICE_PTRS | BC_KEEP_IDS | BC_VALIDATE), ordered, &h);
+        (void)hipStreamSynchronize(g->stream);
+        if (s != BC_OK) return s;
+        g.reset(h);
     }
     *out = g.release();
     return BC_OK;
@@ -127,24 +136,59 @@ bc_status bc_graph_info(const bc_graph* g, int32_t* n, int64_t* m, int32_t* dire
 }
 
 bc_status bc_graph_reach(const bc_graph* g, uint32_t* lo, uint32_t* hi) {
+    BC_GUARD_BEGIN
     if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
+    bc_graph* gg = const_cast<bc_graph*>(g);
     size_t bytes = sizeof(uint32_t) * (size_t)g->dg.n;
     if (bytes == 0) return BC_OK;
-    if (lo) BC_HIP(hipMemcpyAsync(lo, g->dg.x0, bytes, hipMemcpyDeviceToHost, g->stream));
-    if (hi) BC_HIP(hipMemcpyAsync(hi, g->dg.x1, bytes, hipMemcpyDeviceToHost, g->stream));
-    BC_HIP(hipStreamSynchronize(g->stream));
+    // per node in the caller's numbering
+    bc::DevBuf t;
+    BC_TRY(t.alloc_on(bytes, g->stream));
+    if (lo) {
+        BC_TRY(bc::rows_to_caller(gg, g->dg.x0, t.p, 1, g->stream));
+        BC_HIP(hipMemcpyAsync(lo, t.p, bytes, hipMemcpyDeviceToHost, g->stream));
+        BC_HIP(hipStreamSynchronize(g->stream));
+    }
+    if (hi) {
+        BC_TRY(bc::rows_to_caller(gg, g->dg.x1, t.p, 1, g->stream));
+        BC_HIP(hipMemcpyAsync(hi, t.p, bytes, hipMemcpyDeviceToHost, g->stream));
+        BC_HIP(hipStreamSynchronize(g->stream));
+    }
     return BC_OK;
+    BC_GUARD_END
 }
 
 bc_status bc_graph_csr(const bc_graph* g, int32_t* row_ptr, int32_t* col) {
+    BC_GUARD_BEGIN
     if (!g) { set_error("graph is NULL"); return BC_EINVAL; }
-    if (row_ptr)
-        BC_HIP(hipMemcpyAsync(row_ptr, g->dg.rp, sizeof(int32_t) * ((size_t)g->dg.n + 1), hipMemcpyDeviceToHost,
-                              g->stream));
-    if (col && g->dg.m > 0)
-        BC_HIP(hipMemcpyAsync(col, g->dg.col, sizeof(int32_t) * (size_t)g->dg.m, hipMemcpyDeviceToHost, g->stream));
+    const size_t n = (size_t)g->dg.n, m = (size_t)g->dg.m;
+    std::vector<int32_t> rp(n + 1), cl(m > 0 ? m : 1);
+    BC_HIP(hipMemcpyAsync(rp.data(), g->dg.rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, g->stream));
+    if (m > 0) BC_HIP(hipMemcpyAsync(cl.data(), g->dg.col, sizeof(int32_t) * m, hipMemcpyDeviceToHost, g->stream));
     BC_HIP(hipStreamSynchronize(g->stream));
+    if (!g->relabeled) {
+        if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int32_t) * (n + 1));
+        if (col && m > 0) std::memcpy(col, cl.data(), sizeof(int32_t) * m);
+        return BC_OK;
+    }
+    // the canonical CSR in the caller's numbering: row v is our row inv[v]
+    // with every target renamed by orig, sorted
+    std::vector<int32_t> orig(n), inv(n);
+    BC_HIP(hipMemcpyAsync(orig.data(), g->orig.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, g->stream));
+    BC_HIP(hipMemcpyAsync(inv.data(), g->inv.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, g->stream));
+    BC_HIP(hipStreamSynchronize(g->stream));
+    std::vector<int32_t> orp(n + 1, 0), ocol(m > 0 ? m : 1);
+    for (size_t v = 0; v < n; ++v) orp[v + 1] = orp[v] + (rp[(size_t)inv[v] + 1] - rp[(size_t)inv[v]]);
+    for (size_t v = 0; v < n; ++v) {
+        const int32_t u = inv[v];
+        int32_t* dst = ocol.data() + orp[v];
+        for (int32_t e = rp[(size_t)u]; e < rp[(size_t)u + 1]; ++e) *dst++ = orig[(size_t)cl[(size_t)e]];
+        std::sort(ocol.data() + orp[v], ocol.data() + orp[v + 1]);
+    }
+    if (row_ptr) std::memcpy(row_ptr, orp.data(), sizeof(int32_t) * (n + 1));
+    if (col && m > 0) std::memcpy(col, ocol.data(), sizeof(int32_t) * m);
     return BC_OK;
+    BC_GUARD_END
 }
 
 static bc_status copy_opts(const bc_opts* opts, bc_opts* o) {
@@ -215,6 +259,7 @@ bc_status bc_source_order(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* 
     bc::DevBuf d;
     BC_TRY(d.alloc_on(sizeof(int32_t) * (size_t)n, g->stream));
     BC_TRY(bc::build_order(g, o, std::min(k, n), d.as<int32_t>(), g->stream));
+    BC_TRY(bc::ids_to_caller(g, d.as<int32_t>(), n, g->stream));
     BC_HIP(hipMemcpyAsync(order, d.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, g->stream));
     BC_HIP(hipStreamSynchronize(g->stream));
     return BC_OK;
@@ -288,8 +333,16 @@ bc_status bc_graph_features(bc_graph* g, float* x, uint32_t* core) {
     BC_TRY(bc::graph_features(g, g->stream));
     const size_t n = (size_t)g->dg.n;
     if (n == 0) return BC_OK;
-    BC_HIP(hipMemcpyAsync(x, g->feat.p, sizeof(float) * 3 * n, hipMemcpyDefault, g->stream));
-    if (core) BC_HIP(hipMemcpyAsync(core, g->core.p, sizeof(uint32_t) * n, hipMemcpyDefault, g->stream));
+    // rows in the caller's numbering
+    bc::DevBuf t;
+    BC_TRY(t.alloc_on(sizeof(float) * 3 * n, g->stream));
+    BC_TRY(bc::rows_to_caller(g, g->feat.p, t.p, 3, g->stream));
+    BC_HIP(hipMemcpyAsync(x, t.p, sizeof(float) * 3 * n, hipMemcpyDefault, g->stream));
+    if (core) {
+        BC_HIP(hipStreamSynchronize(g->stream));
+        BC_TRY(bc::rows_to_caller(g, g->core.p, t.p, 1, g->stream));
+        BC_HIP(hipMemcpyAsync(core, t.p, sizeof(uint32_t) * n, hipMemcpyDefault, g->stream));
+    }
     BC_HIP(hipStreamSynchronize(g->stream));
     return BC_OK;
     BC_GUARD_END

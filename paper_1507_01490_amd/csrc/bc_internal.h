@@ -9,6 +9,13 @@
 //                          the degree in the same coalesced stream as the target
 //   x0[n], x1[n] (u32)     reach data: undirected x0 = x1 = r(v) (component size);
 //                          directed x0 = alpha(v), x1 = omega(v)
+//   orig[n]                the caller's id of each node, or null when the graph
+//                          keeps the caller's numbering.  Undirected graphs are
+//                          renumbered on upload in breadth-first order, so that
+//                          the nodes a batch reaches together sit together in
+//                          the node records; every result and per-node output is
+//                          given back in the caller's numbering, and ties are
+//                          broken by the caller's ids
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,6 +61,7 @@ struct DevGraph {
     const int2* adj;
     const uint32_t* x0;
     const uint32_t* x1;
+    const int32_t* orig;
 };
 
 // Raise the release threshold of the device's default memory pool once per
@@ -172,6 +180,8 @@ struct bc_graph {
     std::mutex cache_mu;                    // guards building the cached orders and features
     bool ordered = false;                   // graph buffers are stream-ordered allocations (server graphs)
     bool big_scc = false;                   // directed reach bounds with the largest-SCC refinement
+    bc::DevBuf orig, inv;                   // renumbering: our id -> caller's id, caller's id -> ours
+    bool relabeled = false;
 };
 
 namespace bc {
@@ -188,6 +198,17 @@ namespace bc {
 // transpose and reach data.  rp/col are host or device pointers per flags.
 bc_status graph_build(bc_graph* g, int32_t n, int64_t m, const int32_t* rp, const int32_t* col,
                       uint32_t flags);
+// Renumber a built undirected graph in breadth-first order (the locality
+// seed order): *out receives the renumbered graph (built on the same stream,
+// with orig/inv), g is left as it was for the caller to release.
+bc_status graph_relabel(bc_graph* g, uint32_t flags, bool ordered, bc_graph** out);
+// Id maps of a renumbered graph, on the device: ids[i] = inv[ids[i]] (caller's
+// ids to ours) or orig[ids[i]] (ours to the caller's); no-ops otherwise.
+bc_status ids_to_internal(bc_graph* g, int32_t* d_ids, int64_t count, hipStream_t s);
+bc_status ids_to_caller(bc_graph* g, int32_t* d_ids, int64_t count, hipStream_t s);
+// Gather per-node rows from our numbering into the caller's: dst[v] = src[inv[v]]
+// (rows of `width` 4-byte words); a plain copy when the graph is not renumbered.
+bc_status rows_to_caller(bc_graph* g, const void* d_src, void* d_dst, int width, hipStream_t s);
 // bc_graph_create on stream s; ordered = stream-ordered graph buffers.
 bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
                        hipStream_t s, bool ordered, bc_graph** out);
@@ -201,7 +222,9 @@ bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_devic
 bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipStream_t s);
 // Move the nf distinct node ids h_first (host) to the front of the order
 // d_order (a permutation of [0, n)), keeping the relative order of the rest.
-bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s);
+// (caller_ids: h_first holds the caller's ids, else ids of the graph's own numbering)
+bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s,
+                      bool caller_ids = true);
 bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order, hipStream_t s);
 bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s);
 

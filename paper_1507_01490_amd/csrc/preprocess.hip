@@ -187,10 +187,13 @@ __global__ void k_pack_adj(int64_t m, const int32_t* __restrict__ col, const uin
     }
 }
 
-__global__ void k_degree_keys(int32_t n, const uint32_t* __restrict__ deg, uint64_t* __restrict__ key) {
+// (decreasing degree, increasing id): the id is the caller's (orig[u]) on a
+// renumbered graph, so that the degree order is the same with or without it
+__global__ void k_degree_keys(int32_t n, const uint32_t* __restrict__ deg, const int32_t* __restrict__ orig,
+                              uint64_t* __restrict__ key) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
-        key[u] = ((uint64_t)(0xFFFFFFFFu - deg[u]) << 32) | (uint32_t)u;
+        key[u] = ((uint64_t)(0xFFFFFFFFu - deg[u]) << 32) | (uint32_t)(orig ? orig[u] : (int32_t)u);
 }
 
 __global__ void k_low32(int32_t n, const uint64_t* __restrict__ key, int32_t* __restrict__ out) {
@@ -506,6 +509,53 @@ __global__ void k_front_scatter(int32_t n, int32_t nf, const int32_t* __restrict
         if (flag[i]) out[nf + pos[i]] = order[i];
 }
 
+// inv[orig[u]] = u
+__global__ void k_inverse(int32_t n, const int32_t* __restrict__ orig, int32_t* __restrict__ inv) {
+    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) inv[orig[u]] = u;
+}
+
+// row lengths of the renumbered graph: len[u] = outdeg(orig[u])
+__global__ void k_relabel_len(int32_t n, const int32_t* __restrict__ orig, const uint32_t* __restrict__ deg,
+                              int32_t* __restrict__ len) {
+    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x)
+        len[u] = (int32_t)deg[orig[u]];
+}
+
+// rows of the renumbered graph: row u is row orig[u] with every target
+// renamed by inv (one wave per row)
+__global__ void k_relabel_rows(int32_t n, const int32_t* __restrict__ orig, const int32_t* __restrict__ inv,
+                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const int32_t* __restrict__ nrp, int32_t* __restrict__ ncol) {
+    const int lane = threadIdx.x & 63;
+    const int32_t waves = (int32_t)(gridDim.x * (blockDim.x / 64));
+    for (int32_t u = (int32_t)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64); u < n; u += waves) {
+        const int32_t o = orig[u];
+        const int32_t b = rp[o], len = rp[o + 1] - b, dst = nrp[u];
+        for (int32_t j = lane; j < len; j += 64) ncol[dst + j] = inv[col[b + j]];
+    }
+}
+
+__global__ void k_map_ids(int64_t count, const int32_t* __restrict__ map, int32_t* __restrict__ ids) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        ids[i] = map[ids[i]];
+}
+
+// dst[v] = src[inv[v]], rows of `width` 4-byte words
+__global__ void k_gather_rows(int32_t n, int width, const int32_t* __restrict__ inv, const uint32_t* __restrict__ src,
+                              uint32_t* __restrict__ dst) {
+    const int64_t total = (int64_t)n * width;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / width, w = i % width;
+        dst[i] = src[(int64_t)inv[v] * width + w];
+    }
+}
+
+// dst[u] = src[orig[u]] (caller's per-node floats into our numbering)
+__global__ void k_gather_f32(int32_t n, const int32_t* __restrict__ orig, const float* __restrict__ src,
+                             float* __restrict__ dst) {
+    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) dst[u] = src[orig[u]];
+}
+
 template <class F>
 bc_status cub_call(F&& f, hipStream_t s, DevBuf& tmp) {
     size_t bytes = 0;
@@ -642,11 +692,12 @@ bc_status order_by_degree(bc_graph* g, int32_t* d_order, hipStream_t s) {
         BC_TRY(k0.alloc_on(sizeof(uint64_t) * (size_t)n, s));
         BC_TRY(k1.alloc_on(sizeof(uint64_t) * (size_t)n, s));
         BC_TRY(galloc(g, g->order_deg, sizeof(int32_t) * (size_t)n, s));
-        k_degree_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.deg, k0.as<uint64_t>());
+        k_degree_keys<<<grid_for(n), kBlk, 0, s>>>(n, g->dg.deg, g->dg.orig, k0.as<uint64_t>());
         BC_TRY(cub_call([&](void* t, size_t& b) {
             return hipcub::DeviceRadixSort::SortKeys(t, b, k0.as<uint64_t>(), k1.as<uint64_t>(), n, 0, 64, s);
         }, s, tmp));
         k_low32<<<grid_for(n), kBlk, 0, s>>>(n, k1.as<uint64_t>(), g->order_deg.as<int32_t>());
+        BC_TRY(ids_to_internal(g, g->order_deg.as<int32_t>(), n, s));
         BC_HIP(hipStreamSynchronize(s));
         g->have_order_deg = true;
     }
@@ -701,6 +752,13 @@ bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_devic
     BC_TRY(val1.alloc_on(sizeof(int32_t) * (size_t)n, s));
     BC_HIP(hipMemcpyAsync(sc.p, scores, sizeof(float) * (size_t)n,
                           scores_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (!scores_on_device && g->relabeled) {
+        // the caller's scores are indexed by the caller's ids
+        DevBuf sc2;
+        BC_TRY(sc2.alloc_on(sizeof(float) * (size_t)n, s));
+        k_gather_f32<<<grid_for(n), kBlk, 0, s>>>(n, g->orig.as<int32_t>(), sc.as<float>(), sc2.as<float>());
+        sc.swap(sc2);
+    }
     k_score_keys<<<grid_for(n), kBlk, 0, s>>>(n, sc.as<float>(), d_order, key0.as<uint32_t>());
     // radix sort is stable: equal scores keep the degree order
     BC_TRY(cub_call([&](void* t, size_t& b) {
@@ -901,7 +959,8 @@ bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s
     return BC_OK;
 }
 
-bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s) {
+bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s,
+                      bool caller_ids) {
     const int32_t n = g->dg.n;
     if (nf < 0 || nf > n) { set_error("opts.nfirst %d outside [0, n = %d]", nf, n); return BC_EINVAL; }
     if (nf == 0 || n == 0) return BC_OK;
@@ -922,6 +981,12 @@ bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* 
     BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
     if (err) { set_error("opts.first holds a node outside [0, n) or a repeated node"); return BC_EINVAL; }
+    if (g->relabeled && caller_ids) {
+        // the caller's ids into ours, and the marks again by our ids
+        BC_TRY(ids_to_internal(g, out.as<int32_t>(), nf, s));
+        BC_HIP(hipMemsetAsync(mark.p, 0, sizeof(uint32_t) * (size_t)n, s));
+        k_front_check<<<grid_for(nf), kBlk, 0, s>>>(nf, n, out.as<int32_t>(), mark.as<uint32_t>(), errb.as<uint32_t>());
+    }
     k_front_flags<<<grid_for(n), kBlk, 0, s>>>(n, d_order, mark.as<uint32_t>(), flag.as<int32_t>());
     BC_TRY(cub_call([&](void* t, size_t& b) {
         return hipcub::DeviceScan::ExclusiveSum(t, b, flag.as<int32_t>(), pos.as<int32_t>(), n, s);
@@ -947,6 +1012,76 @@ bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipS
     BC_HIP(hipMemcpyAsync(&err, errb.p, sizeof(err), hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
     if (err) { set_error("opts.perm is not a permutation of [0, n)"); return BC_EINVAL; }
+    return ids_to_internal(g, d_order, n, s);  // the caller's ids into ours
+}
+
+bc_status ids_to_internal(bc_graph* g, int32_t* d_ids, int64_t count, hipStream_t s) {
+    if (!g->relabeled || count <= 0) return BC_OK;
+    k_map_ids<<<grid_for(count), kBlk, 0, s>>>(count, g->inv.as<int32_t>(), d_ids);
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+bc_status ids_to_caller(bc_graph* g, int32_t* d_ids, int64_t count, hipStream_t s) {
+    if (!g->relabeled || count <= 0) return BC_OK;
+    k_map_ids<<<grid_for(count), kBlk, 0, s>>>(count, g->orig.as<int32_t>(), d_ids);
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+bc_status rows_to_caller(bc_graph* g, const void* d_src, void* d_dst, int width, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    if (!g->relabeled) {
+        BC_HIP(hipMemcpyAsync(d_dst, d_src, sizeof(uint32_t) * (size_t)n * width, hipMemcpyDeviceToDevice, s));
+        return BC_OK;
+    }
+    k_gather_rows<<<grid_for((int64_t)n * width), kBlk, 0, s>>>(n, width, g->inv.as<int32_t>(),
+                                                                 static_cast<const uint32_t*>(d_src),
+                                                                 static_cast<uint32_t*>(d_dst));
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+// The renumbered graph: nodes in the locality seed order (breadth-first from
+// an approximate centre, then the other components by degree), so that a
+// node's neighbours, which a batch reaches together, have nearby ids and
+// their node records share cache lines and memory pages.  Built by a second
+// pass of graph_build over the renamed rows (which sorts them); the result
+// is the same graph up to the names of its nodes.
+bc_status graph_relabel(bc_graph* g, uint32_t flags, bool ordered, bc_graph** out) {
+    *out = nullptr;
+    const int32_t n = g->dg.n;
+    const int64_t m = g->dg.m;
+    hipStream_t s = g->stream;
+    BC_TRY(locality_seed(g, s));
+    std::unique_ptr<bc_graph> h(new bc_graph());
+    h->stream = s;
+    h->ordered = ordered;
+    h->device = g->device;
+    BC_TRY(galloc(h.get(), h->orig, sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(galloc(h.get(), h->inv, sizeof(int32_t) * (size_t)n, s));
+    BC_HIP(hipMemcpyAsync(h->orig.p, g->order_loc_seed.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    k_inverse<<<grid_for(n), kBlk, 0, s>>>(n, h->orig.as<int32_t>(), h->inv.as<int32_t>());
+    DevBuf len, nrp, ncol, tmp;
+    BC_TRY(len.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(nrp.alloc_on(sizeof(int32_t) * ((size_t)n + 1), s));
+    BC_TRY(ncol.alloc_on(sizeof(int32_t) * (size_t)(m > 0 ? m : 1), s));
+    k_relabel_len<<<grid_for(n), kBlk, 0, s>>>(n, h->orig.as<int32_t>(), g->dg.deg, len.as<int32_t>());
+    BC_TRY(cub_call([&](void* t, size_t& b) {
+        return hipcub::DeviceScan::ExclusiveSum(t, b, len.as<int32_t>(), nrp.as<int32_t>(), n, s);
+    }, s, tmp));
+    const int32_t mm = (int32_t)m;
+    BC_HIP(hipMemcpyAsync(nrp.as<int32_t>() + n, &mm, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    k_relabel_rows<<<grid_for((int64_t)n * 64), kBlk, 0, s>>>(n, h->orig.as<int32_t>(), h->inv.as<int32_t>(),
+                                                                g->dg.rp, g->dg.col, nrp.as<int32_t>(),
+                                                                ncol.as<int32_t>());
+    BC_HIP(hipStreamSynchronize(s));
+    BC_TRY(graph_build(h.get(), n, m, nrp.as<int32_t>(), ncol.as<int32_t>(), flags | BC_DEVICE_PTRS));
+    h->dg.orig = h->orig.as<int32_t>();
+    h->relabeled = true;
+    h->preprocess_ms += g->preprocess_ms;
+    *out = h.release();
     return BC_OK;
 }
 

@@ -49,8 +49,12 @@ void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o,
     // orders, features and core numbers
     uint64_t gb = 4 * (N + 1) + 4 * M + 8 * M + 4 * N + 8 * N + 8 * N + 16 * N;
     if (directed) gb += 4 * (N + 1) + 4 * M;  // in-CSR
-    // upload: raw copy, sort buffers and component / SCC scratch
-    const uint64_t ub = 12 * M + 40 * N + (1u << 20);
+    else gb += 8 * N;                          // renumbering maps
+    // upload: raw copy, sort buffers and component / SCC scratch; an
+    // undirected graph is built twice (the second time renumbered), so the
+    // first build is held until the second one exists
+    uint64_t ub = 12 * M + 40 * N + (1u << 20);
+    if (!directed) ub += gb + 16 * N + 4 * M;
     const int W = o.width == 128 || o.width == 256 ? o.width : 64;
     const uint64_t SW = W == 64 ? 4 : (W == 128 ? 8 : 16);
     const uint64_t per_slot = N * (8 * SW + 12);
@@ -574,7 +578,7 @@ bc_status bc_server_add_graph(bc_server* S, int32_t n, int64_t m, const int32_t*
     SRV_GUARD_BEGIN
     if (!S || !graph_id || !row_ptr || (m > 0 && !col) || n < 0 || m < 0) { set_error("bad argument"); return BC_EINVAL; }
     if (flags & BC_DEVICE_PTRS) { set_error("server graphs take host arrays"); return BC_EINVAL; }
-    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_BIG_SCC)) { set_error("unknown flag bits"); return BC_EINVAL; }
+    if (flags & ~(uint32_t)(BC_DIRECTED | BC_VALIDATE | BC_BIG_SCC | BC_KEEP_IDS)) { set_error("unknown flag bits"); return BC_EINVAL; }
     if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != m) { set_error("row_ptr[0] must be 0 and row_ptr[n] = m"); return BC_EGRAPH; }
     std::unique_ptr<bc::SrvGraph> G(new bc::SrvGraph());
     G->n = n;

@@ -57,8 +57,9 @@ struct Layout {
 enum : int32_t { S_EMPTY = 0, S_LIVE = 1, S_CUT = 2, S_DONE = 3, S_TRIVIAL = 4, S_DEFER = 5 };
 
 struct SrcState {
-    int32_t id, status;
+    int32_t id, status;   // id: the node in the graph's own numbering (what the batch traverses)
     uint32_t x0, x1;
+    int32_t oid, pad_;    // oid: the caller's id of the node (ties, results, per-node outputs)
     uint64_t nd, fd, tg, mvis;
 };
 
@@ -241,7 +242,7 @@ __device__ inline bool cut_rule(const SrcState& s, uint32_t d, const ThRec& th) 
         all_gt = all_gt && (lhs > rhs);
         all_ge = all_ge && (lhs >= rhs);
     }
-    return all_gt || (all_ge && (int64_t)s.id > th.id);
+    return all_gt || (all_ge && (int64_t)s.oid > th.id);
 }
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
@@ -654,8 +655,8 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
                 if (!s_flags[j]) continue;
                 const SrcState& s = S[j];
                 const bool triv = s.status == S_TRIVIAL;
-                T.all_f[s.id] = triv ? 0 : s.fd;
-                T.all_r[s.id] = triv ? 1u : (uint32_t)s.nd;
+                T.all_f[s.oid] = triv ? 0 : s.fd;
+                T.all_r[s.oid] = triv ? 1u : (uint32_t)s.nd;
                 if (triv) ++nt;
                 else {
                     ++nd;
@@ -685,7 +686,7 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
                     ++nd;
                     mv += s.mvis;
                 }
-                if (have0 && !key_gt(A, F, s.id, th0.A, th0.F, (int32_t)th0.id)) s_flags[j] = 0;
+                if (have0 && !key_gt(A, F, s.oid, th0.A, th0.F, (int32_t)th0.id)) s_flags[j] = 0;
                 else need = true;
             }
             if (need) {
@@ -694,12 +695,12 @@ __device__ uint32_t cut_step(const TopKDev& T, SrcState* S, int W, uint32_t d, b
                     if (!s_flags[j]) continue;
                     const SrcState& s = S[j];
                     if (s.status == S_TRIVIAL) {
-                        topk_insert(T, 0, 1, 0, s.id, 1);
+                        topk_insert(T, 0, 1, 0, s.oid, 1);
                     } else {
                         const uint64_t r = s.nd;
                         const uint64_t A = r <= 1 ? 0 : (r - 1) * (r - 1);
                         const uint64_t F = r <= 1 ? 1 : s.fd;
-                        topk_insert(T, A, F, s.fd, s.id, (uint32_t)r);
+                        topk_insert(T, A, F, s.fd, s.oid, (uint32_t)r);
                     }
                 }
                 if (locked) lock_release(T.lock);
@@ -822,6 +823,7 @@ __device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, u
         if (i < n) {
             const int32_t v = order[i];
             s.id = v;
+            s.oid = G.orig ? G.orig[v] : v;
             s.x0 = G.x0[v];
             s.x1 = G.x1[v];
             s.tg = G.deg[v];
@@ -842,6 +844,7 @@ __device__ void init_batch(const DevGraph& G, const int32_t* order, int32_t n, u
             }
         } else {
             s.id = -1;
+            s.oid = -1;
             s.x0 = s.x1 = 0;
             s.tg = 0;
             s.status = S_EMPTY;
@@ -1385,6 +1388,7 @@ __device__ inline DevGraph uni_graph(const DevGraph& g) {
     o.adj = uni_ptr(g.adj);
     o.x0 = uni_ptr(g.x0);
     o.x1 = uni_ptr(g.x1);
+    o.orig = uni_ptr(g.orig);
     return o;
 }
 __device__ inline TopKDev uni_topk(const TopKDev& t) {
@@ -1991,6 +1995,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
             if (i < G.n) {
                 const int32_t v = order[i];
                 sv.id = v;
+                sv.oid = G.orig ? G.orig[v] : v;
                 sv.x0 = G.x0[v];
                 sv.x1 = G.x1[v];
                 sv.tg = G.deg[v];
@@ -2004,6 +2009,7 @@ __global__ __launch_bounds__(kLdsBlk) void k_batched_lds(DevGraph G, const int32
                 }
             } else {
                 sv.id = -1;
+                sv.oid = -1;
                 sv.x0 = sv.x1 = 0;
                 sv.tg = 0;
                 sv.status = S_EMPTY;
@@ -2905,7 +2911,7 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
                 BC_HIP(hipStreamSynchronize(s));
             }
             BC_TRY(order_locality(g, W, d_order, s));
-            if (head > 0) BC_TRY(order_front(g, h.data(), (int32_t)head, d_order, s));
+            if (head > 0) BC_TRY(order_front(g, h.data(), (int32_t)head, d_order, s, false));
         } else {
             const SeedPlan sp = seed_plan(o, kk, n, W);
             // the k best-scored sources first (the predicted top-k), then the

@@ -82,8 +82,10 @@ def test_footprint_arithmetic():
     """The serving admission estimate (pure host arithmetic, no device call)."""
     n, m = 20000, 160000
     g, u, q_plain = bc.footprint(n, m, k=10, mode="plain")
-    assert g == 4 * (n + 1) + 12 * m + 36 * n
-    assert u == 12 * m + 40 * n + (1 << 20)
+    # undirected: CSR, packed arcs, per-node arrays and the two renumbering maps
+    assert g == 4 * (n + 1) + 12 * m + 36 * n + 8 * n
+    # upload scratch, plus the first build held while the renumbered one is made
+    assert u == 12 * m + 40 * n + (1 << 20) + g + 16 * n + 4 * m
     per_slot = n * (8 * 4 + 12)
     _, _, q16 = bc.footprint(n, m, k=10, mode="batched", slots=16)
     _, _, q32 = bc.footprint(n, m, k=10, mode="batched", slots=32)
@@ -96,7 +98,8 @@ def test_footprint_arithmetic():
     _, _, qs = bc.footprint(100, 400, k=1, mode="batched", slots=64)
     _, _, qp = bc.footprint(100, 400, k=1, mode="plain")
     assert qs - qp == 2 * 100 * 44 + 8
-    gd, _, _ = bc.footprint(n, m, directed=True)
-    assert gd - g == 4 * (n + 1) + 4 * m
+    gd, ud, _ = bc.footprint(n, m, directed=True)
+    assert gd - g == 4 * (n + 1) + 4 * m - 8 * n
+    assert ud == 12 * m + 40 * n + (1 << 20)
     for big in (bc.footprint(2 * n, m), bc.footprint(n, 2 * m), bc.footprint(n, m, k=100)):
         assert big[0] + big[2] > g + q_plain

@@ -125,11 +125,16 @@ def locality_order(rp, col, B):
 ORDERS = ["degree", "grouped", "locality", "learned", "learned_grouped", "learned_locality", "auto"]
 
 
+@pytest.mark.parametrize("keep_ids", [True, False])
 @pytest.mark.parametrize("gi", range(13))
-def test_orders_are_permutations_and_follow_their_rules(gi):
+def test_orders_are_permutations_and_follow_their_rules(gi, keep_ids):
+    """The degree rule in the caller's ids always; the locality rule's ties and
+    neighbour order follow the graph's own numbering, which is the caller's
+    with keep_ids (and on directed graphs) and is pinned there."""
     g = graphs()[gi]
     rp, col = canonical(g)
-    with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+    pin_locality = keep_ids or g.directed
+    with bc.Graph(g.row_ptr, g.col, directed=g.directed, keep_ids=keep_ids) as G:
         for name in ORDERS:
             for mode in ("plain", "batched"):
                 o = G.source_order(10, mode=mode, order=name)
@@ -139,7 +144,8 @@ def test_orders_are_permutations_and_follow_their_rules(gi):
         seed = locality_seed(rp, col)
         for width in (64, 128, 256):
             loc = G.source_order(10, order="locality", width=width)
-            assert loc.tolist() == carve(rp, col, seed, width).tolist(), width
+            if pin_locality:
+                assert loc.tolist() == carve(rp, col, seed, width).tolist(), width
             # a second call returns the cached order
             assert G.source_order(10, order="locality", width=width).tolist() == loc.tolist()
         perm = np.random.default_rng(gi).permutation(g.n)
@@ -151,9 +157,15 @@ def test_locality_batches_are_compact():
     sources lie within a few hops of its first source."""
     g = synth.grid_shortcuts(20000, 0.0, 8)
     rp, col = canonical(g)
-    with bc.Graph(g.row_ptr, g.col) as G:
+    with bc.Graph(g.row_ptr, g.col, keep_ids=True) as G:
         o = G.source_order(10, order="locality", width=64)
     assert o.tolist() == locality_order(rp, col, 64).tolist()
+    with bc.Graph(g.row_ptr, g.col) as G:  # renumbered: still compact balls
+        o2 = G.source_order(10, order="locality", width=64)
+    assert sorted(o2.tolist()) == list(range(g.n))
+    for b in range(0, g.n - 64, 64 * 37):
+        d = bfs_dist(rp, col, int(o2[b]))
+        assert int(d[o2[b:b + 64]].max()) <= 20
     spans = []
     for b in range(0, g.n - 64, 64 * 37):
         d = bfs_dist(rp, col, int(o[b]))

@@ -51,8 +51,9 @@ typedef struct bc_graph bc_graph;
 #define BC_VALIDATE    0x2u  /* undirected only: reject a CSR that is not symmetric           */
 #define BC_DEVICE_PTRS 0x4u  /* row_ptr / col are device pointers (read, never kept)          */
 #define BC_KEEP_IDS    0x10u /* undirected only: keep the caller's numbering on the device.  By
-                                default an undirected graph is renumbered on upload in breadth-first
-                                order (from an approximate centre; other components by degree), so
+                                default an undirected graph of 100,000 nodes or more is renumbered
+                                on upload in breadth-first order (from an approximate centre; other
+                                components by degree), so
                                 that the node records of neighbours, which a batch reaches together,
                                 sit together in memory.  The renumbering is invisible: every result,
                                 per-node output and input (orders, scores, warm-start lists) uses the
@@ -457,7 +458,9 @@ void bc_server_opts_default(bc_server_opts* opts);
 /* Start a server (its lane threads and streams).  Errors: BC_EINVAL, BC_EDEVICE. */
 bc_status bc_server_create(const bc_server_opts* opts, bc_server** out);
 
-/* Cancel queued requests, wait for running ones, free every graph and stream. */
+/* Cancel queued requests, wait for running ones (requests in the device queue
+ * get a minute; then they fail with BC_EDEVICE and the queue's kernel stops
+ * claiming batches), free every graph and stream. */
 bc_status bc_server_destroy(bc_server* s);
 
 /* Register a graph (host arrays as for bc_graph_create, copied; not resident
@@ -479,6 +482,12 @@ bc_status bc_wait(bc_server* s, uint64_t ticket, int32_t timeout_ms);
  * BC_ENOMEM when its footprint exceeds the whole budget), or BC_ECANCELED. */
 bc_status bc_poll(bc_server* s, uint64_t ticket, int32_t* ids, uint64_t* farness, uint32_t* reach, int32_t* count,
                   bc_stats* stats, bc_request_info* info);
+
+/* Progress of a request in the device queue: source batches finished and
+ * batches in all (both 0 for a request that is not in the queue, or not yet
+ * in it).  Read from a counter the kernel raises in pinned host memory; no
+ * device call.  BC_EINVAL for an unknown ticket. */
+bc_status bc_progress(bc_server* s, uint64_t ticket, uint64_t* done_batches, uint64_t* total_batches);
 
 /* Cancel: a queued request is dropped at once; a running one completes and
  * its result is discarded.  BC_EINVAL if it has already finished. */

@@ -148,6 +148,7 @@ def load_library(path: str = LIB_PATH):
     lib.bc_wait.argtypes = [P, u64, i32]
     lib.bc_poll.argtypes = [P, u64, P, P, P, P, ctypes.POINTER(Stats), ctypes.POINTER(RequestInfo)]
     lib.bc_cancel.argtypes = [P, u64]
+    lib.bc_progress.argtypes = [P, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]
     lib.bc_server_info.argtypes = [P, ctypes.POINTER(ServerStats)]
     lib.bc_autotune.argtypes = [P, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(Opts), ctypes.POINTER(TuneReport)]
     lib.bc_footprint.argtypes = [i32, i64, u32, i32, ctypes.POINTER(Opts), i32, ctypes.POINTER(u64),
@@ -165,7 +166,7 @@ def load_library(path: str = LIB_PATH):
                  "bc_server_destroy", "bc_server_add_graph", "bc_submit", "bc_wait", "bc_poll", "bc_cancel",
                  "bc_server_info", "bc_footprint", "bc_autotune", "bc_mlp_forward", "bc_mlp_loss_grad",
                  "bc_mlp_adam", "bc_multi_create", "bc_multi_run", "bc_multi_destroy", "bc_topk_multi",
-                 "bc_topk_static"):
+                 "bc_topk_static", "bc_progress"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -582,6 +583,12 @@ class Server:
         res = TopK(ids[:c].copy(), far[:c].copy(), rea[:c].copy(), st.as_dict())
         res.info = info.as_dict()
         return res
+
+    def progress(self, ticket: int):
+        """(finished batches, all batches) of a request in the device queue (0, 0 otherwise)."""
+        d, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load_library().bc_progress(self._h, ctypes.c_uint64(ticket), ctypes.byref(d), ctypes.byref(t)))
+        return d.value, t.value
 
     def cancel(self, ticket: int):
         _check(load_library().bc_cancel(self._h, ctypes.c_uint64(ticket)))

@@ -38,6 +38,8 @@ void set_error(const char* fmt, ...) {
     va_end(ap);
 }
 
+constexpr int32_t kRelabelMinNodes = 100000;  // undirected graphs of this many nodes or more are renumbered
+
 bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col, uint32_t flags,
                        hipStream_t stream, bool ordered, bc_graph** out) {
     if (!out) { set_error("out is NULL"); return BC_EINVAL; }
@@ -57,7 +59,9 @@ bc_status graph_create(int32_t n, int64_t m, const int32_t* row_ptr, const int32
         (void)hipStreamSynchronize(g->stream);
         return s;
     }
-    if (!(flags & (BC_DIRECTED | BC_KEEP_IDS)) && n > 1) {
+    // small graphs keep their numbering: their node records stay in the
+    // caches anyway, and the second build would dominate their upload
+    if (!(flags & (BC_DIRECTED | BC_KEEP_IDS)) && n >= kRelabelMinNodes) {
         bc_graph* h = nullptr;
         s = graph_relabel(g.get(), flags & ~(uint32_t)(BC_DEVICE_PTRS | BC_KEEP_IDS | BC_VALIDATE), ordered, &h);
         (void)hipStreamSynchronize(g->stream);

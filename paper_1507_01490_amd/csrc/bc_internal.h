@@ -289,6 +289,7 @@ bc_status devq_pump(DevQueue* q);
 // Publish the rest of a request once its seed batches have finished (true
 // when it did); launch and published-batch counts for the server's report.
 bool devq_advance(DevQueue* q, QueueJob* j);
+void devq_progress(DevQueue* q, const QueueJob* j, uint64_t* done, uint64_t* total);
 unsigned long long devq_launches(DevQueue* q);
 unsigned long long devq_published(DevQueue* q);
 

@@ -49,12 +49,12 @@ void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o,
     // orders, features and core numbers
     uint64_t gb = 4 * (N + 1) + 4 * M + 8 * M + 4 * N + 8 * N + 8 * N + 16 * N;
     if (directed) gb += 4 * (N + 1) + 4 * M;  // in-CSR
-    else gb += 8 * N;                          // renumbering maps
+    else if (N >= 100000) gb += 8 * N;         // renumbering maps
     // upload: raw copy, sort buffers and component / SCC scratch; an
     // undirected graph is built twice (the second time renumbered), so the
     // first build is held until the second one exists
     uint64_t ub = 12 * M + 40 * N + (1u << 20);
-    if (!directed) ub += gb + 16 * N + 4 * M;
+    if (!directed && N >= 100000) ub += gb + 16 * N + 4 * M;
     const int W = o.width == 128 || o.width == 256 ? o.width : 64;
     const uint64_t SW = W == 64 ? 4 : (W == 128 ? 8 : 16);
     const uint64_t per_slot = N * (8 * SW + 12);
@@ -708,6 +708,20 @@ bc_status bc_poll(bc_server* S, uint64_t ticket, int32_t* ids, uint64_t* farness
     }
     S->reqs.erase(it);
     return rs;
+    SRV_GUARD_END
+}
+
+bc_status bc_progress(bc_server* S, uint64_t ticket, uint64_t* done_batches, uint64_t* total_batches) {
+    SRV_GUARD_BEGIN
+    if (!S || !done_batches || !total_batches) { set_error("bad argument"); return BC_EINVAL; }
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) { set_error("unknown ticket"); return BC_EINVAL; }
+    bc::SrvReq* r = it->second.get();
+    *done_batches = 0;
+    *total_batches = 0;
+    if (r->qjob && S->q) bc::devq_progress(S->q, r->qjob, done_batches, total_batches);
+    return BC_OK;
     SRV_GUARD_END
 }
 

@@ -1314,29 +1314,54 @@ struct JobDesc {
     const int32_t* order;
     TopKDev T;
     QStats* st;
-    unsigned long long start;  // first global batch of this range
-    uint32_t count;            // batches in the range (>= 1)
+    // the range of global batches, one word so that a reader that races a
+    // rewrite of the slot sees the old range, none, or the new one, never a
+    // mix: (count << kRangeStartBits) | (first batch mod 2^kRangeStartBits);
+    // 0 = no range.  Written last when a descriptor is published.
+    unsigned long long range;
     uint32_t bofs;             // local index of its first batch
     uint32_t total;            // batches of the whole query
     uint32_t seed;             // the query's first `seed` batches: the others wait (bounded) for them
+    uint32_t pad_;
     uint32_t* ctr;             // device, 2 words: finished batches, finished seed batches
     Rec* out;                  // host-visible copy of the finished list (k records), or null
     unsigned long long* out_st;  // host-visible copy of the QStats words, or null
     uint32_t* done;            // host-visible: count of results + 1 once the query is finished, or null
     uint32_t* seeded;          // host-visible: 1 once the query's seed batches have finished, or null
+    uint32_t* progress;        // host-visible: batches of the query finished so far, or null
 };
 static_assert(sizeof(JobDesc) % 8 == 0, "descriptors are copied in 8-byte words");
-static_assert(offsetof(JobDesc, start) % 8 == 0 && offsetof(JobDesc, count) % 8 == 0,
-              "the range fields are read as 8-byte words");
+static_assert(offsetof(JobDesc, range) % 8 == 0, "the range is read as one 8-byte word");
+
+// A range's count takes the top 26 bits (a query has at most
+// ceil((2^31 - 1) / 64) < 2^26 batches) and its first batch the low 38, modulo
+// 2^38: the ranges in a table at one time lie within a few queries of each
+// other, far less than 2^38 batches apart, so the difference below is exact.
+constexpr int kRangeStartBits = 38;
+constexpr unsigned long long kRangeStartMask = (1ull << kRangeStartBits) - 1;
+__host__ __device__ inline unsigned long long pack_range(unsigned long long start, uint32_t count) {
+    return ((unsigned long long)count << kRangeStartBits) | (start & kRangeStartMask);
+}
+// Position of global batch c in the range packed in w, or a value >= the
+// range's count when c is outside it.
+__host__ __device__ inline unsigned long long range_offset(unsigned long long w, unsigned long long c) {
+    return (c - (w & kRangeStartMask)) & kRangeStartMask;
+}
+__host__ __device__ inline uint32_t range_count(unsigned long long w) { return (uint32_t)(w >> kRangeStartBits); }
 static_assert(sizeof(QStats) % 8 == 0, "statistics are copied in 8-byte words");
 
 struct JobLaunch {
     const JobDesc* jobs;                  // descriptor table (device or pinned host memory)
     uint32_t njobs;                       // entries of the table scanned for a batch
-    uint32_t idle_ticks;                  // time with nothing claimable before a workgroup ends (100 MHz
-                                          // ticks; 0: end at the first look that finds nothing)
+    uint32_t pad_;
+    uint64_t idle_ticks;                  // time with nothing claimable before a workgroup ends while no
+                                          // query is in flight (100 MHz ticks; 0: at the first look)
+    uint64_t idle_cap;                    // the same, whatever is in flight (the exit every workgroup
+                                          // reaches if the host stops counting)
     const unsigned long long* published;  // batches published (monotone; device or pinned host memory)
-    const uint32_t* stop;                 // nonzero: end once nothing is claimable (may be null)
+    const uint32_t* stop;                 // nonzero: claim nothing more and end (may be null)
+    const uint32_t* active;               // queries in flight, host-maintained (may be null): while
+                                          // nonzero an idle workgroup keeps waiting for their batches
     unsigned long long* claim;            // device: next global batch to hand out (kept across launches)
     int W;
     int32_t ncap;                         // nodes per slot (the largest graph)
@@ -1430,6 +1455,8 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             uint32_t reps = 1;
             unsigned long long c = poll64(L.claim);
             for (;;) {
+                // told to stop: claim nothing more (the batches in hand finish)
+                if (L.stop && __hip_atomic_load(L.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) break;
                 // relaxed: a claimed batch's descriptor is read with system-scope
                 // loads, and its data after the acquire fence of a job switch
                 const unsigned long long pub = __hip_atomic_load(L.published, __ATOMIC_RELAXED,
@@ -1444,8 +1471,11 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
                     }
                     continue;
                 }
-                if (L.stop && __hip_atomic_load(L.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) break;
-                if (__builtin_amdgcn_s_memrealtime() - t_idle >= L.idle_ticks) break;
+                const uint64_t idle = __builtin_amdgcn_s_memrealtime() - t_idle;
+                if (idle >= L.idle_cap) break;
+                if (idle >= L.idle_ticks &&
+                    (!L.active || __hip_atomic_load(L.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == 0u))
+                    break;
                 backoff(reps);
                 c = poll64(L.claim);
             }
@@ -1460,15 +1490,15 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             // overlap, and the range of a claimed batch stays in the table
             // until its query has finished)
             for (uint32_t i = tid; i < L.njobs; i += B) {
-                const JobDesc* jd = &L.jobs[i];
-                const unsigned long long st0 = sys_ld64(&jd->start);
-                const unsigned long long cw = sys_ld64(reinterpret_cast<const unsigned long long*>(&jd->count));
-                const unsigned long long cnt = cw & 0xFFFFFFFFull;
-                if (st0 <= c && c < st0 + cnt) s_slot = (int32_t)i;
+                const unsigned long long w = sys_ld64(&L.jobs[i].range);
+                if (range_offset(w, c) < range_count(w)) s_slot = (int32_t)i;
             }
             __syncthreads();
             const int32_t js = (int32_t)uni32((uint32_t)s_slot);
             if (js < 0) break;  // cannot happen for a published batch; end rather than guess
+            // the slot's other fields were complete before its range was
+            // written, and stay as they are until its query has finished,
+            // which needs batch c
             const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&L.jobs[js]);
             unsigned long long* dst = reinterpret_cast<unsigned long long*>(&J);
             for (int w = tid; w < (int)(sizeof(JobDesc) / 8); w += B) dst[w] = sys_ld64(&src[w]);
@@ -1477,8 +1507,11 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             // its caches may hold of them before it reads them
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __syncthreads();
-            jstart = uni64(J.start);
-            jend = jstart + uni32(J.count);
+            const unsigned long long rw = uni64(J.range);
+            const unsigned long long off = range_offset(rw, c);
+            if (off >= range_count(rw)) break;  // cannot happen (see above); end rather than guess
+            jstart = c - off;
+            jend = jstart + range_count(rw);
         }
         const uint32_t b = uni32(J.bofs) + (uint32_t)(c - jstart);
         const uint32_t seed = uni32(J.seed), total = uni32(J.total);
@@ -1518,6 +1551,8 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
                     __hip_atomic_store(seeded, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
             const uint32_t f = __hip_atomic_fetch_add(&ctr[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t* prog = uni_ptr(J.progress);
+            if (prog) __hip_atomic_fetch_max(prog, f + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             if (f + 1 == total) {
                 // the query's last batch: every other batch's list updates and
                 // statistics happen before its increment, which this one read
@@ -3195,8 +3230,10 @@ void launch_jobs(bc_multi* p, hipStream_t st) {
     L.jobs = p->jobs.as<JobDesc>();
     L.njobs = p->njobs;
     L.idle_ticks = 0;  // every batch is published before the launch: end when none is left
+    L.idle_cap = 0;
     L.published = p->ctl.as<unsigned long long>() + 1;
     L.stop = nullptr;
+    L.active = nullptr;
     L.claim = p->ctl.as<unsigned long long>();
     L.W = p->W;
     L.ncap = p->ncap;
@@ -3289,8 +3326,7 @@ bc_status multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks
         d.T.footnote = (!g->dg.directed && (o.bounds & BC_BOUND_FOOTNOTE)) ? 1 : 0;
         d.st = (QStats*)(q + kHdr + sizeof(Rec) * (size_t)kq);
         d.ctr = (uint32_t*)(q + kHdr + sizeof(Rec) * (size_t)kq + sizeof(QStats));
-        d.start = pos;
-        d.count = cnt;
+        d.range = pack_range(pos, cnt);
         d.bofs = bofs;
         d.total = nb;
         d.seed = std::min<uint32_t>(nb, (uint32_t)((kq + W - 1) / W));
@@ -3298,6 +3334,7 @@ bc_status multi_create(bc_graph* const* graphs, int32_t count, const int32_t* ks
         d.out_st = nullptr;
         d.done = nullptr;
         d.seeded = nullptr;
+        d.progress = nullptr;
         jd.push_back(d);
         pos += cnt;
     };
@@ -3439,8 +3476,10 @@ struct DevQueue {
     unsigned long long* out_st = nullptr;
     uint32_t* done = nullptr;
     uint32_t* seeded = nullptr;
+    uint32_t* progress = nullptr;
     unsigned long long* published = nullptr;
     uint32_t* stop = nullptr;
+    uint32_t* active = nullptr;      // requests in flight (read by idle workgroups)
     char* dhost = nullptr;           // the same block as the device addresses it
     unsigned long long launches = 0;
     DevBuf ctr, claim, ns, qa, qb, clr, stamps;
@@ -3465,11 +3504,18 @@ struct DevQueue {
 
 namespace {
 
-constexpr uint32_t kQueueIdleTicks = 500000;  // 5 ms (100 MHz) with nothing to claim before the kernel ends
+// A serving kernel's workgroups wait for work while requests are in flight:
+// one that left early would leave the batches published later (a request's
+// rest, once its seed batches are done) to fewer workgroups until the whole
+// launch ended.  With nothing in flight they leave after a short idle time,
+// so that the launch ends and the device is free for other work; the cap is
+// the exit every workgroup reaches whatever the host does.
+constexpr uint64_t kQueueIdleTicks = 500000;        // 5 ms (100 MHz) idle with nothing in flight
+constexpr uint64_t kQueueIdleCap = 12000000000ull;  // 120 s idle in any case
 
 size_t queue_host_bytes() {
     return sizeof(JobDesc) * kQueueCap + sizeof(Rec) * (size_t)kQueueCap * kQueueMaxK +
-           sizeof(QStats) * kQueueCap + 2 * sizeof(uint32_t) * kQueueCap + 64;
+           sizeof(QStats) * kQueueCap + 3 * sizeof(uint32_t) * kQueueCap + 128;
 }
 
 template <class T>
@@ -3483,6 +3529,8 @@ void launch_queue(DevQueue* q) {
     L.jobs = reinterpret_cast<const JobDesc*>(q->dhost);
     L.njobs = kQueueCap;
     L.idle_ticks = kQueueIdleTicks;
+    L.idle_cap = kQueueIdleCap;
+    L.active = reinterpret_cast<const uint32_t*>(q->dhost + ((char*)q->active - q->host));
     L.published = reinterpret_cast<const unsigned long long*>(q->dhost + ((char*)q->published - q->host));
     L.stop = reinterpret_cast<const uint32_t*>(q->dhost + ((char*)q->stop - q->host));
     L.claim = q->claim.as<unsigned long long>();
@@ -3493,7 +3541,8 @@ void launch_queue(DevQueue* q) {
 }
 
 // Launch the kernel when work is published and no launch is running
-// (caller holds q->mu).
+// (caller holds q->mu).  A running launch keeps its workgroups while a
+// request is in flight and ends a few milliseconds after the last one.
 bc_status pump_locked(DevQueue* q) {
     if (q->launched) {
         const hipError_t e = hipEventQuery(q->ev);
@@ -3516,15 +3565,24 @@ bc_status pump_locked(DevQueue* q) {
 
 // Write a descriptor into a ring slot and make its batches claimable
 // (caller holds q->mu).
-void publish_locked(DevQueue* q, int slot, JobDesc d) {
-    d.start = q->total;
+void publish_locked(DevQueue* q, int slot, JobDesc d, uint32_t count) {
+    // the slot is free, so its range is 0 and no workgroup takes it while the
+    // other fields change; the range comes last, then the total that makes
+    // the range's batches claimable
+    d.range = 0;
     std::memcpy(&q->ring[slot], &d, sizeof(d));
-    q->total += d.count;
-    // the descriptor is complete before the total that makes it claimable
+    __atomic_store_n(&q->ring[slot].range, pack_range(q->total, count), __ATOMIC_RELEASE);
+    q->total += count;
     __atomic_store_n(q->published, q->total, __ATOMIC_RELEASE);
 }
 
-JobDesc job_desc(const DevQueue* q, const QueueJob* j, uint32_t bofs, uint32_t count) {
+// Take a finished query's range out of its slot (caller holds q->mu): a
+// free slot matches no batch while a later request rewrites it.
+void clear_slot_locked(DevQueue* q, int slot) {
+    if (slot >= 0) __atomic_store_n(&q->ring[slot].range, 0ull, __ATOMIC_RELEASE);
+}
+
+JobDesc job_desc(const DevQueue* q, const QueueJob* j, uint32_t bofs) {
     const bc_graph* g = j->g;
     char* st = j->state.as<char>();
     JobDesc d;
@@ -3540,7 +3598,6 @@ JobDesc job_desc(const DevQueue* q, const QueueJob* j, uint32_t bofs, uint32_t c
     d.T.footnote = j->footnote;
     d.st = (QStats*)(st + kHdr + sizeof(Rec) * (size_t)j->kk);
     d.ctr = q->ctr.as<uint32_t>() + 2 * j->slot;
-    d.count = count;
     d.bofs = bofs;
     d.total = j->nb;
     d.seed = j->seed;
@@ -3548,6 +3605,7 @@ JobDesc job_desc(const DevQueue* q, const QueueJob* j, uint32_t bofs, uint32_t c
     d.out_st = dev_view(q, q->out_st + (size_t)j->slot * (sizeof(QStats) / 8));
     d.done = dev_view(q, q->done + j->slot);
     d.seeded = dev_view(q, q->seeded + j->slot);
+    d.progress = dev_view(q, q->progress + j->slot);
     return d;
 }
 
@@ -3580,8 +3638,11 @@ bc_status devq_create(int W, int32_t ncap, int slots, DevQueue** out, uint64_t* 
     h += sizeof(uint32_t) * kQueueCap;
     q->seeded = reinterpret_cast<uint32_t*>(h);
     h += sizeof(uint32_t) * kQueueCap;
+    q->progress = reinterpret_cast<uint32_t*>(h);
+    h += sizeof(uint32_t) * kQueueCap;
     q->published = reinterpret_cast<unsigned long long*>(h);
     q->stop = reinterpret_cast<uint32_t*>(h + 8);
+    q->active = reinterpret_cast<uint32_t*>(h + 64);
     void* dp = nullptr;
     BC_HIP(hipHostGetDevicePointer(&dp, q->host, 0));
     q->dhost = reinterpret_cast<char*>(dp);
@@ -3655,10 +3716,13 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
     for (int i = 0; i < need; ++i) q->busy[(size_t)sl[i]] = 1;
     __atomic_store_n(&q->done[j->slot], 0u, __ATOMIC_RELAXED);
     __atomic_store_n(&q->seeded[j->slot], 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(&q->progress[j->slot], 0u, __ATOMIC_RELAXED);
     // the seed batches first: the rest is published when they have finished,
     // so that every later batch starts with a k-th best record and the
     // workgroups meanwhile take other requests' batches
-    publish_locked(q, j->slot, job_desc(q, j.get(), 0, j->seed));
+    // in flight before its first batch is claimable, so that no idle workgroup leaves
+    __atomic_store_n(q->active, __atomic_load_n(q->active, __ATOMIC_RELAXED) + 1u, __ATOMIC_RELEASE);
+    publish_locked(q, j->slot, job_desc(q, j.get(), 0), j->seed);
     BC_TRY(pump_locked(q));
     *out = j.release();
     return BC_OK;
@@ -3667,7 +3731,7 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
 bool devq_advance(DevQueue* q, QueueJob* j) {
     if (!j->rest_pending || __atomic_load_n(&q->seeded[j->slot], __ATOMIC_ACQUIRE) == 0u) return false;
     std::lock_guard<std::mutex> lk(q->mu);
-    publish_locked(q, j->slot2, job_desc(q, j, j->seed, j->nb - j->seed));
+    publish_locked(q, j->slot2, job_desc(q, j, j->seed), j->nb - j->seed);
     j->rest_pending = false;
     (void)pump_locked(q);
     return true;
@@ -3681,6 +3745,11 @@ unsigned long long devq_launches(DevQueue* q) {
 unsigned long long devq_published(DevQueue* q) {
     std::lock_guard<std::mutex> lk(q->mu);
     return q->total;
+}
+
+void devq_progress(DevQueue* q, const QueueJob* j, uint64_t* done, uint64_t* total) {
+    *done = __atomic_load_n(&q->progress[j->slot], __ATOMIC_RELAXED);
+    *total = j->nb;
 }
 
 bool devq_done(DevQueue* q, const QueueJob* j) { return __atomic_load_n(&q->done[j->slot], __ATOMIC_ACQUIRE) != 0u; }
@@ -3711,7 +3780,12 @@ bc_status devq_collect(DevQueue* q, QueueJob* j, int32_t* ids, uint64_t* farness
 void devq_release(DevQueue* q, QueueJob* j) {
     {
         std::lock_guard<std::mutex> lk(q->mu);
-        if (j->slot >= 0) q->busy[(size_t)j->slot] = 0;
+        clear_slot_locked(q, j->slot);
+        clear_slot_locked(q, j->slot2);
+        if (j->slot >= 0) {
+            q->busy[(size_t)j->slot] = 0;
+            __atomic_store_n(q->active, __atomic_load_n(q->active, __ATOMIC_RELAXED) - 1u, __ATOMIC_RELEASE);
+        }
         if (j->slot2 >= 0) q->busy[(size_t)j->slot2] = 0;
     }
     q->cv.notify_all();

@@ -365,6 +365,15 @@ def cycle(n: int) -> Csr:
     return from_edges(n, i, (i + 1) % n, directed=False, name=f"cycle{n}")
 
 
+def circulant(n: int, gens) -> Csr:
+    """Circulant graph: node i joined to (i + s) mod n for each s in gens.
+    Vertex-transitive, so every node has the same farness and reach."""
+    i = np.arange(n)
+    src = np.concatenate([i for _ in gens])
+    dst = np.concatenate([(i + s) % n for s in gens])
+    return from_edges(n, src, dst, directed=False, name=f"circulant{n}")
+
+
 def complete(n: int) -> Csr:
     i, j = np.triu_indices(n, k=1)
     return from_edges(n, i, j, directed=False, name=f"complete{n}")

@@ -82,10 +82,15 @@ def test_footprint_arithmetic():
     """The serving admission estimate (pure host arithmetic, no device call)."""
     n, m = 20000, 160000
     g, u, q_plain = bc.footprint(n, m, k=10, mode="plain")
-    # undirected: CSR, packed arcs, per-node arrays and the two renumbering maps
-    assert g == 4 * (n + 1) + 12 * m + 36 * n + 8 * n
-    # upload scratch, plus the first build held while the renumbered one is made
-    assert u == 12 * m + 40 * n + (1 << 20) + g + 16 * n + 4 * m
+    # undirected, below the renumbering size: CSR, packed arcs, per-node arrays
+    assert g == 4 * (n + 1) + 12 * m + 36 * n
+    assert u == 12 * m + 40 * n + (1 << 20)
+    # from 100,000 nodes: the two renumbering maps, and the first build held
+    # while the renumbered one is made
+    nb, mb = 200000, 1600000
+    gb, ub, _ = bc.footprint(nb, mb)
+    assert gb == 4 * (nb + 1) + 12 * mb + 36 * nb + 8 * nb
+    assert ub == 12 * mb + 40 * nb + (1 << 20) + gb + 16 * nb + 4 * mb
     per_slot = n * (8 * 4 + 12)
     _, _, q16 = bc.footprint(n, m, k=10, mode="batched", slots=16)
     _, _, q32 = bc.footprint(n, m, k=10, mode="batched", slots=32)
@@ -99,7 +104,7 @@ def test_footprint_arithmetic():
     _, _, qp = bc.footprint(100, 400, k=1, mode="plain")
     assert qs - qp == 2 * 100 * 44 + 8
     gd, ud, _ = bc.footprint(n, m, directed=True)
-    assert gd - g == 4 * (n + 1) + 4 * m - 8 * n
+    assert gd - g == 4 * (n + 1) + 4 * m
     assert ud == 12 * m + 40 * n + (1 << 20)
     for big in (bc.footprint(2 * n, m), bc.footprint(n, 2 * m), bc.footprint(n, m, k=100)):
         assert big[0] + big[2] > g + q_plain

@@ -14,12 +14,16 @@ from paper_1507_01490_amd import synth
 
 pytestmark = pytest.mark.gpu
 
+# graphs of 100,000 nodes and more are renumbered
 GRAPHS = [
-    ("ba", lambda: synth.barabasi_albert(3000, 4, 81)),
-    ("grid", lambda: synth.grid_shortcuts(4000, 0.01, 82)),
-    ("collab", lambda: synth.collaboration(6000, 1500, 2.1, 200, 83)),
-    ("cycle", lambda: synth.cycle(40)),  # every node ties: the caller's ids decide
-    ("union", lambda: synth.disjoint_union(synth.path(9), synth.star(12), synth.empty(3), synth.complete(5))),
+    ("ba", lambda: synth.barabasi_albert(120000, 4, 81), (1, 10, 50)),
+    ("grid", lambda: synth.grid_shortcuts(110000, 0.01, 82), (1, 10, 50)),
+    ("collab", lambda: synth.collaboration(120000, 30000, 2.1, 200, 83), (10,)),
+    # vertex-transitive, a few dozen levels deep: every node ties, so the
+    # caller's ids decide
+    ("circulant", lambda: synth.circulant(100000, (1, 47, 2209)), (10,)),
+    ("union", lambda: synth.disjoint_union(synth.path(9), synth.star(12), synth.empty(99970), synth.complete(5)),
+     (1, 10, 50)),
 ]
 
 
@@ -30,12 +34,14 @@ def same(a, b):
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)))
 def test_renumbering_is_invisible(gi):
-    name, make = GRAPHS[gi]
+    name, make, ks = GRAPHS[gi]
     g = make()
     print(f"[relabel] {name} n={g.n}", flush=True)
+    refs = {k: oracle.topk(g, k, nthreads=16) for k in set(ks) | {10}}
     with bc.Graph(g.row_ptr, g.col) as R, bc.Graph(g.row_ptr, g.col, keep_ids=True) as K:
-        for k in (1, 10, 50):
-            ref = oracle.topk(g, k)
+        for k in ks:
+            print(f"[relabel] {name} k={k}", flush=True)
+            ref = refs[k]
             for kw in (dict(mode="plain"), dict(mode="batched"), dict(mode="batched", width=256),
                        dict(mode="batched", order="learned_grouped"), dict(mode="batched", order="locality")):
                 a, b = R.topk(k, **kw), K.topk(k, **kw)
@@ -45,6 +51,7 @@ def test_renumbering_is_invisible(gi):
             out = bc.topk_multi([R, K], [k, k])
             assert same(out[0], out[1]) and out[0].ids.tolist() == ref["ids"].tolist()
         # per-node outputs in the caller's numbering
+        print(f"[relabel] {name} per-node outputs", flush=True)
         rp_r, col_r = R.csr()
         rp_k, col_k = K.csr()
         assert rp_r.tolist() == rp_k.tolist() and col_r.tolist() == col_k.tolist()
@@ -65,15 +72,15 @@ def test_renumbering_is_invisible(gi):
         assert R.source_order(10, mode="plain", order="degree", first=first)[:5].tolist() == first.tolist()
         a = R.topk(10, mode="batched", order=perm)
         b = R.topk(10, mode="batched", first=first)
-        ref = oracle.topk(g, 10)
+        ref = refs[10]
         assert a.ids.tolist() == ref["ids"].tolist() and b.ids.tolist() == ref["ids"].tolist()
         sc = np.random.default_rng(7).random(g.n).astype(np.float32)
         assert R.topk(10, mode="plain", scores=sc).ids.tolist() == ref["ids"].tolist()
 
 
 def test_server_on_renumbered_graphs():
-    g = synth.collaboration(6000, 1500, 2.1, 200, 84)
-    ref = oracle.topk(g, 10)
+    g = synth.barabasi_albert(150000, 4, 84)
+    ref = oracle.topk(g, 10, nthreads=16)
     for queue in (False, True):
         with bc.Server(lanes=1, budget_bytes=1 << 30, queue=queue) as S:
             gid = S.add_graph(g.row_ptr, g.col)

@@ -1354,14 +1354,16 @@ struct JobLaunch {
     const JobDesc* jobs;                  // descriptor table (device or pinned host memory)
     uint32_t njobs;                       // entries of the table scanned for a batch
     uint32_t pad_;
-    uint64_t idle_ticks;                  // time with nothing claimable before a workgroup ends while no
-                                          // query is in flight (100 MHz ticks; 0: at the first look)
-    uint64_t idle_cap;                    // the same, whatever is in flight (the exit every workgroup
-                                          // reaches if the host stops counting)
+    uint64_t idle_ticks;                  // time with nothing claimable, no batch of the launch running
+                                          // and none ended, before a workgroup ends (100 MHz ticks; 0:
+                                          // at the first look)
+    uint64_t idle_cap;                    // time with nothing claimable after which a workgroup ends
+                                          // whatever the others do
     const unsigned long long* published;  // batches published (monotone; device or pinned host memory)
     const uint32_t* stop;                 // nonzero: claim nothing more and end (may be null)
-    const uint32_t* active;               // queries in flight, host-maintained (may be null): while
-                                          // nonzero an idle workgroup keeps waiting for their batches
+    uint32_t* running;                    // device: batches claimed and not yet ended (may be null: the
+                                          // idle rule is then the time alone)
+    unsigned long long* last_end;         // device: clock reading when a batch last ended (with running)
     unsigned long long* claim;            // device: next global batch to hand out (kept across launches)
     int W;
     int32_t ncap;                         // nodes per slot (the largest graph)
@@ -1430,6 +1432,15 @@ __device__ inline TopKDev uni_topk(const TopKDev& t) {
     return o;
 }
 
+// A claimed batch has ended (one thread of its workgroup): the clock reading
+// first, then the release decrement that an idle workgroup reads with acquire.
+__device__ inline void batch_ended(const JobLaunch& L) {
+    if (!L.running) return;
+    __hip_atomic_fetch_max(L.last_end, (unsigned long long)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_sub(L.running, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int WW, int B>
 __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t* slot_stamp) {
     using Lo = Layout<WW>;
@@ -1467,15 +1478,25 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
                     if (__hip_atomic_compare_exchange_strong(L.claim, &c, c + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT)) {
                         got = c;
+                        if (L.running) __hip_atomic_fetch_add(L.running, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
                     continue;
                 }
-                const uint64_t idle = __builtin_amdgcn_s_memrealtime() - t_idle;
+                // Idle.  While a batch of this launch runs, or ended less than
+                // idle_ticks ago, work may still follow from it (the rest of a
+                // query is published once its seed batches end), so the
+                // workgroup stays; the rule depends on device work alone, never
+                // on host progress, which may itself wait for this launch.
+                const uint64_t now = __builtin_amdgcn_s_memrealtime();
+                const uint64_t idle = now - t_idle;
                 if (idle >= L.idle_cap) break;
-                if (idle >= L.idle_ticks &&
-                    (!L.active || __hip_atomic_load(L.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == 0u))
-                    break;
+                if (idle >= L.idle_ticks) {
+                    if (!L.running) break;
+                    // acquire: an ended batch's clock reading is seen with its decrement
+                    const uint32_t run = __hip_atomic_fetch_add(L.running, 0u, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (run == 0u && (int64_t)(now - poll64(L.last_end)) >= (int64_t)L.idle_ticks) break;
+                }
                 backoff(reps);
                 c = poll64(L.claim);
             }
@@ -1495,7 +1516,10 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             }
             __syncthreads();
             const int32_t js = (int32_t)uni32((uint32_t)s_slot);
-            if (js < 0) break;  // cannot happen for a published batch; end rather than guess
+            if (js < 0) {  // cannot happen for a published batch; end rather than guess
+                if (tid == 0) batch_ended(L);
+                break;
+            }
             // the slot's other fields were complete before its range was
             // written, and stay as they are until its query has finished,
             // which needs batch c
@@ -1509,7 +1533,10 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
             __syncthreads();
             const unsigned long long rw = uni64(J.range);
             const unsigned long long off = range_offset(rw, c);
-            if (off >= range_count(rw)) break;  // cannot happen (see above); end rather than guess
+            if (off >= range_count(rw)) {  // cannot happen (see above); end rather than guess
+                if (tid == 0) batch_ended(L);
+                break;
+            }
             jstart = c - off;
             jend = jstart + range_count(rw);
         }
@@ -1576,6 +1603,7 @@ __global__ __launch_bounds__(B) void k_jobs(JobLaunch L, SlotPtrs base, uint32_t
                 uint32_t* done = uni_ptr(J.done);
                 if (done) __hip_atomic_store(done, (uint32_t)cnt + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
+            batch_ended(L);
         }
         __syncthreads();
     }
@@ -3233,7 +3261,8 @@ void launch_jobs(bc_multi* p, hipStream_t st) {
     L.idle_cap = 0;
     L.published = p->ctl.as<unsigned long long>() + 1;
     L.stop = nullptr;
-    L.active = nullptr;
+    L.running = nullptr;
+    L.last_end = nullptr;
     L.claim = p->ctl.as<unsigned long long>();
     L.W = p->W;
     L.ncap = p->ncap;
@@ -3479,7 +3508,6 @@ struct DevQueue {
     uint32_t* progress = nullptr;
     unsigned long long* published = nullptr;
     uint32_t* stop = nullptr;
-    uint32_t* active = nullptr;      // requests in flight (read by idle workgroups)
     char* dhost = nullptr;           // the same block as the device addresses it
     unsigned long long launches = 0;
     DevBuf ctr, claim, ns, qa, qb, clr, stamps;
@@ -3504,13 +3532,14 @@ struct DevQueue {
 
 namespace {
 
-// A serving kernel's workgroups wait for work while requests are in flight:
-// one that left early would leave the batches published later (a request's
-// rest, once its seed batches are done) to fewer workgroups until the whole
-// launch ended.  With nothing in flight they leave after a short idle time,
-// so that the launch ends and the device is free for other work; the cap is
-// the exit every workgroup reaches whatever the host does.
-constexpr uint64_t kQueueIdleTicks = 500000;        // 5 ms (100 MHz) idle with nothing in flight
+// A serving kernel's workgroups wait for work while a batch of the launch
+// runs or has just ended: one that left then would leave the batches
+// published next (a request's rest, once its seed batches are done) to
+// fewer workgroups until the whole launch ended.  With no batch running for
+// a few milliseconds and nothing to claim they leave, so that the launch ends
+// and the device is free for other work (a request's preparation on another
+// stream may wait for that); the cap bounds the wait for a long batch.
+constexpr uint64_t kQueueIdleTicks = 500000;        // 5 ms (100 MHz)
 constexpr uint64_t kQueueIdleCap = 12000000000ull;  // 120 s idle in any case
 
 size_t queue_host_bytes() {
@@ -3530,10 +3559,11 @@ void launch_queue(DevQueue* q) {
     L.njobs = kQueueCap;
     L.idle_ticks = kQueueIdleTicks;
     L.idle_cap = kQueueIdleCap;
-    L.active = reinterpret_cast<const uint32_t*>(q->dhost + ((char*)q->active - q->host));
     L.published = reinterpret_cast<const unsigned long long*>(q->dhost + ((char*)q->published - q->host));
     L.stop = reinterpret_cast<const uint32_t*>(q->dhost + ((char*)q->stop - q->host));
     L.claim = q->claim.as<unsigned long long>();
+    L.running = reinterpret_cast<uint32_t*>(q->claim.as<char>() + 8);
+    L.last_end = reinterpret_cast<unsigned long long*>(q->claim.as<char>() + 16);
     L.W = q->W;
     L.ncap = q->ncap;
     SlotPtrs base{q->ns.as<uint64_t>(), q->qa.as<int32_t>(), q->qb.as<int32_t>(), q->clr.as<int32_t>()};
@@ -3642,7 +3672,6 @@ bc_status devq_create(int W, int32_t ncap, int slots, DevQueue** out, uint64_t* 
     h += sizeof(uint32_t) * kQueueCap;
     q->published = reinterpret_cast<unsigned long long*>(h);
     q->stop = reinterpret_cast<uint32_t*>(h + 8);
-    q->active = reinterpret_cast<uint32_t*>(h + 64);
     void* dp = nullptr;
     BC_HIP(hipHostGetDevicePointer(&dp, q->host, 0));
     q->dhost = reinterpret_cast<char*>(dp);
@@ -3720,8 +3749,6 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
     // the seed batches first: the rest is published when they have finished,
     // so that every later batch starts with a k-th best record and the
     // workgroups meanwhile take other requests' batches
-    // in flight before its first batch is claimable, so that no idle workgroup leaves
-    __atomic_store_n(q->active, __atomic_load_n(q->active, __ATOMIC_RELAXED) + 1u, __ATOMIC_RELEASE);
     publish_locked(q, j->slot, job_desc(q, j.get(), 0), j->seed);
     BC_TRY(pump_locked(q));
     *out = j.release();
@@ -3782,10 +3809,7 @@ void devq_release(DevQueue* q, QueueJob* j) {
         std::lock_guard<std::mutex> lk(q->mu);
         clear_slot_locked(q, j->slot);
         clear_slot_locked(q, j->slot2);
-        if (j->slot >= 0) {
-            q->busy[(size_t)j->slot] = 0;
-            __atomic_store_n(q->active, __atomic_load_n(q->active, __ATOMIC_RELAXED) - 1u, __ATOMIC_RELEASE);
-        }
+        if (j->slot >= 0) q->busy[(size_t)j->slot] = 0;
         if (j->slot2 >= 0) q->busy[(size_t)j->slot2] = 0;
     }
     q->cv.notify_all();

@@ -36,7 +36,10 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
+
+#include <hip/hip_cooperative_groups.h>
 
 #include "bc_internal.h"
 
@@ -115,6 +118,7 @@ struct Ctl {
     unsigned long long active[4];
     uint32_t cnt_g[256];
     unsigned long long cnt_t[256];
+    uint32_t err;                  // cooperative level loop: a list outgrew n (the loop stopped)
 };
 
 struct SlotPtrs {
@@ -138,6 +142,9 @@ __device__ inline void st64(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline int32_t ld32(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t ldu32(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // A value that every lane of the workgroup holds alike (read from LDS after a
@@ -871,12 +878,9 @@ __global__ void k_slot_init(const uint32_t* __restrict__ deg, int32_t n, uint64_
 // and reads the control block to see whether any source is still live.
 
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* order, int32_t count, uint32_t b,
-                                                    int W, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st) {
-    __shared__ CutLds CL;
-    __shared__ uint32_t s_flen;
-    __shared__ unsigned long long s_arcs;
-    __shared__ uint64_t s_act[4];
+__device__ void plain_init_body(const DevGraph& G, const int32_t* order, int32_t count, uint32_t b, int W,
+                                const SlotPtrs& P, SrcState* S, Ctl* C, const TopKDev& T, QStats* st, CutLds& CL,
+                                uint32_t& s_flen, unsigned long long& s_arcs, uint64_t* s_act) {
     init_batch<WW>(G, order, count, b, W, P, S, &s_flen, &s_arcs);
     const uint32_t live = cut_step<WW>(T, S, W, 0, false, nullptr, nullptr, false, false, st, s_act, CL);
     if (threadIdx.x == 0) {
@@ -894,6 +898,16 @@ __global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* 
         for (int j = 0; j < 4; ++j) C->active[j] = j < WW ? s_act[j] : 0;
         atomicAdd(&st->batches, 1ull);
     }
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_init(DevGraph G, const int32_t* order, int32_t count, uint32_t b,
+                                                    int W, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st) {
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_flen;
+    __shared__ unsigned long long s_arcs;
+    __shared__ uint64_t s_act[4];
+    plain_init_body<WW>(G, order, count, b, W, P, S, C, T, st, CL, s_flen, s_arcs, s_act);
 }
 
 // Shared epilogue of the plain expand/pull kernels: flush the workgroup's bit
@@ -937,11 +951,8 @@ __device__ void plain_level_epilogue(Ctl* C, SrcState* S, TopKDev T, QStats* st,
 // same step takes the other case).  Every thread reads the same control
 // words, written by kernels that finished before this one started.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, Ctl* C, QStats* st, int gated) {
-    if (gated && (C->live == 0 || C->pull != 0)) return;
-    __shared__ LdsExpand<WW> L;
-    __shared__ uint64_t s_act[4];
-    __shared__ unsigned long long s_arcs, s_ent;
+__device__ void plain_expand_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, QStats* st, LdsExpand<WW>& L,
+                                  uint64_t* s_act, unsigned long long& s_arcs, unsigned long long& s_ent) {
     const uint32_t flen = C->flen, stamp = C->stamp;
     const int tid = threadIdx.x;
     if (tid < WW) s_act[tid] = C->active[tid];
@@ -962,19 +973,23 @@ __global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, C
     if (tid == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
 }
 
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, Ctl* C, QStats* st, int gated) {
+    if (gated && (C->live == 0 || C->pull != 0)) return;
+    __shared__ LdsExpand<WW> L;
+    __shared__ uint64_t s_act[4];
+    __shared__ unsigned long long s_arcs, s_ent;
+    plain_expand_body<WW>(G, P, C, st, L, s_act, s_arcs, s_ent);
+}
+
 // After a push step: the per-source counters of the level from its list of
 // newly reached nodes (once per node), then the cut step in the last
 // workgroup.  Same gate as the push step.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_count(SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st,
-                                                     int W, int gated) {
-    if (gated && (C->live == 0 || C->pull != 0)) return;
+__device__ void plain_count_body(const SlotPtrs& P, SrcState* S, Ctl* C, const TopKDev& T, QStats* st, int W,
+                                 uint32_t* cg, unsigned long long* ct, CutLds& CL, uint32_t& s_last,
+                                 uint64_t* s_act) {
     using Lo = Layout<WW>;
-    __shared__ uint32_t cg[kBlk];
-    __shared__ unsigned long long ct[kBlk];
-    __shared__ CutLds CL;
-    __shared__ uint32_t s_last;
-    __shared__ uint64_t s_act[4];
     const uint32_t tid = threadIdx.x;
     cg[tid] = 0;
     ct[tid] = 0;
@@ -1000,20 +1015,27 @@ __global__ __launch_bounds__(kBlk) void k_plain_count(SlotPtrs P, SrcState* S, C
     plain_level_epilogue<WW>(C, S, T, st, W, cg, ct, CL, s_act, &s_last);
 }
 
-// Bottom-up step: every node not yet seen by some live source looks for an
-// in-neighbour in the frontier of that source (early exit once all of its
-// unseen live bits are found).  One thread owns a node, so all bits it finds
-// are new and counted here.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
-                                                    QStats* st, int W, int gated) {
-    if (gated && (C->live == 0 || C->pull == 0)) return;
-    using Lo = Layout<WW>;
+__global__ __launch_bounds__(kBlk) void k_plain_count(SlotPtrs P, SrcState* S, Ctl* C, TopKDev T, QStats* st,
+                                                     int W, int gated) {
+    if (gated && (C->live == 0 || C->pull != 0)) return;
     __shared__ uint32_t cg[kBlk];
     __shared__ unsigned long long ct[kBlk];
     __shared__ CutLds CL;
     __shared__ uint32_t s_last;
     __shared__ uint64_t s_act[4];
+    plain_count_body<WW>(P, S, C, T, st, W, cg, ct, CL, s_last, s_act);
+}
+
+// Bottom-up step: every node not yet seen by some live source looks for an
+// in-neighbour in the frontier of that source (early exit once all of its
+// unseen live bits are found).  One thread owns a node, so all bits it finds
+// are new and counted here.
+template <int WW>
+__device__ void plain_pull_body(const DevGraph& G, const SlotPtrs& P, SrcState* S, Ctl* C, const TopKDev& T,
+                                QStats* st, int W, uint32_t* cg, unsigned long long* ct, CutLds& CL,
+                                uint32_t& s_last, uint64_t* s_act) {
+    using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     uint64_t act[WW];
 #pragma unroll
@@ -1076,6 +1098,18 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Src
 }
 
 template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
+                                                    QStats* st, int W, int gated) {
+    if (gated && (C->live == 0 || C->pull == 0)) return;
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_last;
+    __shared__ uint64_t s_act[4];
+    plain_pull_body<WW>(G, P, S, C, T, st, W, cg, ct, CL, s_last, s_act);
+}
+
+template <int WW>
 __global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C, int gated) {
     if (gated && C->ran == 0) return;
     clear_cur<WW>(P, P.qa, C->flen, blockIdx.x * kBlk, gridDim.x * kBlk);
@@ -1086,10 +1120,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C, int
 // counter is idle between levels and counts finished workgroups here; the
 // done_blocks word counts the new frontier entries.
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ctl* C, LevelParams lp, int gated) {
-    if (gated && C->ran == 0) return;
-    __shared__ uint32_t s_last;
-    __shared__ unsigned long long s_arcs;
+__device__ void plain_build_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, const LevelParams& lp,
+                                 uint32_t& s_last, unsigned long long& s_arcs) {
     const int tid = threadIdx.x;
     uint64_t act[WW];
 #pragma unroll
@@ -1128,11 +1160,19 @@ __global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ct
     C->done_blocks = 0;
 }
 
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ctl* C, LevelParams lp, int gated) {
+    if (gated && C->ran == 0) return;
+    __shared__ uint32_t s_last;
+    __shared__ unsigned long long s_arcs;
+    plain_build_body<WW>(G, P, C, lp, s_last, s_arcs);
+}
+
 // End of a batch: reset seen and cur of every node the batch reached (nxt
 // is already zero; cur is non-zero only for sources of a batch that ended
 // at level 0).
 template <int WW>
-__global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
+__device__ void plain_clear_body(const SlotPtrs& P, Ctl* C) {
     using Lo = Layout<WW>;
     const uint32_t nc = C->clen;
     for (uint32_t i = blockIdx.x * kBlk + threadIdx.x; i < nc; i += gridDim.x * kBlk) {
@@ -1142,6 +1182,81 @@ __global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
             rec[j] = 0;
             rec[Lo::CUR + j] = 0;
         }
+    }
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_clear(SlotPtrs P, Ctl* C) {
+    plain_clear_body<WW>(P, C);
+}
+
+// Every level of `nb` consecutive batches in one cooperative launch: the
+// phases the host otherwise launches one by one per level are separated by
+// grid barriers, and the decision to go on is read on the device.  Each
+// branch after a barrier reads only control words that no phase changes
+// before the next barrier (live, pull and the list lengths at the top of a
+// level, nlen after the counting phase), so every workgroup takes the same
+// branch and reaches the same barriers.  A list longer than n (which would
+// mean the level step wrote out of order) stops the loop with C->err set,
+// before any kernel indexes the lists with that length.
+__device__ inline void grid_barrier(cooperative_groups::grid_group& g) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    g.sync();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <int WW>
+__global__ __launch_bounds__(kBlk) void k_plain_coop(DevGraph G, const int32_t* order, int32_t count, uint32_t b0,
+                                                    uint32_t nb, int W, SlotPtrs P, SrcState* S, Ctl* C, TopKDev T,
+                                                    QStats* st, LevelParams lp) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ LdsExpand<WW> L;
+    __shared__ uint32_t cg[kBlk];
+    __shared__ unsigned long long ct[kBlk];
+    __shared__ CutLds CL;
+    __shared__ uint32_t s_last, s_flen;
+    __shared__ unsigned long long s_arcs, s_ent;
+    __shared__ uint64_t s_act[4];
+    const uint32_t n = (uint32_t)G.n;
+    for (uint32_t b = b0; b < b0 + nb; ++b) {
+        if (blockIdx.x == 0) plain_init_body<WW>(G, order, count, b, W, P, S, C, T, st, CL, s_flen, s_arcs, s_act);
+        grid_barrier(grid);
+        bool bad = false;
+        for (;;) {
+            const uint32_t live = ldu32(&C->live), pull = ldu32(&C->pull);
+            if (ldu32(&C->flen) > n || ldu32(&C->clen) > n) {
+                bad = true;
+                break;
+            }
+            if (!live) break;
+            if (pull) {
+                plain_pull_body<WW>(G, P, S, C, T, st, W, cg, ct, CL, s_last, s_act);
+                grid_barrier(grid);
+            } else {
+                plain_expand_body<WW>(G, P, C, st, L, s_act, s_arcs, s_ent);
+                grid_barrier(grid);
+                if (ldu32(&C->nlen) > n) {
+                    bad = true;
+                    break;
+                }
+                plain_count_body<WW>(P, S, C, T, st, W, cg, ct, CL, s_last, s_act);
+                grid_barrier(grid);
+            }
+            if (ldu32(&C->nlen) > n) {
+                bad = true;
+                break;
+            }
+            clear_cur<WW>(P, P.qa, ldu32(&C->flen), blockIdx.x * kBlk, gridDim.x * kBlk);
+            grid_barrier(grid);
+            plain_build_body<WW>(G, P, C, lp, s_last, s_arcs);
+            grid_barrier(grid);
+        }
+        if (bad) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) __hip_atomic_store(&C->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;  // every workgroup read the same lengths, so all of them end here
+        }
+        plain_clear_body<WW>(P, C);
+        grid_barrier(grid);
     }
 }
 
@@ -2542,6 +2657,27 @@ bc_status ensure_batched(Workspace& W_, const DevGraph& G, int want, hipStream_t
 // Level-synchronous batches over order[0, count), batches [0, nb), on the
 // plain slot of Wk (sized for WW words per node), adding their kernel time
 // to *ms.
+// Workgroups of a cooperative level launch: as many as the device holds at
+// once, up to kCoopPerCu per compute unit (more make each grid barrier
+// slower than they make a level faster); 0 when the device cannot launch
+// the kernel cooperatively.
+constexpr int kCoopPerCu = 2;
+
+template <int WW>
+int coop_grid() {
+    int dev = 0, coop = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_plain_coop<WW>), kBlk,
+                                                     0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int lim = kCoopPerCu;
+    if (const char* e = std::getenv("BC_COOP_PER_CU")) lim = std::max(1, std::atoi(e));
+    return std::min(per_cu, lim) * device_cus();
+}
+
 template <int WW>
 bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count, uint32_t nb, Workspace& Wk,
                             TopKDev T, QStats* d_st, const LevelParams& lp, hipStream_t s, double* ms,
@@ -2559,6 +2695,40 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
     SrcState* S = Wk.srcs.as<SrcState>();
     Ctl* C = Wk.ctl.as<Ctl>();
     uint32_t* hctl = Wk.hctl;
+    const int cgrid = graph_levels == 0 && nb > 0 ? coop_grid<WW>() : 0;
+    if (cgrid > 0) {
+        // every level of every batch in one cooperative launch
+        BC_HIP(hipMemsetAsync(&C->err, 0, sizeof(uint32_t), s));
+        EventPair ev;
+        BC_TRY(ev.create());
+        DevGraph a_g = G;
+        const int32_t* a_ord = ord;
+        int32_t a_count = count;
+        uint32_t a_b0 = 0, a_nb = nb;
+        int a_w = W;
+        SlotPtrs a_p = P;
+        SrcState* a_s = S;
+        Ctl* a_c = C;
+        TopKDev a_t = T;
+        QStats* a_st = d_st;
+        LevelParams a_lp = lp;
+        void* args[] = {&a_g, &a_ord, &a_count, &a_b0, &a_nb, &a_w, &a_p, &a_s, &a_c, &a_t, &a_st, &a_lp};
+        BC_HIP(hipEventRecord(ev.a, s));
+        BC_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_plain_coop<WW>), dim3(cgrid), dim3(kBlk),
+                                          args, 0, s));
+        BC_HIP(hipEventRecord(ev.b, s));
+        uint32_t err = 0;
+        BC_HIP(hipMemcpyAsync(&err, &C->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        double t = 0;
+        BC_TRY(ev.ms(&t));
+        BC_HIP(hipStreamSynchronize(s));  // the copy of the error word
+        if (err) {
+            set_error("internal: a level list of the cooperative loop exceeded n = %d", n);
+            return BC_EDEVICE;
+        }
+        *ms += t;
+        return BC_OK;
+    }
     // graph_levels > 0: capture that many gated level steps once and replay
     // them, reading the control block once per replay instead of per level
     GraphHolder gh;
@@ -2776,8 +2946,8 @@ bc_status run_query(bc_graph* g, int32_t k, bc_opts o, int32_t* ids, uint64_t* f
         set_error("unknown mode %d", o.mode);
         return BC_EINVAL;
     }
-    if (o.graph_levels < 0 || o.graph_levels > 64) {
-        set_error("graph_levels must be in [0, 64] (got %d)", o.graph_levels);
+    if (o.graph_levels < -1 || o.graph_levels > 64) {
+        set_error("graph_levels must be in [-1, 64] (got %d)", o.graph_levels);
         return BC_EINVAL;
     }
     if (o.seed_width != 0 && o.seed_width != 64 && o.seed_width != 128 && o.seed_width != 256) {

@@ -37,6 +37,8 @@ VARIANTS = [
     dict(mode="plain", width=64, graph_levels=4),                     # captured level steps
     dict(mode="batched", width=128, defer_arcs=40, graph_levels=3),
     dict(mode="plain", width=256, pull_alpha=1e9, pull_beta=1e-9, graph_levels=2),
+    dict(mode="plain", width=64, graph_levels=-1),                    # one host round trip per level
+    dict(mode="batched", width=64, defer_arcs=1, graph_levels=-1),
 ]
 
 
@@ -121,6 +123,33 @@ def test_medium_graphs(kind):
                 assert_same(G.topk(k, **v), ref, (kind, k, v))
 
 
+LOOP_GRAPHS = [lambda: synth.barabasi_albert(3000, 4, 21), lambda: synth.grid_shortcuts(4000, 0.01, 22),
+               lambda: synth.rmat(12, 8, 0.57, 0.19, 0.19, 23), lambda: synth.random_small(600, 0.005, True, 24),
+               lambda: synth.disjoint_union(synth.path(40), synth.star(30), synth.empty(7))]
+
+
+@pytest.mark.parametrize("gi", range(len(LOOP_GRAPHS)))
+def test_level_loops_agree(gi):
+    """The three drivers of the level-synchronous batches (one cooperative
+    launch, one host round trip per level, captured level steps) run the same
+    level steps: the same answer everywhere, and in plain mode, where each
+    batch starts from the state the previous one left, the same counters."""
+    g = LOOP_GRAPHS[gi]()
+    print(f"[loops] graph {gi} n={g.n} m={g.m}", flush=True)
+    with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+        for k in (1, 10, 70):
+            ref = oracle.topk(g, k)
+            for kw in (dict(mode="plain", width=64), dict(mode="plain", width=256, pull_alpha=14.0),
+                       dict(mode="batched", width=64, defer_arcs=1), dict(mode="batched", width=128, seed_width=256)):
+                runs = [G.topk(k, graph_levels=gl, **kw) for gl in (0, -1, 3)]
+                for r in runs:
+                    assert_same(r, ref, (gi, k, kw))
+                if kw["mode"] == "plain":
+                    for key in ("m_vis", "levels", "pull_levels", "node_arcs", "batches", "n_cut", "n_done"):
+                        vals = [int(r.stats[key]) for r in runs]
+                        assert len(set(vals)) == 1, (gi, k, kw, key, vals)
+
+
 def test_reach_data_matches_oracle():
     for seed in range(4):
         g = synth.random_small(300, 0.006 + 0.002 * seed, True, 77 + seed)
@@ -177,5 +206,8 @@ def test_errors():
         assert e.value.status == -1
         with pytest.raises(bc.BcError) as e:
             G.topk(3, order=np.array([0, 0, 1, 2, 3]))
+        assert e.value.status == -1
+        with pytest.raises(bc.BcError) as e:
+            G.topk(3, mode="plain", graph_levels=-2)
         assert e.value.status == -1
         assert_same(G.topk(3), oracle.topk(g, 3))  # still usable after errors

@@ -140,12 +140,13 @@ typedef struct bc_opts {
     int32_t defer_width;    /* BC_MODE_BATCHED: sources per batch of the re-run of deferred
                                sources, 64, 128 or 256 (0 = 256)                         */
     const float* mlp;       /* BC_ORDER_LEARNED: host, BC_MLP_PARAMS floats              */
-    int32_t graph_levels;   /* level-synchronous batches: 0 (the default) runs every level
-                               of every batch of a phase in one cooperative launch, grid
-                               barriers between the level steps; -1 makes one host round
-                               trip per level; 1..64 captures that many level steps in a
-                               HIP graph and replays it, checking for live sources once
-                               per replay                                                */
+    int32_t graph_levels;   /* level-synchronous batches: 0 (the default) makes one host
+                               round trip per level; 1..64 captures that many level steps
+                               in a HIP graph and replays it, checking for live sources
+                               once per replay; -1 runs every level of every batch of a
+                               phase in one cooperative launch, grid barriers between the
+                               level steps (BC_EINVAL where the device cannot launch it
+                               cooperatively). The default measures fastest on gfx950.  */
     int32_t seed_width;     /* BC_MODE_BATCHED: sources per seed batch, a multiple of width
                                up to 256 (0 = width, or 256 when k > width);
                                seed_batches counts these batches                         */

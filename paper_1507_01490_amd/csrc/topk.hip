@@ -36,7 +36,6 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstddef>
-#include <cstdlib>
 #include <cstring>
 
 #include <hip/hip_cooperative_groups.h>
@@ -554,7 +553,12 @@ __device__ inline void clear_cur(const SlotPtrs& P, const int32_t* F, uint32_t l
 // has run: nxt is reset everywhere; the live bits go to seen and cur, nodes
 // with a live bit go to the frontier list F, first-seen nodes to the reset
 // list.  With no live bit at all only nxt is reset.  Block-uniform loop.
-template <int WW>
+// kFresh: the caller's compute unit holds no copy of the records that
+// predates the level's atomic updates (a kernel of its own, or after a grid
+// barrier's acquire), so nxt is read with a plain load; otherwise (the
+// persistent kernels, whose own plain loads may have cached a record before
+// the atomics changed it) it is taken with an exchange.
+template <int WW, bool kFresh = false>
 __device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t first, uint32_t stride,
                             const uint64_t* act, bool any_live, int32_t* F, uint32_t* fctr, uint32_t* clen,
                             unsigned long long* arcs, uint32_t* seen_filter = nullptr) {
@@ -574,10 +578,21 @@ __device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, u
             } else {
                 uint64_t nb[WW];
                 uint64_t any = 0;
+                if constexpr (kFresh) {
 #pragma unroll
-                for (int j = 0; j < WW; ++j) {
-                    nb[j] = atomicExch((unsigned long long*)&rec[Lo::NXT + j], 0ull) & act[j];
-                    any |= nb[j];
+                    for (int j = 0; j < WW; ++j) nb[j] = rec[Lo::NXT + j];
+#pragma unroll
+                    for (int j = 0; j < WW; ++j) {
+                        rec[Lo::NXT + j] = 0;
+                        nb[j] &= act[j];
+                        any |= nb[j];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < WW; ++j) {
+                        nb[j] = atomicExch((unsigned long long*)&rec[Lo::NXT + j], 0ull) & act[j];
+                        any |= nb[j];
+                    }
                 }
                 if (any) {
                     uint64_t old_any = 0;
@@ -950,10 +965,22 @@ __device__ void plain_level_epilogue(Ctl* C, SrcState* S, TopKDev T, QStats* st,
 // source is live and the step's direction is push (the pull kernel of the
 // same step takes the other case).  Every thread reads the same control
 // words, written by kernels that finished before this one started.
+// Frontier entries per chunk a workgroup claims in a push step: about
+// kChunkArcs arcs (the level's arcs spread evenly over its entries), at most
+// kBlk.  A level of a few heavy entries, such as the hub sources of level 0
+// in degree order, then spreads over many workgroups instead of one.
+constexpr unsigned long long kChunkArcs = 4096;
+__host__ __device__ inline uint32_t expand_chunk(uint32_t flen, unsigned long long arcs) {
+    if (arcs == 0) return kBlk;
+    const unsigned long long per = (unsigned long long)flen * kChunkArcs / arcs;
+    return per < 1 ? 1u : (per > (unsigned long long)kBlk ? (uint32_t)kBlk : (uint32_t)per);
+}
+
 template <int WW>
 __device__ void plain_expand_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, QStats* st, LdsExpand<WW>& L,
                                   uint64_t* s_act, unsigned long long& s_arcs, unsigned long long& s_ent) {
     const uint32_t flen = C->flen, stamp = C->stamp;
+    const uint32_t per = expand_chunk(flen, C->front_arcs);
     const int tid = threadIdx.x;
     if (tid < WW) s_act[tid] = C->active[tid];
     if (tid == 0) {
@@ -964,10 +991,11 @@ __device__ void plain_expand_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, 
     for (;;) {
         if (tid == 0) L.chunk = atomicAdd(&C->chunk, 1u);
         __syncthreads();
-        const uint32_t e0 = L.chunk * kBlk;
+        const unsigned long long e0 = (unsigned long long)L.chunk * per;
         __syncthreads();
         if (e0 >= flen) break;
-        expand_entries<WW>(G, P, P.qa, e0, min(flen, e0 + kBlk), s_act, P.qb, &C->nlen, stamp, L, &s_arcs, &s_ent);
+        expand_entries<WW>(G, P, P.qa, (uint32_t)e0, min(flen, (uint32_t)e0 + per), s_act, P.qb, &C->nlen, stamp, L,
+                           &s_arcs, &s_ent);
     }
     if (tid == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
     if (tid == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
@@ -1030,13 +1058,26 @@ __global__ __launch_bounds__(kBlk) void k_plain_count(SlotPtrs P, SrcState* S, C
 // Bottom-up step: every node not yet seen by some live source looks for an
 // in-neighbour in the frontier of that source (early exit once all of its
 // unseen live bits are found).  One thread owns a node, so all bits it finds
-// are new and counted here.
+// are new and counted here.  A node with more than kPullWave in-arcs is
+// scanned by its whole wave, 64 arcs a round, the bits found OR-reduced over
+// the wave (on skewed graphs one thread walking a hub's list serially held
+// its wave, and the level, for the whole walk).
+constexpr int32_t kPullWave = 32;
+
+// OR of x over the 64 lanes of the wave, in every lane.
+__device__ inline uint64_t wave_or(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+    return x;
+}
+
 template <int WW>
 __device__ void plain_pull_body(const DevGraph& G, const SlotPtrs& P, SrcState* S, Ctl* C, const TopKDev& T,
                                 QStats* st, int W, uint32_t* cg, unsigned long long* ct, CutLds& CL,
                                 uint32_t& s_last, uint64_t* s_act) {
     using Lo = Layout<WW>;
     const int tid = threadIdx.x;
+    const int lane = (int)lane_id();
     uint64_t act[WW];
 #pragma unroll
     for (int j = 0; j < WW; ++j) act[j] = C->active[j];
@@ -1048,45 +1089,91 @@ __device__ void plain_pull_body(const DevGraph& G, const SlotPtrs& P, SrcState* 
     for (uint32_t base = blockIdx.x * kBlk; base < (uint32_t)G.n; base += stride) {
         const int32_t w = (int32_t)(base + tid);
         bool app = false;
-        uint64_t pbits[WW];
+        uint64_t pbits[WW], unv[WW], acc[WW];
         uint32_t pdeg = 0;
+        uint64_t any = 0;
+        int32_t e0 = 0, e1 = 0;
 #pragma unroll
-        for (int j = 0; j < WW; ++j) pbits[j] = 0;
+        for (int j = 0; j < WW; ++j) {
+            pbits[j] = 0;
+            unv[j] = 0;
+            acc[j] = 0;
+        }
+        uint64_t* rec = nullptr;
         if (w < G.n) {
-            uint64_t* rec = &P.ns[(size_t)w * Lo::SW];
-            uint64_t unv[WW], acc[WW];
-            uint64_t any = 0;
+            rec = &P.ns[(size_t)w * Lo::SW];
 #pragma unroll
             for (int j = 0; j < WW; ++j) {
                 unv[j] = act[j] & ~rec[j];
-                acc[j] = 0;
                 any |= unv[j];
             }
             if (any) {
-                const int32_t e1 = G.irp[w + 1];
-                for (int32_t e = G.irp[w]; e < e1; ++e) {
+                e0 = G.irp[w];
+                e1 = G.irp[w + 1];
+            }
+        }
+        const bool heavy = any && e1 - e0 > kPullWave;
+        if (any && !heavy) {
+            for (int32_t e = e0; e < e1; ++e) {
+                const uint64_t* ur = &P.ns[(size_t)G.icol[e] * Lo::SW];
+                ++scanned;
+                bool full = true;
+#pragma unroll
+                for (int j = 0; j < WW; ++j) {
+                    acc[j] |= ur[Lo::CUR + j] & unv[j];
+                    full = full && (acc[j] == unv[j]);
+                }
+                if (full) break;
+            }
+        }
+        // the wave's heavy nodes, one at a time, each list read by all lanes
+        unsigned long long hm = __ballot(heavy);
+        while (hm) {
+            const int l = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const int32_t h0 = __shfl(e0, l), h1 = __shfl(e1, l);
+            uint64_t hu[WW], ha[WW];
+#pragma unroll
+            for (int j = 0; j < WW; ++j) {
+                hu[j] = __shfl(unv[j], l);
+                ha[j] = 0;
+            }
+            for (int32_t eb = h0; eb < h1; eb += 64) {
+                const int32_t e = eb + lane;
+                uint64_t part[WW];
+#pragma unroll
+                for (int j = 0; j < WW; ++j) part[j] = 0;
+                if (e < h1) {
                     const uint64_t* ur = &P.ns[(size_t)G.icol[e] * Lo::SW];
-                    ++scanned;
-                    bool full = true;
 #pragma unroll
-                    for (int j = 0; j < WW; ++j) {
-                        acc[j] |= ur[Lo::CUR + j] & unv[j];
-                        full = full && (acc[j] == unv[j]);
-                    }
-                    if (full) break;
+                    for (int j = 0; j < WW; ++j) part[j] = ur[Lo::CUR + j] & hu[j];
                 }
-                uint64_t got = 0;
+                if (lane == 0) scanned += (unsigned long long)min(64, h1 - eb);
+                bool full = true;
 #pragma unroll
-                for (int j = 0; j < WW; ++j) got |= acc[j];
-                if (got) {
-                    pdeg = (uint32_t)(rec[Lo::META] >> 32);
-#pragma unroll
-                    for (int j = 0; j < WW; ++j) {
-                        rec[Lo::NXT + j] = acc[j];
-                        pbits[j] = acc[j];
-                    }
-                    app = true;
+                for (int j = 0; j < WW; ++j) {
+                    ha[j] |= wave_or(part[j]);
+                    full = full && (ha[j] == hu[j]);
                 }
+                if (full) break;
+            }
+            if (lane == l) {
+#pragma unroll
+                for (int j = 0; j < WW; ++j) acc[j] = ha[j];
+            }
+        }
+        if (any) {
+            uint64_t got = 0;
+#pragma unroll
+            for (int j = 0; j < WW; ++j) got |= acc[j];
+            if (got) {
+                pdeg = (uint32_t)(rec[Lo::META] >> 32);
+#pragma unroll
+                for (int j = 0; j < WW; ++j) {
+                    rec[Lo::NXT + j] = acc[j];
+                    pbits[j] = acc[j];
+                }
+                app = true;
             }
         }
         wave_count_nodes<WW>(pbits, pdeg, cg, ct);
@@ -1130,7 +1217,7 @@ __device__ void plain_build_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, c
     const uint32_t nlen = C->nlen;
     if (tid == 0) s_arcs = 0;
     __syncthreads();
-    build_level<WW>(P, P.qb, nlen, blockIdx.x * kBlk, gridDim.x * kBlk, act, any_live, P.qa, &C->done_blocks,
+    build_level<WW, true>(P, P.qb, nlen, blockIdx.x * kBlk, gridDim.x * kBlk, act, any_live, P.qa, &C->done_blocks,
                     &C->clen, &s_arcs);
     __syncthreads();
     if (tid == 0 && s_arcs) atomicAdd(&C->acc_arcs, s_arcs);
@@ -2661,7 +2748,7 @@ bc_status ensure_batched(Workspace& W_, const DevGraph& G, int want, hipStream_t
 // once, up to kCoopPerCu per compute unit (more make each grid barrier
 // slower than they make a level faster); 0 when the device cannot launch
 // the kernel cooperatively.
-constexpr int kCoopPerCu = 2;
+constexpr int kCoopPerCu = 1;
 
 template <int WW>
 int coop_grid() {
@@ -2673,9 +2760,7 @@ int coop_grid() {
         (void)hipGetLastError();
         return 0;
     }
-    int lim = kCoopPerCu;
-    if (const char* e = std::getenv("BC_COOP_PER_CU")) lim = std::max(1, std::atoi(e));
-    return std::min(per_cu, lim) * device_cus();
+    return std::min(per_cu, kCoopPerCu) * device_cus();
 }
 
 template <int WW>
@@ -2695,7 +2780,11 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
     SrcState* S = Wk.srcs.as<SrcState>();
     Ctl* C = Wk.ctl.as<Ctl>();
     uint32_t* hctl = Wk.hctl;
-    const int cgrid = graph_levels == 0 && nb > 0 ? coop_grid<WW>() : 0;
+    const int cgrid = graph_levels == -1 && nb > 0 ? coop_grid<WW>() : 0;
+    if (graph_levels == -1 && nb > 0 && cgrid == 0) {
+        set_error("this device cannot run the level loop as one cooperative launch");
+        return BC_EINVAL;
+    }
     if (cgrid > 0) {
         // every level of every batch in one cooperative launch
         BC_HIP(hipMemsetAsync(&C->err, 0, sizeof(uint32_t), s));
@@ -2774,7 +2863,9 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
             if (pull) {
                 k_plain_pull<WW><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
             } else {
-                k_plain_expand<WW><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
+                // one workgroup per claimed chunk, up to 8 per compute unit
+                const int64_t chunks = ((int64_t)flen + expand_chunk(flen, fa) - 1) / expand_chunk(flen, fa);
+                k_plain_expand<WW><<<clamp_grid(chunks * kBlk, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
                 // new nodes <= arcs out of the frontier
                 k_plain_count<WW><<<clamp_grid((int64_t)std::min<unsigned long long>(fa, (unsigned long long)n),
                                                4 * cus), kBlk, 0, s>>>(P, S, C, T, d_st, W, 0);
@@ -3309,7 +3400,8 @@ bc_status run_topk_static(bc_graph* g, int32_t k, int32_t* ids, uint64_t* farnes
             if (pull) {
                 k_plain_pull<1><<<clamp_grid(n, 8 * cus), kBlk, 0, s>>>(G, P, S, C, T, d_st, W, 0);
             } else {
-                k_plain_expand<1><<<clamp_grid(flen, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
+                const int64_t chunks = ((int64_t)flen + expand_chunk(flen, fa) - 1) / expand_chunk(flen, fa);
+                k_plain_expand<1><<<clamp_grid(chunks * kBlk, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
                 k_plain_count<1><<<clamp_grid((int64_t)std::min<unsigned long long>(fa, (unsigned long long)n), 4 * cus),
                                    kBlk, 0, s>>>(P, S, C, T, d_st, W, 0);
             }

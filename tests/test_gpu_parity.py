@@ -37,7 +37,7 @@ VARIANTS = [
     dict(mode="plain", width=64, graph_levels=4),                     # captured level steps
     dict(mode="batched", width=128, defer_arcs=40, graph_levels=3),
     dict(mode="plain", width=256, pull_alpha=1e9, pull_beta=1e-9, graph_levels=2),
-    dict(mode="plain", width=64, graph_levels=-1),                    # one host round trip per level
+    dict(mode="plain", width=64, graph_levels=-1),                    # one cooperative launch
     dict(mode="batched", width=64, defer_arcs=1, graph_levels=-1),
 ]
 
@@ -130,8 +130,8 @@ LOOP_GRAPHS = [lambda: synth.barabasi_albert(3000, 4, 21), lambda: synth.grid_sh
 
 @pytest.mark.parametrize("gi", range(len(LOOP_GRAPHS)))
 def test_level_loops_agree(gi):
-    """The three drivers of the level-synchronous batches (one cooperative
-    launch, one host round trip per level, captured level steps) run the same
+    """The three drivers of the level-synchronous batches (one host round
+    trip per level, one cooperative launch, captured level steps) run the same
     level steps: the same answer everywhere, and in plain mode, where each
     batch starts from the state the previous one left, the same counters."""
     g = LOOP_GRAPHS[gi]()

@@ -279,6 +279,44 @@ __device__ inline void append_if(bool app, int32_t w, int32_t* list, uint32_t* c
     if (app) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = w;
 }
 
+// Workgroup-aggregated append of w[u] where app[u] holds, u < N: one atomic
+// on the global counter per workgroup and call instead of one per wave (the
+// level-synchronous kernels' counters are single words that every wave of
+// the grid would otherwise hit).  sh: B / 64 + 1 words of LDS.  Call with
+// the whole workgroup.
+template <int B, int N>
+__device__ inline void block_append(const bool* app, const int32_t* w, int32_t* list, uint32_t* ctr, uint32_t* sh) {
+    const int lane = (int)lane_id();
+    const int wave = threadIdx.x >> 6;
+    unsigned long long bal[N];
+    uint32_t wc = 0;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        bal[u] = __ballot(app[u]);
+        wc += (uint32_t)__popcll(bal[u]);
+    }
+    if (lane == 0) sh[wave] = wc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < B / 64; ++i) {
+            const uint32_t x = sh[i];
+            sh[i] = t;
+            t += x;
+        }
+        sh[B / 64] = t ? atomicAdd(ctr, t) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = sh[B / 64] + sh[wave];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        if (app[u]) list[pos + (uint32_t)__popcll(bal[u] & lt)] = w[u];
+        pos += (uint32_t)__popcll(bal[u]);
+    }
+    __syncthreads();  // sh is reused by the next call
+}
+
 // gamma(b) += 1 and tgamma(b) += deg for every bit b of `bits` (word j)
 __device__ inline void count_new(uint64_t bits, int j, uint32_t deg, uint32_t* cg, unsigned long long* ct) {
     while (bits) {
@@ -451,10 +489,10 @@ struct LdsExpand {
 // target loads before it visits any target's record: two in the
 // level-synchronous kernel, one in the persistent kernels, where the second
 // arc's registers cost more than its overlap gains.
-template <int WW, int B = kBlk, int kArcs = 2>
+template <int WW, int B = kBlk, int kArcs = 2, bool kBlockAppend = false>
 __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32_t* F, uint32_t e0, uint32_t e1,
                                const uint64_t* act, int32_t* N, uint32_t* nctr, uint32_t stamp, LdsExpand<WW, B>& L,
-                               unsigned long long* arcs, unsigned long long* entries) {
+                               unsigned long long* arcs, unsigned long long* entries, uint32_t* bsh = nullptr) {
     using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     const uint32_t e = e0 + tid;
@@ -502,7 +540,8 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
                 w = G.col[L.beg[i] + (int32_t)(a - L.off[i])];
                 app = visit<WW>(&P.ns[(size_t)w * Lo::SW], &L.m[i * WW], stamp);
             }
-            append_if(app, w, N, nctr);
+            if constexpr (kBlockAppend) block_append<B, 1>(&app, &w, N, nctr, bsh);
+            else append_if(app, w, N, nctr);
         }
     } else {
         for (uint32_t a0 = 0; a0 < total; a0 += kArcs * B) {
@@ -530,8 +569,12 @@ __device__ void expand_entries(const DevGraph& G, const SlotPtrs& P, const int32
 #pragma unroll
             for (int u = 0; u < kArcs; ++u)
                 if (app[u]) app[u] = visit<WW>(&P.ns[(size_t)w[u] * Lo::SW], &L.m[own[u] * WW], stamp);
+            if constexpr (kBlockAppend) {
+                block_append<B, kArcs>(app, w, N, nctr, bsh);
+            } else {
 #pragma unroll
-            for (int u = 0; u < kArcs; ++u) append_if(app[u], w[u], N, nctr);
+                for (int u = 0; u < kArcs; ++u) append_if(app[u], w[u], N, nctr);
+            }
         }
     }
     if (tid == 0) *arcs += total;
@@ -561,7 +604,7 @@ __device__ inline void clear_cur(const SlotPtrs& P, const int32_t* F, uint32_t l
 template <int WW, bool kFresh = false>
 __device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, uint32_t first, uint32_t stride,
                             const uint64_t* act, bool any_live, int32_t* F, uint32_t* fctr, uint32_t* clen,
-                            unsigned long long* arcs, uint32_t* seen_filter = nullptr) {
+                            unsigned long long* arcs, uint32_t* seen_filter = nullptr, uint32_t* bsh = nullptr) {
     using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     unsigned long long my_arcs = 0;
@@ -611,8 +654,15 @@ __device__ void build_level(const SlotPtrs& P, const int32_t* N, uint32_t len, u
             }
         }
         if (any_live) {
-            append_if(keep, w, F, fctr);
-            append_if(fresh, w, P.clr, clen);
+            if constexpr (kFresh) {
+                // a kernel of its own over the whole grid: one global atomic
+                // per workgroup and list (kBlk threads)
+                block_append<kBlk, 1>(&keep, &w, F, fctr, bsh);
+                block_append<kBlk, 1>(&fresh, &w, P.clr, clen, bsh);
+            } else {
+                append_if(keep, w, F, fctr);
+                append_if(fresh, w, P.clr, clen);
+            }
         }
     }
     if (my_arcs) atomicAdd(arcs, my_arcs);
@@ -978,7 +1028,8 @@ __host__ __device__ inline uint32_t expand_chunk(uint32_t flen, unsigned long lo
 
 template <int WW>
 __device__ void plain_expand_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, QStats* st, LdsExpand<WW>& L,
-                                  uint64_t* s_act, unsigned long long& s_arcs, unsigned long long& s_ent) {
+                                  uint64_t* s_act, unsigned long long& s_arcs, unsigned long long& s_ent,
+                                  uint32_t* bsh) {
     const uint32_t flen = C->flen, stamp = C->stamp;
     const uint32_t per = expand_chunk(flen, C->front_arcs);
     const int tid = threadIdx.x;
@@ -994,8 +1045,8 @@ __device__ void plain_expand_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, 
         const unsigned long long e0 = (unsigned long long)L.chunk * per;
         __syncthreads();
         if (e0 >= flen) break;
-        expand_entries<WW>(G, P, P.qa, (uint32_t)e0, min(flen, (uint32_t)e0 + per), s_act, P.qb, &C->nlen, stamp, L,
-                           &s_arcs, &s_ent);
+        expand_entries<WW, kBlk, 2, true>(G, P, P.qa, (uint32_t)e0, min(flen, (uint32_t)e0 + per), s_act, P.qb,
+                                          &C->nlen, stamp, L, &s_arcs, &s_ent, bsh);
     }
     if (tid == 0 && s_arcs) atomicAdd(&st->node_arcs, s_arcs);
     if (tid == 0 && s_ent) atomicAdd(&st->frontier_entries, s_ent);
@@ -1007,7 +1058,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_expand(DevGraph G, SlotPtrs P, C
     __shared__ LdsExpand<WW> L;
     __shared__ uint64_t s_act[4];
     __shared__ unsigned long long s_arcs, s_ent;
-    plain_expand_body<WW>(G, P, C, st, L, s_act, s_arcs, s_ent);
+    __shared__ uint32_t bsh[kBlk / 64 + 1];
+    plain_expand_body<WW>(G, P, C, st, L, s_act, s_arcs, s_ent, bsh);
 }
 
 // After a push step: the per-source counters of the level from its list of
@@ -1074,7 +1126,7 @@ __device__ inline uint64_t wave_or(uint64_t x) {
 template <int WW>
 __device__ void plain_pull_body(const DevGraph& G, const SlotPtrs& P, SrcState* S, Ctl* C, const TopKDev& T,
                                 QStats* st, int W, uint32_t* cg, unsigned long long* ct, CutLds& CL,
-                                uint32_t& s_last, uint64_t* s_act) {
+                                uint32_t& s_last, uint64_t* s_act, uint32_t* bsh) {
     using Lo = Layout<WW>;
     const int tid = threadIdx.x;
     const int lane = (int)lane_id();
@@ -1177,7 +1229,7 @@ __device__ void plain_pull_body(const DevGraph& G, const SlotPtrs& P, SrcState* 
             }
         }
         wave_count_nodes<WW>(pbits, pdeg, cg, ct);
-        append_if(app, w, P.qb, &C->nlen);
+        block_append<kBlk, 1>(&app, &w, P.qb, &C->nlen, bsh);
     }
     if (scanned) atomicAdd(&st->node_arcs, scanned);
     __syncthreads();
@@ -1193,7 +1245,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_pull(DevGraph G, SlotPtrs P, Src
     __shared__ CutLds CL;
     __shared__ uint32_t s_last;
     __shared__ uint64_t s_act[4];
-    plain_pull_body<WW>(G, P, S, C, T, st, W, cg, ct, CL, s_last, s_act);
+    __shared__ uint32_t bsh[kBlk / 64 + 1];
+    plain_pull_body<WW>(G, P, S, C, T, st, W, cg, ct, CL, s_last, s_act, bsh);
 }
 
 template <int WW>
@@ -1208,7 +1261,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_clearcur(SlotPtrs P, Ctl* C, int
 // done_blocks word counts the new frontier entries.
 template <int WW>
 __device__ void plain_build_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, const LevelParams& lp,
-                                 uint32_t& s_last, unsigned long long& s_arcs) {
+                                 uint32_t& s_last, unsigned long long& s_arcs, uint32_t* bsh) {
     const int tid = threadIdx.x;
     uint64_t act[WW];
 #pragma unroll
@@ -1218,7 +1271,7 @@ __device__ void plain_build_body(const DevGraph& G, const SlotPtrs& P, Ctl* C, c
     if (tid == 0) s_arcs = 0;
     __syncthreads();
     build_level<WW, true>(P, P.qb, nlen, blockIdx.x * kBlk, gridDim.x * kBlk, act, any_live, P.qa, &C->done_blocks,
-                    &C->clen, &s_arcs);
+                          &C->clen, &s_arcs, nullptr, bsh);
     __syncthreads();
     if (tid == 0 && s_arcs) atomicAdd(&C->acc_arcs, s_arcs);
     __threadfence();
@@ -1252,7 +1305,8 @@ __global__ __launch_bounds__(kBlk) void k_plain_build(DevGraph G, SlotPtrs P, Ct
     if (gated && C->ran == 0) return;
     __shared__ uint32_t s_last;
     __shared__ unsigned long long s_arcs;
-    plain_build_body<WW>(G, P, C, lp, s_last, s_arcs);
+    __shared__ uint32_t bsh[kBlk / 64 + 1];
+    plain_build_body<WW>(G, P, C, lp, s_last, s_arcs, bsh);
 }
 
 // End of a batch: reset seen and cur of every node the batch reached (nxt
@@ -1304,6 +1358,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_coop(DevGraph G, const int32_t* 
     __shared__ uint32_t s_last, s_flen;
     __shared__ unsigned long long s_arcs, s_ent;
     __shared__ uint64_t s_act[4];
+    __shared__ uint32_t bsh[kBlk / 64 + 1];
     const uint32_t n = (uint32_t)G.n;
     for (uint32_t b = b0; b < b0 + nb; ++b) {
         if (blockIdx.x == 0) plain_init_body<WW>(G, order, count, b, W, P, S, C, T, st, CL, s_flen, s_arcs, s_act);
@@ -1317,10 +1372,10 @@ __global__ __launch_bounds__(kBlk) void k_plain_coop(DevGraph G, const int32_t* 
             }
             if (!live) break;
             if (pull) {
-                plain_pull_body<WW>(G, P, S, C, T, st, W, cg, ct, CL, s_last, s_act);
+                plain_pull_body<WW>(G, P, S, C, T, st, W, cg, ct, CL, s_last, s_act, bsh);
                 grid_barrier(grid);
             } else {
-                plain_expand_body<WW>(G, P, C, st, L, s_act, s_arcs, s_ent);
+                plain_expand_body<WW>(G, P, C, st, L, s_act, s_arcs, s_ent, bsh);
                 grid_barrier(grid);
                 if (ldu32(&C->nlen) > n) {
                     bad = true;
@@ -1335,7 +1390,7 @@ __global__ __launch_bounds__(kBlk) void k_plain_coop(DevGraph G, const int32_t* 
             }
             clear_cur<WW>(P, P.qa, ldu32(&C->flen), blockIdx.x * kBlk, gridDim.x * kBlk);
             grid_barrier(grid);
-            plain_build_body<WW>(G, P, C, lp, s_last, s_arcs);
+            plain_build_body<WW>(G, P, C, lp, s_last, s_arcs, bsh);
             grid_barrier(grid);
         }
         if (bad) {

@@ -138,7 +138,8 @@ typedef struct bc_opts {
                                1 = move every batch to the records after its first level,
                                a testing aid for the record path)                       */
     int32_t defer_width;    /* BC_MODE_BATCHED: sources per batch of the re-run of deferred
-                               sources, 64, 128 or 256 (0 = 256)                         */
+                               sources, 64, 128 or 256 (0: the narrowest of them that
+                               holds every deferred source in one batch, else 256)       */
     const float* mlp;       /* BC_ORDER_LEARNED: host, BC_MLP_PARAMS floats              */
     int32_t graph_levels;   /* level-synchronous batches: 0 (the default) makes one host
                                round trip per level; 1..64 captures that many level steps

@@ -3048,8 +3048,11 @@ bc_status run_ww(bc_graph* g, int32_t k, const bc_opts& o, const int32_t* d_orde
         BC_HIP(hipStreamSynchronize(s));
         if (ndef > 0) {
             // deferred sources, restarted level-synchronously against the
-            // final-ish threshold, in batches of defer_width sources
-            const int dw = o.defer_width > 0 ? o.defer_width : 256;
+            // final-ish threshold, in batches of defer_width sources (by
+            // default the narrowest width that holds them all in one batch,
+            // else 256: a wide batch shares each full-graph level sweep among
+            // more sources, a narrow one moves smaller node records)
+            const int dw = o.defer_width > 0 ? o.defer_width : (ndef <= 64 ? 64 : (ndef <= 128 ? 128 : 256));
             const int32_t* dl = Wk.defer.as<int32_t>();
             const uint32_t dnb = (ndef + (uint32_t)dw - 1) / (uint32_t)dw;
             if (dw == W) {

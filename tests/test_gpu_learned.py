@@ -201,7 +201,8 @@ def test_learned_order_gain(gi):
         ref = oracle.topk(g, 100, nthreads=8)
         for order in ("learned", "learned_grouped"):
             a = G.topk(100, mode="batched", order=order)
-            assert a.ids.tolist() == ref["ids"].tolist()
+            assert a.ids.tolist() == ref["ids"].tolist(), order
+            assert a.farness.tolist() == ref["f"].tolist() and a.reach.tolist() == ref["r"].tolist(), order
 
 
 def test_learned_grouped_falls_back_to_degree_order_on_directed_graphs():

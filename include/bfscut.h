@@ -260,7 +260,10 @@ bc_status bc_graph_csr(const bc_graph* g, int32_t* row_ptr, int32_t* col);
  * The caller owns every output array.  Blocking.  Several calls may run on
  * one graph at the same time from different threads (each call allocates its
  * own working memory).  Errors: BC_EINVAL (k <= 0, NULL outputs, bad opts),
- * BC_ENOMEM, BC_EDEVICE.
+ * BC_ENOMEM, BC_EDEVICE.  With the environment variable BC_CHECK_LISTS=1
+ * (a debugging aid), the host-driven level loop also copies the frontier
+ * and reset lists after every level and fails with BC_EDEVICE if an entry
+ * is not a node id.
  */
 bc_status bc_topk(bc_graph* g, int32_t k, const bc_opts* opts, int32_t* ids, uint64_t* farness,
                   uint32_t* reach, int32_t* count, bc_stats* stats);

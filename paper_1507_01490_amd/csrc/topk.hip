@@ -2818,10 +2818,39 @@ int coop_grid() {
     return std::min(per_cu, kCoopPerCu) * device_cus();
 }
 
+// Debugging aid of the host-driven level loop (environment variable
+// BC_CHECK_LISTS=1): after every level, copy the frontier and reset lists to
+// the host and check that every listed id is a node (the lengths are checked
+// on every run).  A violation fails the query before any kernel indexes
+// the records with a bad id.
+bool check_lists_enabled() {
+    const char* e = std::getenv("BC_CHECK_LISTS");
+    return e && e[0] == '1';
+}
+
+bc_status check_level_lists(const SlotPtrs& P, uint32_t flen, uint32_t clen, int32_t n, uint32_t level,
+                            hipStream_t s) {
+    std::vector<int32_t> h(std::max(flen, clen));
+    const std::pair<const int32_t*, uint32_t> lists[2] = {{P.qa, flen}, {P.clr, clen}};
+    for (int l = 0; l < 2; ++l) {
+        if (lists[l].second == 0) continue;
+        BC_HIP(hipMemcpyAsync(h.data(), lists[l].first, sizeof(int32_t) * lists[l].second, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
+        for (uint32_t i = 0; i < lists[l].second; ++i)
+            if (h[i] < 0 || h[i] >= n) {
+                set_error("internal: level %u %s list entry %u is %d, not a node of 0..%d", level,
+                          l == 0 ? "frontier" : "reset", i, h[i], n - 1);
+                return BC_EDEVICE;
+            }
+    }
+    return BC_OK;
+}
+
 template <int WW>
 bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count, uint32_t nb, Workspace& Wk,
                             TopKDev T, QStats* d_st, const LevelParams& lp, hipStream_t s, double* ms,
                             int graph_levels) {
+    const bool check_lists = check_lists_enabled();
     const int W = 64 * WW;
     const int32_t n = G.n;
     const int cus = device_cus();
@@ -2910,6 +2939,7 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
             }
             unsigned long long fa;
             std::memcpy(&fa, hctl + 10, sizeof(fa));
+            if (check_lists) BC_TRY(check_level_lists(P, flen, hctl[3], n, hctl[0], s));
             if (!live) break;
             if (gh.exec) {
                 BC_HIP(hipGraphLaunch(gh.exec, s));

@@ -150,6 +150,22 @@ def test_level_loops_agree(gi):
                         assert len(set(vals)) == 1, (gi, k, kw, key, vals)
 
 
+def test_level_list_checks(monkeypatch):
+    """With BC_CHECK_LISTS=1 the host-driven level loop copies the frontier
+    and reset lists after every level and checks every id against n; the
+    queries (plain mode, and the seed batches and deferred re-run of the
+    batched mode) pass the check and still equal the oracle."""
+    monkeypatch.setenv("BC_CHECK_LISTS", "1")
+    for g in (synth.path(9), synth.star(12), synth.empty(5), synth.barabasi_albert(3000, 4, 31),
+              synth.rmat(11, 8, 0.57, 0.19, 0.19, 32)):
+        with bc.Graph(g.row_ptr, g.col, directed=g.directed) as G:
+            for k in (1, 10):
+                ref = oracle.topk(g, k)
+                for kw in (dict(mode="plain", width=64), dict(mode="plain", width=256, pull_alpha=1e9, pull_beta=1e-9),
+                           dict(mode="batched", width=64, defer_arcs=1)):
+                    assert_same(G.topk(k, **kw), ref, (g.n, k, kw))
+
+
 def test_reach_data_matches_oracle():
     for seed in range(4):
         g = synth.random_small(300, 0.006 + 0.002 * seed, True, 77 + seed)

@@ -47,12 +47,13 @@ def cpu_sample(name: str):
     """(graph, description) of the bounded sample the CPU oracle is timed on
     when the full workload takes it much longer than ~30 s: the same
     generator at a smaller size.  None when the full workload is the sample."""
+    # sized for roughly 10-20 s of the 16-thread oracle
     if name == "rmat21":
-        return (synth.rmat(18, 16, 0.57, 0.19, 0.19, 2),
-                "directed R-MAT scale=18 edge_factor=16 (0.57,0.19,0.19,0.05) dedup seed=2, same generator")
+        return (synth.rmat(20, 16, 0.57, 0.19, 0.19, 2),
+                "directed R-MAT scale=20 edge_factor=16 (0.57,0.19,0.19,0.05) dedup seed=2, same generator")
     if name == "collab":
-        return (synth.collaboration(100_000, 25_000, 2.1, 200, 4),
-                "collaboration projection actors=100000 groups=25000 zipf=2.1 cap=200 seed=4, same generator")
+        return (synth.collaboration(250_000, 62_500, 2.1, 200, 4),
+                "collaboration projection actors=250000 groups=62500 zipf=2.1 cap=200 seed=4, same generator")
     return None
 
 

@@ -286,6 +286,11 @@ bc_status devq_collect(DevQueue* q, QueueJob* j, int32_t* ids, uint64_t* farness
 void devq_release(DevQueue* q, QueueJob* j);
 void devq_free(QueueJob* j);  // memory of an entry whose queue is gone
 bc_status devq_pump(DevQueue* q);
+// A lane brackets device work of its own with these while a queue exists:
+// the pump then lets a long-running launch end so that this work, which may
+// share a hardware queue with it, can run.
+void devq_wait_begin(DevQueue* q);
+void devq_wait_end(DevQueue* q);
 // Publish the rest of a request once its seed batches have finished (true
 // when it did); launch and published-batch counts for the server's report.
 bool devq_advance(DevQueue* q, QueueJob* j);

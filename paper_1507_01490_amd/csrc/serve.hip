@@ -249,6 +249,8 @@ void lane_main(bc_server* S, int lane) {
         r->t_start = S->now_ms();
         ++S->running;
         const bool to_queue = r->to_queue;
+        // device work of this lane may wait behind a running queue launch
+        DevQueue* qw = S->q;
         lk.unlock();
 
         bc_status rs = BC_OK;
@@ -256,11 +258,13 @@ void lane_main(bc_server* S, int lane) {
         if (upload) {
             bc_graph* g = nullptr;
             try {
+                devq_wait_begin(qw);
                 rs = graph_create(G->n, G->m, G->rp.data(), G->m ? G->col.data() : nullptr, G->flags, st, true, &g);
             } catch (...) {
                 set_error("internal error");
                 rs = BC_EDEVICE;
             }
+            devq_wait_end(qw);
             if (rs != BC_OK) err = bc_last_error();
             lk.lock();
             G->loading = false;
@@ -304,12 +308,14 @@ void lane_main(bc_server* S, int lane) {
                 err = bc_last_error();
             } else {
                 try {
+                    devq_wait_begin(qw);
                     rs = run_topk(G->g, r->k, r->o, r->ids.data(), r->far.data(), r->reach.data(), &r->count, &r->st,
                                   st, true);
                 } catch (...) {
                     set_error("internal error");
                     rs = BC_EDEVICE;
                 }
+                devq_wait_end(qw);
                 if (rs != BC_OK) err = bc_last_error();
             }
         }

@@ -3860,6 +3860,10 @@ struct DevQueue {
     uint32_t* stop = nullptr;
     char* dhost = nullptr;           // the same block as the device addresses it
     unsigned long long launches = 0;
+    int waiters = 0;                 // lanes waiting for device work of their own (atomic builtins)
+    long long wait_since = 0;        // steady-clock ns when the count last left zero (atomic builtins)
+    bool yielding = false;           // stop raised to let a launch end for a waiting lane
+    std::chrono::steady_clock::time_point t_launch{};
     DevBuf ctr, claim, ns, qa, qb, clr, stamps;
     std::mutex mu;
     std::condition_variable cv;
@@ -3920,15 +3924,44 @@ void launch_queue(DevQueue* q) {
     k_jobs<WW, kBatchBlk><<<q->slots, kBatchBlk, 0, q->stream>>>(L, base, q->stamps.as<uint32_t>());
 }
 
+// A lane's own device work (an upload, a source order, a whole-request
+// query) goes to its stream, which may share a hardware queue with the
+// running launch and then waits until that launch ends.  Once a lane has
+// waited this long, and the launch has run at least as long, the launch is
+// told to stop claiming (its workgroups finish their batches and leave) and
+// is started again afterwards.
+constexpr auto kQueueYield = std::chrono::milliseconds(2);
+
+static long long steady_ns() {
+    return (long long)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
 // Launch the kernel when work is published and no launch is running
 // (caller holds q->mu).  A running launch keeps its workgroups while a
-// request is in flight and ends a few milliseconds after the last one.
+// batch of it runs and ends a few milliseconds after the last one, or
+// yields to a waiting lane.
 bc_status pump_locked(DevQueue* q) {
     if (q->launched) {
         const hipError_t e = hipEventQuery(q->ev);
-        if (e == hipErrorNotReady) return BC_OK;
+        if (e == hipErrorNotReady) {
+            const long long yield_ns = std::chrono::nanoseconds(kQueueYield).count();
+            if (!q->yielding && __atomic_load_n(&q->waiters, __ATOMIC_ACQUIRE) > 0 &&
+                steady_ns() - __atomic_load_n(&q->wait_since, __ATOMIC_ACQUIRE) > yield_ns &&
+                std::chrono::steady_clock::now() - q->t_launch > kQueueYield) {
+                __atomic_store_n(q->stop, 1u, __ATOMIC_RELEASE);
+                q->yielding = true;
+            }
+            return BC_OK;
+        }
         BC_HIP(e);
         q->launched = false;
+        if (q->yielding) {
+            // the launch has ended: published batches not yet claimed go to the next one
+            __atomic_store_n(q->stop, 0u, __ATOMIC_RELEASE);
+            q->yielding = false;
+        }
     }
     bool pending = false;
     for (int i = 0; i < kQueueCap && !pending; ++i) pending = q->busy[(size_t)i] != 0;
@@ -3939,6 +3972,7 @@ bc_status pump_locked(DevQueue* q) {
     BC_HIP(hipGetLastError());
     BC_HIP(hipEventRecord(q->ev, q->stream));
     q->launched = true;
+    q->t_launch = std::chrono::steady_clock::now();
     ++q->launches;
     return BC_OK;
 }
@@ -4045,6 +4079,14 @@ bc_status devq_create(int W, int32_t ncap, int slots, DevQueue** out, uint64_t* 
     return BC_OK;
 }
 
+void devq_wait_begin(DevQueue* q) {
+    if (q && __atomic_fetch_add(&q->waiters, 1, __ATOMIC_ACQ_REL) == 0)
+        __atomic_store_n(&q->wait_since, steady_ns(), __ATOMIC_RELEASE);
+}
+void devq_wait_end(DevQueue* q) {
+    if (q) __atomic_fetch_sub(&q->waiters, 1, __ATOMIC_ACQ_REL);
+}
+
 void devq_destroy(DevQueue* q) {
     if (!q) return;
     __atomic_store_n(q->stop, 1u, __ATOMIC_RELEASE);
@@ -4074,8 +4116,16 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
     BC_TRY(j->ring.alloc_on(sizeof(ThRec) * ((size_t)n + 1), prep));
     BC_TRY(j->state.alloc_on(sbytes, prep));
     BC_HIP(hipMemsetAsync(j->state.p, 0, sbytes, prep));
-    if (j->kk > 0) BC_TRY(build_order(g, o, j->kk, j->order.as<int32_t>(), prep));
-    BC_HIP(hipStreamSynchronize(prep));
+    {
+        // the order is device work on the lane's stream (see kQueueYield)
+        devq_wait_begin(q);
+        bc_status rs = BC_OK;
+        if (j->kk > 0) rs = build_order(g, o, j->kk, j->order.as<int32_t>(), prep);
+        const hipError_t se = hipStreamSynchronize(prep);
+        devq_wait_end(q);
+        BC_TRY(rs);
+        BC_HIP(se);
+    }
     j->nb = (uint32_t)((n + W - 1) / W);
     j->seed = std::min<uint32_t>(j->nb, (uint32_t)((j->kk + W - 1) / W));
     j->rest_pending = j->seed < j->nb;

@@ -170,6 +170,9 @@ struct bc_graph {
     bool have_order_loc[3] = {false, false, false};
     bc::DevBuf feat, core;  // learned-order features (n x 3 float) and core numbers, built on first use
     bool have_feat = false;
+    bc::DevBuf order_lrn;                 // cached order by decreasing perceptron score, for lrn_params
+    std::vector<float> lrn_params;        // the parameters it was scored with (the first set asked for)
+    bool have_order_lrn = false;
     int core_sweeps = 0;
     hipStream_t stream = nullptr;
     double preprocess_ms = 0.0;
@@ -225,7 +228,12 @@ bc_status order_given(bc_graph* g, const int32_t* h_perm, int32_t* d_order, hipS
 // (caller_ids: h_first holds the caller's ids, else ids of the graph's own numbering)
 bc_status order_front(bc_graph* g, const int32_t* h_first, int32_t nf, int32_t* d_order, hipStream_t s,
                       bool caller_ids = true);
-bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order, hipStream_t s);
+// The sources by decreasing perceptron score (ties by degree, then id) for
+// the host parameters h_params; cached per graph for the first parameter set.
+bc_status order_learned(bc_graph* g, const float* h_params, int32_t* d_order, hipStream_t s);
+// The first `head` entries of the device order d_by_score, then every other
+// source in the grouped degree order.
+bc_status order_head_grouped(bc_graph* g, const int32_t* d_by_score, int32_t head, int32_t* d_order, hipStream_t s);
 bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s);
 
 // Learned order (learned.hip): features cached in g->feat / g->core; the

@@ -10,6 +10,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstring>
 #include <chrono>
 
 #include "bc_internal.h"
@@ -770,25 +771,66 @@ bc_status order_by_scores(bc_graph* g, const float* scores, bool scores_on_devic
     return BC_OK;
 }
 
-// The first `head` sources by decreasing device score, then every other
+// Score every source with the perceptron (features cached per graph) and
+// sort by decreasing score.  The order depends only on the graph and the
+// parameters, so the one for the first parameter set a graph is asked for is
+// kept, like the degree-based orders; it is never rebuilt, so a copy taken
+// from it on another stream cannot meet a rewrite.  Other parameter sets are
+// scored on every call.
+bc_status order_learned(bc_graph* g, const float* h_params, int32_t* d_order, hipStream_t s) {
+    const int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    BC_TRY(graph_features(g, s));
+    bool keep = false;
+    {
+        std::lock_guard<std::mutex> lk(g->cache_mu);
+        if (g->have_order_lrn &&
+            std::memcmp(g->lrn_params.data(), h_params, sizeof(float) * BC_MLP_PARAMS) == 0) {
+            BC_HIP(hipMemcpyAsync(d_order, g->order_lrn.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
+                                  s));
+            return BC_OK;
+        }
+        keep = !g->have_order_lrn;
+    }
+    // scored without the cache lock (the score order takes it for the degree order)
+    DevBuf prm, sc, ord;
+    BC_TRY(prm.alloc_on(sizeof(float) * BC_MLP_PARAMS, s));
+    BC_TRY(sc.alloc_on(sizeof(float) * (size_t)n, s));
+    BC_TRY(galloc(g, ord, sizeof(int32_t) * (size_t)n, s));
+    BC_HIP(hipMemcpyAsync(prm.p, h_params, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
+    BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
+    BC_TRY(order_by_scores(g, sc.as<float>(), true, ord.as<int32_t>(), s));  // returns with s drained
+    BC_HIP(hipMemcpyAsync(d_order, ord.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    if (keep) {
+        std::lock_guard<std::mutex> lk(g->cache_mu);
+        if (!g->have_order_lrn) {  // another thread may have kept its own meanwhile
+            g->order_lrn.swap(ord);
+            g->lrn_params.assign(h_params, h_params + BC_MLP_PARAMS);
+            g->have_order_lrn = true;
+            return BC_OK;
+        }
+    }
+    BC_HIP(hipStreamSynchronize(s));  // the copy has read ord before it is freed
+    return BC_OK;
+}
+
+// The first `head` sources of the score order d_by_score, then every other
 // source in the grouped degree order (relative order kept).
-bc_status order_head_grouped(bc_graph* g, const float* d_scores, int32_t head, int32_t* d_order,
+bc_status order_head_grouped(bc_graph* g, const int32_t* d_by_score, int32_t head, int32_t* d_order,
                              hipStream_t s) {
     int32_t n = g->dg.n;
     if (n == 0) return BC_OK;
     head = std::min(std::max(head, 0), n);
-    DevBuf by_score, grp, mark, keep, nsel, tmp;
-    BC_TRY(by_score.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    DevBuf grp, mark, keep, nsel, tmp;
     BC_TRY(grp.alloc_on(sizeof(int32_t) * (size_t)n, s));
     BC_TRY(mark.alloc_on((size_t)n, s));
     BC_TRY(keep.alloc_on((size_t)n, s));
     BC_TRY(nsel.alloc_on(sizeof(int32_t), s));
-    BC_TRY(order_by_scores(g, d_scores, true, by_score.as<int32_t>(), s));
     BC_TRY(order_grouped(g, grp.as<int32_t>(), s));
     BC_HIP(hipMemsetAsync(mark.p, 0, (size_t)n, s));
     if (head > 0) {
-        k_mark_head<<<grid_for(head), kBlk, 0, s>>>(head, by_score.as<int32_t>(), mark.as<uint8_t>());
-        BC_HIP(hipMemcpyAsync(d_order, by_score.p, sizeof(int32_t) * (size_t)head, hipMemcpyDeviceToDevice, s));
+        k_mark_head<<<grid_for(head), kBlk, 0, s>>>(head, d_by_score, mark.as<uint8_t>());
+        BC_HIP(hipMemcpyAsync(d_order, d_by_score, sizeof(int32_t) * (size_t)head, hipMemcpyDeviceToDevice, s));
     }
     k_keep_unmarked<<<grid_for(n), kBlk, 0, s>>>(n, grp.as<int32_t>(), mark.as<uint8_t>(), keep.as<uint8_t>());
     BC_TRY(cub_call([&](void* t, size_t& b) {

@@ -45,9 +45,9 @@ namespace bc {
 void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o, int32_t slots,
                uint64_t* graph_bytes, uint64_t* upload_bytes, uint64_t* query_bytes) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), M = (uint64_t)(m > 0 ? m : 0);
-    // out-CSR, arcs packed with target degrees, degree, reach pair, two cached
-    // orders, features and core numbers
-    uint64_t gb = 4 * (N + 1) + 4 * M + 8 * M + 4 * N + 8 * N + 8 * N + 16 * N;
+    // out-CSR, arcs packed with target degrees, degree, reach pair, three
+    // cached orders (degree, grouped, learned), features and core numbers
+    uint64_t gb = 4 * (N + 1) + 4 * M + 8 * M + 4 * N + 8 * N + 12 * N + 16 * N;
     if (directed) gb += 4 * (N + 1) + 4 * M;  // in-CSR
     else if (N >= 100000) gb += 8 * N;         // renumbering maps
     // upload: raw copy, sort buffers and component / SCC scratch; an
@@ -71,7 +71,7 @@ void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o,
                   + 4 * N + 64              // deferred sources
                   + 24 * N;                 // order sort temporaries
     if (o.mode == BC_MODE_BATCHED) qb += sl * per_slot + 4 * sl;
-    if (o.order == BC_ORDER_LEARNED || o.order == BC_ORDER_LEARNED_GROUPED) qb += 4 * N + 4 * BC_MLP_PARAMS + 16 * N;
+    if (o.order == BC_ORDER_LEARNED || o.order == BC_ORDER_LEARNED_GROUPED) qb += 8 * N + 4 * BC_MLP_PARAMS + 16 * N;
     *graph_bytes = gb;
     *upload_bytes = ub;
     *query_bytes = qb;
@@ -125,7 +125,7 @@ uint64_t queue_request_bytes(int32_t n, int32_t k, const bc_opts& o) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), kk = (uint64_t)(k > 0 ? k : 1);
     uint64_t b = 4 * N + 24 * (N + 1) + 512 + 32 * kk + 24 * N;
     if (o.order == BC_ORDER_LEARNED || o.order == BC_ORDER_LEARNED_GROUPED || o.order == BC_ORDER_LEARNED_LOCALITY)
-        b += 4 * N + 4 * BC_MLP_PARAMS + 16 * N;
+        b += 8 * N + 4 * BC_MLP_PARAMS + 16 * N;
     return b;
 }
 

@@ -3301,14 +3301,8 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
         BC_TRY(order_by_scores(g, o.scores, false, d_order, s));
     } else if (ord == BC_ORDER_LEARNED || ord == BC_ORDER_LEARNED_GROUPED || ord == BC_ORDER_LEARNED_LOCALITY) {
         if (!o.mlp) { set_error("learned orders need opts.mlp"); return BC_EINVAL; }
-        BC_TRY(graph_features(g, s));
-        DevBuf prm, sc;
-        BC_TRY(prm.alloc_on(sizeof(float) * BC_MLP_PARAMS, s));
-        BC_TRY(sc.alloc_on(sizeof(float) * (size_t)n, s));
-        BC_HIP(hipMemcpyAsync(prm.p, o.mlp, sizeof(float) * BC_MLP_PARAMS, hipMemcpyHostToDevice, s));
-        BC_TRY(mlp_forward(prm.as<float>(), g->feat.as<float>(), n, sc.as<float>(), s));
         if (ord == BC_ORDER_LEARNED) {
-            BC_TRY(order_by_scores(g, sc.as<float>(), true, d_order, s));
+            BC_TRY(order_learned(g, o.mlp, d_order, s));
         } else if (ord == BC_ORDER_LEARNED_LOCALITY) {
             // the k best-scored sources, then the locality order without them
             const SeedPlan sp = seed_plan(o, kk, n, W);
@@ -3316,7 +3310,7 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
                 std::min<int64_t>((int64_t)n, std::min<int64_t>((int64_t)sp.batches * sp.sw, (int64_t)kk));
             DevBuf bys;
             BC_TRY(bys.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
-            BC_TRY(order_by_scores(g, sc.as<float>(), true, bys.as<int32_t>(), s));
+            BC_TRY(order_learned(g, o.mlp, bys.as<int32_t>(), s));
             std::vector<int32_t> h((size_t)(head > 0 ? head : 1));
             if (head > 0) {
                 BC_HIP(hipMemcpyAsync(h.data(), bys.p, sizeof(int32_t) * (size_t)head, hipMemcpyDeviceToHost, s));
@@ -3331,7 +3325,10 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
             // highest-degree nodes
             const int64_t head =
                 std::min<int64_t>((int64_t)n, std::min<int64_t>((int64_t)sp.batches * sp.sw, (int64_t)kk));
-            BC_TRY(order_head_grouped(g, sc.as<float>(), (int32_t)head, d_order, s));
+            DevBuf bys;
+            BC_TRY(bys.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
+            BC_TRY(order_learned(g, o.mlp, bys.as<int32_t>(), s));
+            BC_TRY(order_head_grouped(g, bys.as<int32_t>(), (int32_t)head, d_order, s));
         }
     } else {
         set_error("unknown order %d", o.order);

@@ -218,3 +218,41 @@ def test_source_order_errors():
             G.source_order(3, width=32)
         with pytest.raises(ValueError):
             G.source_order(3, order=np.array([0, 1, 2]))
+
+
+def score_order(scores, deg_order):
+    """Decreasing score, ties in the degree order (a stable sort of it)."""
+    s = np.asarray(scores, np.float32)[deg_order]
+    return deg_order[np.argsort(-s, kind="stable")]
+
+
+@pytest.mark.parametrize("keep_ids", [True, False])
+def test_learned_order_per_parameter_set(keep_ids):
+    """The learned order is kept per graph for the first parameter set it is
+    asked for; a second set is scored on its own, the first is still served
+    afterwards, and each equals decreasing perceptron score over the degree
+    order, on a graph renumbered on upload too."""
+    import torch
+    g = synth.barabasi_albert(100_000, 4, 17)
+    rp, _ = canonical(g)
+    dego = degree_order(rp)
+    p1 = bc.default_mlp()
+    p2 = (p1 + np.random.default_rng(5).normal(0, 0.5, p1.shape)).astype(np.float32)
+    with bc.Graph(g.row_ptr, g.col, keep_ids=keep_ids) as G:
+        x, _ = G.features()
+        want = {}
+        for name, p in (("p1", p1), ("p2", p2)):
+            y = bc.mlp_forward(torch.from_numpy(p).cuda(), x.contiguous()).cpu().numpy()
+            want[name] = score_order(y, dego).tolist()
+        assert want["p1"] != want["p2"]
+        first = G.source_order(10, order="learned", mlp=p1).tolist()
+        assert first == want["p1"]
+        assert G.source_order(10, order="learned", mlp=p2).tolist() == want["p2"]
+        assert G.source_order(10, order="learned", mlp=p1).tolist() == want["p1"]
+        # the combined orders take their head from the same score order
+        head = G.source_order(100, order="learned_grouped", mlp=p2)[:100].tolist()
+        assert head == want["p2"][:100]
+        head = G.source_order(100, order="learned_locality", mlp=p1, width=64)[:100].tolist()
+        assert head == want["p1"][:100]
+    with bc.Graph(g.row_ptr, g.col, keep_ids=keep_ids) as G:
+        assert G.source_order(10, order="learned", mlp=p2).tolist() == want["p2"]

@@ -173,6 +173,10 @@ struct bc_graph {
     bc::DevBuf order_lrn;                 // cached order by decreasing perceptron score, for lrn_params
     std::vector<float> lrn_params;        // the parameters it was scored with (the first set asked for)
     bool have_order_lrn = false;
+    static constexpr int kLrnHeads = 4;   // learned head + grouped tail orders kept, per head length
+    bc::DevBuf order_lrn_head[kLrnHeads];
+    int32_t lrn_head[kLrnHeads] = {0, 0, 0, 0};
+    int n_lrn_heads = 0;
     int core_sweeps = 0;
     hipStream_t stream = nullptr;
     double preprocess_ms = 0.0;
@@ -234,6 +238,9 @@ bc_status order_learned(bc_graph* g, const float* h_params, int32_t* d_order, hi
 // The first `head` entries of the device order d_by_score, then every other
 // source in the grouped degree order.
 bc_status order_head_grouped(bc_graph* g, const int32_t* d_by_score, int32_t head, int32_t* d_order, hipStream_t s);
+// The `head` best-scored sources for h_params, then the grouped order; kept
+// per graph for the kept parameter set and up to kLrnHeads head lengths.
+bc_status order_learned_grouped(bc_graph* g, const float* h_params, int32_t head, int32_t* d_order, hipStream_t s);
 bc_status order_locality(bc_graph* g, int32_t B, int32_t* d_order, hipStream_t s);
 
 // Learned order (learned.hip): features cached in g->feat / g->core; the

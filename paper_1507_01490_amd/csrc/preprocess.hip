@@ -814,6 +814,51 @@ bc_status order_learned(bc_graph* g, const float* h_params, int32_t* d_order, hi
     return BC_OK;
 }
 
+// The learned head + grouped tail.  Like the score order it depends only on
+// the graph, the parameters and the head length (one per k), so for the kept
+// parameter set the first kLrnHeads head lengths asked for are kept; none is
+// ever rebuilt.  Other requests are merged per call.
+bc_status order_learned_grouped(bc_graph* g, const float* h_params, int32_t head, int32_t* d_order,
+                                hipStream_t s) {
+    const int32_t n = g->dg.n;
+    if (n == 0) return BC_OK;
+    auto kept_params = [&]() {
+        return g->have_order_lrn &&
+               std::memcmp(g->lrn_params.data(), h_params, sizeof(float) * BC_MLP_PARAMS) == 0;
+    };
+    {
+        std::lock_guard<std::mutex> lk(g->cache_mu);
+        if (kept_params()) {
+            for (int i = 0; i < g->n_lrn_heads; ++i) {
+                if (g->lrn_head[i] == head) {
+                    BC_HIP(hipMemcpyAsync(d_order, g->order_lrn_head[i].p, sizeof(int32_t) * (size_t)n,
+                                          hipMemcpyDeviceToDevice, s));
+                    return BC_OK;
+                }
+            }
+        }
+    }
+    DevBuf bys, out;
+    BC_TRY(bys.alloc_on(sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(galloc(g, out, sizeof(int32_t) * (size_t)n, s));
+    BC_TRY(order_learned(g, h_params, bys.as<int32_t>(), s));
+    BC_TRY(order_head_grouped(g, bys.as<int32_t>(), head, out.as<int32_t>(), s));  // returns with s drained
+    BC_HIP(hipMemcpyAsync(d_order, out.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    {
+        std::lock_guard<std::mutex> lk(g->cache_mu);
+        bool have = false;
+        for (int i = 0; i < g->n_lrn_heads; ++i) have = have || g->lrn_head[i] == head;
+        if (kept_params() && !have && g->n_lrn_heads < bc_graph::kLrnHeads) {
+            g->order_lrn_head[g->n_lrn_heads].swap(out);
+            g->lrn_head[g->n_lrn_heads] = head;
+            ++g->n_lrn_heads;
+            return BC_OK;
+        }
+    }
+    BC_HIP(hipStreamSynchronize(s));  // the copy has read out before it is freed
+    return BC_OK;
+}
+
 // The first `head` sources of the score order d_by_score, then every other
 // source in the grouped degree order (relative order kept).
 bc_status order_head_grouped(bc_graph* g, const int32_t* d_by_score, int32_t head, int32_t* d_order,

@@ -45,9 +45,10 @@ namespace bc {
 void footprint(int32_t n, int64_t m, bool directed, int32_t k, const bc_opts& o, int32_t slots,
                uint64_t* graph_bytes, uint64_t* upload_bytes, uint64_t* query_bytes) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), M = (uint64_t)(m > 0 ? m : 0);
-    // out-CSR, arcs packed with target degrees, degree, reach pair, three
-    // cached orders (degree, grouped, learned), features and core numbers
-    uint64_t gb = 4 * (N + 1) + 4 * M + 8 * M + 4 * N + 8 * N + 12 * N + 16 * N;
+    // out-CSR, arcs packed with target degrees, degree, reach pair, cached
+    // orders (degree, grouped, learned, up to four learned heads + grouped
+    // tail), features and core numbers
+    uint64_t gb = 4 * (N + 1) + 4 * M + 8 * M + 4 * N + 8 * N + 28 * N + 16 * N;
     if (directed) gb += 4 * (N + 1) + 4 * M;  // in-CSR
     else if (N >= 100000) gb += 8 * N;         // renumbering maps
     // upload: raw copy, sort buffers and component / SCC scratch; an

@@ -3325,10 +3325,7 @@ bc_status build_order(bc_graph* g, const bc_opts& o, int32_t kk, int32_t* d_orde
             // highest-degree nodes
             const int64_t head =
                 std::min<int64_t>((int64_t)n, std::min<int64_t>((int64_t)sp.batches * sp.sw, (int64_t)kk));
-            DevBuf bys;
-            BC_TRY(bys.alloc_on(sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s));
-            BC_TRY(order_learned(g, o.mlp, bys.as<int32_t>(), s));
-            BC_TRY(order_head_grouped(g, bys.as<int32_t>(), (int32_t)head, d_order, s));
+            BC_TRY(order_learned_grouped(g, o.mlp, (int32_t)head, d_order, s));
         }
     } else {
         set_error("unknown order %d", o.order);

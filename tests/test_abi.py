@@ -83,14 +83,14 @@ def test_footprint_arithmetic():
     n, m = 20000, 160000
     g, u, q_plain = bc.footprint(n, m, k=10, mode="plain")
     # undirected, below the renumbering size: CSR, packed arcs, per-node arrays
-    # (degree, reach pair, three cached orders, features and core numbers)
-    assert g == 4 * (n + 1) + 12 * m + 40 * n
+    # (degree, reach pair, seven cached orders, features and core numbers)
+    assert g == 4 * (n + 1) + 12 * m + 56 * n
     assert u == 12 * m + 40 * n + (1 << 20)
     # from 100,000 nodes: the two renumbering maps, and the first build held
     # while the renumbered one is made
     nb, mb = 200000, 1600000
     gb, ub, _ = bc.footprint(nb, mb)
-    assert gb == 4 * (nb + 1) + 12 * mb + 40 * nb + 8 * nb
+    assert gb == 4 * (nb + 1) + 12 * mb + 56 * nb + 8 * nb
     assert ub == 12 * mb + 40 * nb + (1 << 20) + gb + 16 * nb + 4 * mb
     per_slot = n * (8 * 4 + 12)
     _, _, q16 = bc.footprint(n, m, k=10, mode="batched", slots=16)

@@ -231,7 +231,8 @@ def test_learned_order_per_parameter_set(keep_ids):
     """The learned order is kept per graph for the first parameter set it is
     asked for; a second set is scored on its own, the first is still served
     afterwards, and each equals decreasing perceptron score over the degree
-    order, on a graph renumbered on upload too."""
+    order, on a graph renumbered on upload too.  The learned head + grouped
+    tail is the k best-scored sources, then the grouped order without them."""
     import torch
     g = synth.barabasi_albert(100_000, 4, 17)
     rp, _ = canonical(g)
@@ -249,7 +250,15 @@ def test_learned_order_per_parameter_set(keep_ids):
         assert first == want["p1"]
         assert G.source_order(10, order="learned", mlp=p2).tolist() == want["p2"]
         assert G.source_order(10, order="learned", mlp=p1).tolist() == want["p1"]
-        # the combined orders take their head from the same score order
+        # the combined orders take their head from the same score order; the
+        # learned head + grouped tail is kept for up to four head lengths (k
+        # here), a fifth is merged per call, and a repeat is served as kept
+        grp = G.source_order(10, order="grouped").tolist()
+        for k in (1, 10, 100, 200, 300, 10, 300):
+            o = G.source_order(k, order="learned_grouped", mlp=p1).tolist()
+            assert o[:k] == want["p1"][:k], k
+            hs = set(o[:k])
+            assert o[k:] == [v for v in grp if v not in hs], k
         head = G.source_order(100, order="learned_grouped", mlp=p2)[:100].tolist()
         assert head == want["p2"][:100]
         head = G.source_order(100, order="learned_locality", mlp=p1, width=64)[:100].tolist()

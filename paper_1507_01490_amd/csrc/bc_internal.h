@@ -306,6 +306,14 @@ bc_status devq_pump(DevQueue* q);
 // share a hardware queue with it, can run.
 void devq_wait_begin(DevQueue* q);
 void devq_wait_end(DevQueue* q);
+// Scope form of the pair (also ends the wait when the work throws).
+struct DevqWait {
+    DevQueue* q;
+    explicit DevqWait(DevQueue* q_) : q(q_) { devq_wait_begin(q); }
+    ~DevqWait() { devq_wait_end(q); }
+    DevqWait(const DevqWait&) = delete;
+    DevqWait& operator=(const DevqWait&) = delete;
+};
 // Publish the rest of a request once its seed batches have finished (true
 // when it did); launch and published-batch counts for the server's report.
 bool devq_advance(DevQueue* q, QueueJob* j);

@@ -259,13 +259,12 @@ void lane_main(bc_server* S, int lane) {
         if (upload) {
             bc_graph* g = nullptr;
             try {
-                devq_wait_begin(qw);
+                DevqWait wait(qw);
                 rs = graph_create(G->n, G->m, G->rp.data(), G->m ? G->col.data() : nullptr, G->flags, st, true, &g);
             } catch (...) {
                 set_error("internal error");
                 rs = BC_EDEVICE;
             }
-            devq_wait_end(qw);
             if (rs != BC_OK) err = bc_last_error();
             lk.lock();
             G->loading = false;
@@ -309,14 +308,13 @@ void lane_main(bc_server* S, int lane) {
                 err = bc_last_error();
             } else {
                 try {
-                    devq_wait_begin(qw);
+                    DevqWait wait(qw);
                     rs = run_topk(G->g, r->k, r->o, r->ids.data(), r->far.data(), r->reach.data(), &r->count, &r->st,
                                   st, true);
                 } catch (...) {
                     set_error("internal error");
                     rs = BC_EDEVICE;
                 }
-                devq_wait_end(qw);
                 if (rs != BC_OK) err = bc_last_error();
             }
         }

@@ -4112,11 +4112,10 @@ bc_status devq_submit(DevQueue* q, bc_graph* g, int32_t k, const bc_opts& o_in, 
     BC_HIP(hipMemsetAsync(j->state.p, 0, sbytes, prep));
     {
         // the order is device work on the lane's stream (see kQueueYield)
-        devq_wait_begin(q);
+        DevqWait wait(q);
         bc_status rs = BC_OK;
         if (j->kk > 0) rs = build_order(g, o, j->kk, j->order.as<int32_t>(), prep);
-        const hipError_t se = hipStreamSynchronize(prep);
-        devq_wait_end(q);
+        const hipError_t se = hipStreamSynchronize(prep);  // drained on failure too
         BC_TRY(rs);
         BC_HIP(se);
     }

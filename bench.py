@@ -166,7 +166,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "the multi-GPU sharding is a design in DESIGN.md and is not run.", file=sys.stderr)
+              "sharding sources over several GPUs is designed but not implemented, so no multi-GPU figure exists.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -678,6 +678,10 @@ def serve_bench(args, bc, workloads):
     res, span2 = run(times)
     same = all(a.ids.tolist() == b.ids.tolist() and a.farness.tolist() == b.farness.tolist()
                for a, b in zip(burst, res))
+    # visited arcs each request's searches scanned (GPU-counted m_vis; it
+    # depends a little on when each threshold was published, so per run)
+    mvis_burst = sum(int(r.stats["m_vis"]) for r in burst)
+    mvis_open = sum(int(r.stats["m_vis"]) for r in res)
     lat = np.array([r.info["finish_ms"] - r.info["submit_ms"] for r in res])
     wait = np.array([r.info["start_ms"] - r.info["submit_ms"] for r in res])
     svc = np.array([r.info["finish_ms"] - r.info["start_ms"] for r in res])
@@ -691,6 +695,10 @@ def serve_bench(args, bc, workloads):
                 service_p50_ms=round(float(np.percentile(svc, 50)), 2),
                 service_p99_ms=round(float(np.percentile(svc, 99)), 2),
                 capacity_rps=round(capacity, 3), offered_rps=round(rate, 3), load=args.load,
+                gteps_closed_loop=round(mvis_burst / span / 1e9, 2), gteps_open_loop=round(mvis_open / span2 / 1e9, 2),
+                work_m_vis=dict(closed_loop=mvis_burst, open_loop=mvis_open,
+                                kind="GPU-counted m_vis summed over the requests; the closed loop also uploads "
+                                     "the graphs the warm-up did not"),
                 same_results_burst_vs_poisson=bool(same), dtype="int64", data="synthetic",
                 config=dict(workload=workloads.DESCRIPTION["serve512"] if args.mix_count == 512 and args.mix_max_n == 2e5
                             else f"serving mix: {args.mix_count} graphs n~logU[1e3,{args.mix_max_n:g}] (ER deg 8 / BA m=4 / "

@@ -3822,8 +3822,10 @@ void multi_destroy(bc_multi* p) { delete p; }
 // as a workgroup is free, and its batches run beside theirs.  The last batch
 // of a request copies its list and statistics to the ring slot's result area
 // (pinned host memory) and raises its done flag; the host polls the flags.
-// The kernel ends after a bounded idle time with nothing to claim (or at
-// once when told to stop); the host launches it again when work is waiting.
+// The kernel ends after a bounded idle time with nothing to claim, or once
+// its batches end after it is told to stop: at shutdown, or to let a lane's
+// own device work that waits behind it run (kQueueYield).  The host launches
+// it again when work is waiting.
 
 struct QueueJob {
     int slot = -1;          // ring slot of the seed range (its done and seeded flags, its counters)

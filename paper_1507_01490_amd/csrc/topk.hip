@@ -2846,6 +2846,14 @@ bc_status check_level_lists(const SlotPtrs& P, uint32_t flen, uint32_t clen, int
     return BC_OK;
 }
 
+// Workgroups per compute unit of the host loop's grid-stride level kernels
+// other than push and pull (count, build and the clears).  Their lists are
+// often short, and every workgroup of a launch takes a device-wide counter
+// (the last one runs the level's cut step or publishes the list), so fewer
+// workgroups finish a level sooner: 1 per compute unit measured faster than
+// 2, 4 or 8 (BA n = 1M seed batches, R-MAT deferred re-runs).
+constexpr int kLevelGrid = 1;
+
 template <int WW>
 bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count, uint32_t nb, Workspace& Wk,
                             TopKDev T, QStats* d_st, const LevelParams& lp, hipStream_t s, double* ms,
@@ -2953,15 +2961,15 @@ bc_status run_plain_batches(const DevGraph& G, const int32_t* ord, int32_t count
                 k_plain_expand<WW><<<clamp_grid(chunks * kBlk, 8 * cus), kBlk, 0, s>>>(G, P, C, d_st, 0);
                 // new nodes <= arcs out of the frontier
                 k_plain_count<WW><<<clamp_grid((int64_t)std::min<unsigned long long>(fa, (unsigned long long)n),
-                                               4 * cus), kBlk, 0, s>>>(P, S, C, T, d_st, W, 0);
+                                               kLevelGrid * cus), kBlk, 0, s>>>(P, S, C, T, d_st, W, 0);
             }
-            k_plain_clearcur<WW><<<clamp_grid(flen, 4 * cus), kBlk, 0, s>>>(P, C, 0);
+            k_plain_clearcur<WW><<<clamp_grid(flen, kLevelGrid * cus), kBlk, 0, s>>>(P, C, 0);
             // reached nodes <= arcs out of the frontier (push) or n (pull)
             const int64_t bound =
                 pull ? (int64_t)n : (int64_t)std::min<unsigned long long>(fa, (unsigned long long)n);
-            k_plain_build<WW><<<clamp_grid(bound, 4 * cus), kBlk, 0, s>>>(G, P, C, lp, 0);
+            k_plain_build<WW><<<clamp_grid(bound, kLevelGrid * cus), kBlk, 0, s>>>(G, P, C, lp, 0);
         }
-        k_plain_clear<WW><<<clamp_grid(n, 4 * cus), kBlk, 0, s>>>(P, C);
+        k_plain_clear<WW><<<clamp_grid(n, kLevelGrid * cus), kBlk, 0, s>>>(P, C);
     }
     BC_HIP(hipEventRecord(ev.b, s));
     BC_HIP(hipGetLastError());

@@ -124,6 +124,11 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1507_01490_amd.build`")
+    # torch carries HIP runtime libraries of its own.  Loaded after this
+    # library has brought in the system's, they fail to find the GPU, and the
+    # torch tensors this binding hands out (features, scores) cannot be made;
+    # loaded first, both work side by side.  Importing torch touches no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     lib.bc_last_error.restype = ctypes.c_char_p

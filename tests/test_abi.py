@@ -37,6 +37,20 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_loading_the_library_imports_torch_first():
+    """torch's own HIP runtime libraries must be loaded before the library's
+    (the GPU test of the same name shows why); checked in a fresh process,
+    where nothing else imported torch, without a device call."""
+    import sys
+    code = ("import sys, ctypes\n"
+            "import paper_1507_01490_amd as bc\n"
+            "bc.load_library()\n"
+            "print('torch' in sys.modules)\n")
+    env = dict(os.environ, PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, env=env, text=True, timeout=300)
+    assert out.strip().endswith("True")
+
+
 def test_opts_defaults_and_version():
     lib = bc.load_library()
     o = bc.Opts()

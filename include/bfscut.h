@@ -433,7 +433,10 @@ typedef struct bc_server_opts {
                                a workgroup is free and run beside them.  Batched requests
                                with k <= 256 on graphs no larger than the largest one
                                registered before the first request use it; others run as
-                               whole-request launches on the lanes.  0 (default): lanes only */
+                               whole-request launches on the lanes.  When a lane's own
+                               device work has waited 2 ms behind the running kernel, the
+                               kernel finishes its current batches, ends, and is launched
+                               again after that work.  0 (default): lanes only           */
     int32_t queue_width;    /* W of the queue kernel (64, 128 or 256; default 64): every
                                queued request uses it (the width changes the speed only) */
     int32_t queue_slots;    /* workgroups of the queue kernel (0: one per compute unit);

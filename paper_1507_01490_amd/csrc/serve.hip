@@ -227,6 +227,13 @@ void finish_request(bc_server* S, SrvReq* r, SrvGraph* G, bc_status rs, const st
 bool queue_eligible(bc_server* S, const SrvReq* r, const SrvGraph* G);
 bc_status ensure_queue(bc_server* S);
 
+// The server's device queue, or null before its first queued request (it
+// is made once and destroyed only after the lanes have ended).
+DevQueue* queue_of(bc_server* S) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    return S->q;
+}
+
 void lane_main(bc_server* S, int lane) {
     (void)hipSetDevice(S->device);
     hipStream_t st = S->streams[(size_t)lane];
@@ -250,8 +257,6 @@ void lane_main(bc_server* S, int lane) {
         r->t_start = S->now_ms();
         ++S->running;
         const bool to_queue = r->to_queue;
-        // device work of this lane may wait behind a running queue launch
-        DevQueue* qw = S->q;
         lk.unlock();
 
         bc_status rs = BC_OK;
@@ -259,7 +264,8 @@ void lane_main(bc_server* S, int lane) {
         if (upload) {
             bc_graph* g = nullptr;
             try {
-                DevqWait wait(qw);
+                // device work of this lane may wait behind a running queue launch
+                DevqWait wait(queue_of(S));
                 rs = graph_create(G->n, G->m, G->rp.data(), G->m ? G->col.data() : nullptr, G->flags, st, true, &g);
             } catch (...) {
                 set_error("internal error");
@@ -308,7 +314,7 @@ void lane_main(bc_server* S, int lane) {
                 err = bc_last_error();
             } else {
                 try {
-                    DevqWait wait(qw);
+                    DevqWait wait(queue_of(S));
                     rs = run_topk(G->g, r->k, r->o, r->ids.data(), r->far.data(), r->reach.data(), &r->count, &r->st,
                                   st, true);
                 } catch (...) {

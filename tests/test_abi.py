@@ -121,5 +121,9 @@ def test_footprint_arithmetic():
     gd, ud, _ = bc.footprint(n, m, directed=True)
     assert gd - g == 4 * (n + 1) + 4 * m
     assert ud == 12 * m + 40 * n + (1 << 20)
+    # a learned order adds its features and core numbers (16 B), scores and the
+    # score order (8 B) per node, and the perceptron's parameters
+    _, _, ql = bc.footprint(n, m, k=10, mode="plain", order="learned")
+    assert ql - q_plain == 24 * n + 4 * bc.MLP_PARAMS
     for big in (bc.footprint(2 * n, m), bc.footprint(n, 2 * m), bc.footprint(n, m, k=100)):
         assert big[0] + big[2] > g + q_plain
